@@ -1,0 +1,343 @@
+"""Seeded synthetic workloads for the batched Bartlett grid search.
+
+This module is the input side only. It builds array geometries, search grids
+and snapshot matrices drawn from the paper's signal model, and it computes
+nothing of the estimator itself (no covariance, no spectrum, no peaks). The
+FP64 oracle and the HIP path both consume what it returns.
+
+Signal model (Sec. II-B, eq. (observation-generative); amplitude and noise
+laws in Sec. III-A): one snapshot is a sum of steered source amplitudes plus
+circular complex white Gaussian noise, y_t = sum_k a(u_k) s_k,t + n_t, with
+s_k,t ~ CN(0, 1) and n_t ~ CN(0, sigma^2 I). The spatial response is the
+unit-modulus plane-wave response of eq. (spatial-response-y/z):
+a_m(u) = exp(+j 2 pi p_m . u) with element positions p_m in wavelengths and
+u the unit propagation direction (directional cosines, Supplement S-II).
+Element supports are centred about the origin, as the paper requires of its
+support vectors (Sec. II-B, after eq. (spatial-response-z)).
+
+Randomness: every trial owns a child seed sequence
+``SeedSequence(base, spawn_key=(i,))`` (the i-th child of ``SeedSequence(base)``),
+so trial i is the same whatever the batch size. Draw order inside a trial:
+K (if random), M (if random), T (if random), SNR (if random), source angles
+(rejection sampling for the minimum separation), source amplitudes S
+(real parts then imaginary parts), noise N (real then imaginary).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+# grid kinds, same numbering as the C-ABI enum
+GRID_DIRS = 0
+GRID_ULA_DEG = 1
+GRID_AZEL_DEG = 2
+
+SEED_BASE = 0xBA570000
+
+
+def trial_rng(base: int, i: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence(base, spawn_key=(int(i),))))
+
+
+# --------------------------------------------------------------------------- geometry
+
+def ula_positions(n_elem: int, spacing_wl: float = 0.5) -> np.ndarray:
+    """Centred ULA along the y axis, [M][3] in wavelengths (the paper's horizontal
+    support p_y of eq. (spatial-response-y) with the elevation at 90 degrees)."""
+    p = np.zeros((n_elem, 3))
+    p[:, 1] = (np.arange(n_elem) - (n_elem - 1) / 2.0) * spacing_wl
+    return p
+
+
+def ura_positions(nx: int, ny: int, spacing_wl: float = 0.5) -> np.ndarray:
+    """Centred horizontal URA in the xy-plane, broadside at the zenith, [nx*ny][3].
+    Element m = ix*ny + iy, so the response is a_x (x) a_y in Kronecker order
+    (Supplement S-I template, laid horizontally by the orientation matrix)."""
+    px = (np.arange(nx) - (nx - 1) / 2.0) * spacing_wl
+    py = (np.arange(ny) - (ny - 1) / 2.0) * spacing_wl
+    p = np.zeros((nx * ny, 3))
+    p[:, 0] = np.repeat(px, ny)
+    p[:, 1] = np.tile(py, nx)
+    return p
+
+
+def ula_dirs(theta_deg) -> np.ndarray:
+    t = np.deg2rad(np.asarray(theta_deg, dtype=np.float64))
+    return np.stack([np.cos(t), np.sin(t), np.zeros_like(t)], axis=-1)
+
+
+def azel_dirs(az_deg, el_deg) -> np.ndarray:
+    az = np.deg2rad(np.asarray(az_deg, dtype=np.float64))
+    el = np.deg2rad(np.asarray(el_deg, dtype=np.float64))
+    return np.stack([np.cos(el) * np.cos(az), np.cos(el) * np.sin(az), np.sin(el)], axis=-1)
+
+
+def response(pos_wl: np.ndarray, dirs: np.ndarray) -> np.ndarray:
+    """Source responses for data generation, [M][K] complex128."""
+    ph = pos_wl @ dirs.T
+    ph = ph - np.round(ph)
+    return np.exp(2j * np.pi * ph)
+
+
+# --------------------------------------------------------------------------- grids
+
+def ula_grid(n_grid: int) -> np.ndarray:
+    """Angles in degrees over [-90, 90], both endpoints included."""
+    return np.linspace(-90.0, 90.0, n_grid)
+
+
+def azel_grid(n_az: int = 361, n_el: int = 181, el_max: float = 90.0) -> np.ndarray:
+    """[n_az*n_el][2] (az, el) degrees, az-major (g = i_az*n_el + i_el). Azimuth
+    spans [0, 360] with the last column duplicating the first."""
+    az = np.linspace(0.0, 360.0, n_az)
+    el = np.linspace(0.0, el_max, n_el)
+    g = np.empty((n_az * n_el, 2))
+    g[:, 0] = np.repeat(az, n_el)
+    g[:, 1] = np.tile(el, n_az)
+    return g
+
+
+# --------------------------------------------------------------------------- trials
+
+@dataclasses.dataclass
+class TrialSet:
+    """A uniform batch: every trial has the same M, T and K."""
+    Y: np.ndarray                 # complex128 [B][T][M], snapshot-major
+    pos_wl: np.ndarray            # [M][3]
+    grid_kind: int
+    grid: np.ndarray              # [G] degrees, or [G][2] (az, el) degrees, or [G][3] dirs
+    grid_shape: tuple             # (shape0, shape1); shape1 = 1 for 1-D grids
+    wrap0: int                    # 0 none, 1 periodic, 2 periodic with duplicate last row
+    K: int
+    truth: np.ndarray             # [B][K] degrees (1-D) or [B][K][2] (az, el)
+    snr_db: np.ndarray            # [B]
+    sigma2: np.ndarray            # [B] noise variance used
+    name: str = ""
+
+    @property
+    def n_trials(self):
+        return self.Y.shape[0]
+
+    @property
+    def n_snap(self):
+        return self.Y.shape[1]
+
+    @property
+    def n_elem(self):
+        return self.Y.shape[2]
+
+    @property
+    def n_grid(self):
+        return int(self.grid_shape[0] * self.grid_shape[1])
+
+    def y_c64(self) -> np.ndarray:
+        return np.ascontiguousarray(self.Y.astype(np.complex64))
+
+    def rounded(self) -> "TrialSet":
+        """The same trials with Y rounded to complex64 (what the device sees)."""
+        return dataclasses.replace(self, Y=self.Y.astype(np.complex64).astype(np.complex128))
+
+
+def _draw_angles_1d(rng, K, lo, hi, min_sep):
+    while True:
+        th = rng.uniform(lo, hi, size=K)
+        if K < 2 or np.min(np.diff(np.sort(th))) >= min_sep:
+            return np.sort(th)
+
+
+def _great_circle_deg(u, v):
+    return np.rad2deg(np.arccos(np.clip(np.sum(u * v, axis=-1), -1.0, 1.0)))
+
+
+def _draw_angles_azel(rng, K, el_lo, el_hi, min_sep):
+    while True:
+        az = rng.uniform(0.0, 360.0, size=K)
+        el = rng.uniform(el_lo, el_hi, size=K)
+        d = azel_dirs(az, el)
+        ok = True
+        for i in range(K):
+            for j in range(i + 1, K):
+                if _great_circle_deg(d[i], d[j]) < min_sep:
+                    ok = False
+        if ok:
+            return np.stack([az, el], axis=-1)
+
+
+def noise_variance(snr_db: float, K: int, snr_def: str) -> float:
+    """Per-source reading: sigma^2 = 10^(-SNR/10) for unit-power sources. The
+    sum-channel reading follows the paper's SNR definition on the summed
+    channel power per element (Sec. V-A, system parameters): sigma^2 = K 10^(-SNR/10)."""
+    base = 10.0 ** (-snr_db / 10.0)
+    if snr_def == "per_source":
+        return base
+    if snr_def == "sum_channel":
+        return K * base
+    raise ValueError(snr_def)
+
+
+def _snapshots(rng, A, T, sigma2):
+    M, K = A.shape
+    s = (rng.standard_normal((K, T)) + 1j * rng.standard_normal((K, T))) * math.sqrt(0.5)
+    n = (rng.standard_normal((M, T)) + 1j * rng.standard_normal((M, T))) * math.sqrt(0.5 * sigma2)
+    return (A @ s + n).T  # [T][M]
+
+
+def make_ula_trials(n_trials: int, n_elem: int, n_src: int, n_snap: int, snr_db, n_grid: int,
+                    seed_base: int, first_trial: int = 0, ang_lo=-60.0, ang_hi=60.0,
+                    min_sep=5.0, snr_def="per_source", name="") -> TrialSet:
+    """Uniform ULA batch. ``snr_db`` is a scalar or a sequence cycled over trials
+    (trial i takes snr_db[i % len])."""
+    snrs = np.atleast_1d(np.asarray(snr_db, dtype=np.float64))
+    pos = ula_positions(n_elem)
+    Y = np.empty((n_trials, n_snap, n_elem), dtype=np.complex128)
+    truth = np.empty((n_trials, n_src))
+    snr = np.empty(n_trials)
+    sig = np.empty(n_trials)
+    for b in range(n_trials):
+        i = first_trial + b
+        rng = trial_rng(seed_base, i)
+        snr[b] = snrs[i % len(snrs)]
+        th = _draw_angles_1d(rng, n_src, ang_lo, ang_hi, min_sep)
+        sig[b] = noise_variance(snr[b], n_src, snr_def)
+        Y[b] = _snapshots(rng, response(pos, ula_dirs(th)), n_snap, sig[b])
+        truth[b] = th
+    return TrialSet(Y=Y, pos_wl=pos, grid_kind=GRID_ULA_DEG, grid=ula_grid(n_grid),
+                    grid_shape=(n_grid, 1), wrap0=0, K=n_src, truth=truth, snr_db=snr,
+                    sigma2=sig, name=name)
+
+
+def make_ura_trials(n_trials: int, nx: int, ny: int, n_src: int, n_snap: int, snr_db: float,
+                    n_az: int, n_el: int, seed_base: int, first_trial: int = 0,
+                    el_lo=0.0, el_hi=80.0, min_sep=5.0, snr_def="per_source",
+                    name="") -> TrialSet:
+    pos = ura_positions(nx, ny)
+    M = nx * ny
+    Y = np.empty((n_trials, n_snap, M), dtype=np.complex128)
+    truth = np.empty((n_trials, n_src, 2))
+    sig = noise_variance(snr_db, n_src, snr_def)
+    for b in range(n_trials):
+        rng = trial_rng(seed_base, first_trial + b)
+        ae = _draw_angles_azel(rng, n_src, el_lo, el_hi, min_sep)
+        Y[b] = _snapshots(rng, response(pos, azel_dirs(ae[:, 0], ae[:, 1])), n_snap, sig)
+        truth[b] = ae
+    return TrialSet(Y=Y, pos_wl=pos, grid_kind=GRID_AZEL_DEG, grid=azel_grid(n_az, n_el),
+                    grid_shape=(n_az, n_el), wrap0=2, K=n_src, truth=truth,
+                    snr_db=np.full(n_trials, float(snr_db)), sigma2=np.full(n_trials, sig),
+                    name=name)
+
+
+# --------------------------------------------------------------------------- the five workloads
+
+C2_SNRS = (-10.0, -5.0, 0.0, 5.0, 10.0, 15.0, 20.0)
+
+
+def config1(n_trials: int = 100, first_trial: int = 0) -> TrialSet:
+    """16-element half-wavelength ULA, 2 sources in [-60, 60] deg (sep >= 5 deg),
+    64 snapshots, SNR 10 dB, 1801-point grid over [-90, 90] deg."""
+    return make_ula_trials(n_trials, 16, 2, 64, 10.0, 1801, SEED_BASE + 1, first_trial,
+                           name="ula16_k2_t64_g1801")
+
+
+def config2(n_trials: int = 10000, first_trial: int = 0, snr_db=C2_SNRS) -> TrialSet:
+    """64-element ULA, 4 sources, 256 snapshots, 7201-point grid; the SNR sweep
+    -10..20 dB in 5 dB steps is cycled over the trials of one batch."""
+    return make_ula_trials(n_trials, 64, 4, 256, snr_db, 7201, SEED_BASE + 2, first_trial,
+                           name="ula64_k4_t256_g7201")
+
+
+def config3(n_trials: int = 2000, first_trial: int = 0) -> TrialSet:
+    """16x16 horizontal URA, 3 sources (az U[0,360), el U[0,80]), 512 snapshots,
+    SNR 0 dB, 361x181 az/el grid."""
+    return make_ura_trials(n_trials, 16, 16, 3, 512, 0.0, 361, 181, SEED_BASE + 3, first_trial,
+                           name="ura16x16_k3_t512_g361x181")
+
+
+# ------------------------------------------------------------------ ragged (uneven) batches
+
+C4_SIZES = (8, 16, 32, 64, 128)
+
+
+@dataclasses.dataclass
+class RaggedSet:
+    """Trials of different M, T and K packed into one complex pool.
+
+    Trial i occupies pool[y_offset[i] : y_offset[i] + T_i*M_i] as a [T_i][M_i]
+    snapshot-major block. Element positions of trial i are the first M_i rows of
+    the centred ULA of that size; the grid is shared."""
+    pool: np.ndarray              # complex128 [total]
+    y_offset: np.ndarray          # int64 [B] in complex elements
+    n_elem: np.ndarray            # int32 [B]
+    n_snap: np.ndarray            # int32 [B]
+    k: np.ndarray                 # int32 [B]
+    truth: List[np.ndarray]       # per trial [K_i] degrees
+    snr_db: np.ndarray
+    grid: np.ndarray
+    grid_kind: int = GRID_ULA_DEG
+    name: str = ""
+
+    @property
+    def n_trials(self):
+        return len(self.y_offset)
+
+    def trial_y(self, i) -> np.ndarray:
+        o, M, T = int(self.y_offset[i]), int(self.n_elem[i]), int(self.n_snap[i])
+        return self.pool[o:o + M * T].reshape(T, M)
+
+    def pool_c64(self) -> np.ndarray:
+        return np.ascontiguousarray(self.pool.astype(np.complex64))
+
+
+def config4(n_trials: int = 50000, first_trial: int = 0, n_grid: int = 3601,
+            t_max: int = 2048) -> RaggedSet:
+    """Uneven batch: M uniform over {8,16,32,64,128}, K uniform over 1..6,
+    T = clip(rint(exp(U[ln 16, ln t_max])), 16, t_max), SNR ~ U[-10, 20] dB."""
+    seed = SEED_BASE + 4
+    Ms = np.empty(n_trials, np.int32)
+    Ts = np.empty(n_trials, np.int32)
+    Ks = np.empty(n_trials, np.int32)
+    snr = np.empty(n_trials)
+    blocks, truth = [], []
+    for b in range(n_trials):
+        rng = trial_rng(seed, first_trial + b)
+        K = int(rng.integers(1, 7))
+        M = int(C4_SIZES[int(rng.integers(0, len(C4_SIZES)))])
+        T = int(np.clip(np.rint(np.exp(rng.uniform(math.log(16.0), math.log(t_max)))), 16, t_max))
+        s = float(rng.uniform(-10.0, 20.0))
+        th = _draw_angles_1d(rng, K, -60.0, 60.0, 5.0)
+        y = _snapshots(rng, response(ula_positions(M), ula_dirs(th)), T, noise_variance(s, K, "per_source"))
+        Ms[b], Ts[b], Ks[b], snr[b] = M, T, K, s
+        blocks.append(y.reshape(-1))
+        truth.append(th)
+    sizes = np.array([x.size for x in blocks], dtype=np.int64)
+    off = np.zeros(n_trials, np.int64)
+    off[1:] = np.cumsum(sizes)[:-1]
+    pool = np.concatenate(blocks) if blocks else np.zeros(0, np.complex128)
+    return RaggedSet(pool=pool, y_offset=off, n_elem=Ms, n_snap=Ts, k=Ks, truth=truth,
+                     snr_db=snr, grid=ula_grid(n_grid), name="ragged_m8-128_t16-2048_g3601")
+
+
+def config5(n_trials: int, first_trial: int = 0, seed_offset: int = 0, K: int = 4,
+            snr_db: Optional[Sequence[float]] = None) -> TrialSet:
+    """Learned-proposal workload: 64-element ULA, K sources, 256 snapshots, SNR
+    ~ U[-10, 20] dB per trial (or cycled over ``snr_db``), 7201-point grid.
+    ``seed_offset`` separates the training, validation and test streams."""
+    seed = SEED_BASE + 5 + (seed_offset << 8)
+    pos = ula_positions(64)
+    Y = np.empty((n_trials, 256, 64), dtype=np.complex128)
+    truth = np.empty((n_trials, K))
+    snr = np.empty(n_trials)
+    sig = np.empty(n_trials)
+    for b in range(n_trials):
+        i = first_trial + b
+        rng = trial_rng(seed, i)
+        snr[b] = rng.uniform(-10.0, 20.0) if snr_db is None else snr_db[i % len(snr_db)]
+        th = _draw_angles_1d(rng, K, -60.0, 60.0, 5.0)
+        sig[b] = noise_variance(snr[b], K, "per_source")
+        Y[b] = _snapshots(rng, response(pos, ula_dirs(th)), 256, sig[b])
+        truth[b] = th
+    return TrialSet(Y=Y, pos_wl=pos, grid_kind=GRID_ULA_DEG, grid=ula_grid(7201),
+                    grid_shape=(7201, 1), wrap0=0, K=K, truth=truth, snr_db=snr, sigma2=sig,
+                    name="learned_ula64_k4_t256_g7201")
