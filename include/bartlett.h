@@ -1,0 +1,180 @@
+/*
+ * bartlett.h - C-ABI of the MI355X batched Bartlett grid search.
+ *
+ * The operation (paper: "Soft-Coherent Direct Multipath SLAM", Sec. IV-D.2,
+ * "An Efficient Birth Proposal PDF"): for every candidate direction u_g of a
+ * grid, the Bartlett cost of the observation against the candidate's steering
+ * vector, then the candidate(s) of maximum cost and, optionally, the
+ * cost-weighted proposal moments. Read for one array and T snapshots with
+ * independent source phases:
+ *
+ *     R     = (1/T) sum_t y_t y_t^H                         (sample covariance)
+ *     P[g]  = Re(a_g^H R a_g) / M^2 = (1/T) sum_t |a_g^H y_t|^2 / M^2
+ *     a_g[m] = exp(+j 2 pi p_m . u_g)                        (eq. spatial-response-y/z,
+ *                                                             directional cosines, Suppl. S-II)
+ *
+ * Element positions p_m are in wavelengths; observations follow the signal
+ * model of eq. (observation-generative) (Sec. II-B).
+ *
+ * Conventions for every call:
+ *  - Pointers marked "dev" are HIP device pointers on the plan's device;
+ *    "host" pointers are ordinary host memory, read before the call returns.
+ *  - The caller allocates and frees every input, output and workspace buffer.
+ *    A plan owns only its own tables. No call except ba_plan_create (and the
+ *    other *_create calls) allocates device memory.
+ *  - Complex values are interleaved (re, im) float32 pairs ("c64").
+ *  - Calls that take a stream enqueue asynchronously on it (NULL = the null
+ *    stream). Argument errors are detected and returned before anything is
+ *    enqueued. A launch failure returns BA_ERR_DEVICE; faults inside kernels
+ *    surface at the caller's next synchronisation.
+ *  - A plan may be used by one host thread at a time. Calls that share a
+ *    workspace must not overlap.
+ *  - No C++ exception crosses this interface.
+ */
+#ifndef BARTLETT_H
+#define BARTLETT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ba_status;
+#define BA_OK              0
+#define BA_ERR_ARG        -1   /* invalid argument (sizes, null pointers, enums) */
+#define BA_ERR_DEVICE     -2   /* a HIP call or kernel launch failed */
+#define BA_ERR_NOMEM      -3   /* device allocation failed (plan creation only) */
+#define BA_ERR_UNSUPPORTED -4  /* valid request outside what the library implements */
+#define BA_ERR_STATE      -5   /* plan not in a state that allows the call */
+
+typedef struct ba_plan_s* ba_plan;
+
+/* Arithmetic of the grid projection (the dominant contraction). Covariance
+ * accumulation is always FP32; peak refinement and moments are FP64. */
+#define BA_PREC_F32     1   /* FP32 operands, FP32 accumulate (MFMA f32) */
+#define BA_PREC_BF16X3  2   /* hi/lo BF16 split, three BF16 MFMA passes, FP32 accumulate */
+#define BA_PREC_BF16    3   /* single BF16 pass (precision ablation only) */
+
+/* Grid kinds. */
+#define BA_GRID_DIRS      0  /* grid = host double [G][3] unit direction vectors */
+#define BA_GRID_ULA_DEG   1  /* grid = host double [G] angles t from broadside (deg), u = (cos t, sin t, 0) */
+#define BA_GRID_AZEL_DEG  2  /* grid = host double [G][2] (az, el) deg, u = (cos el cos az, cos el sin az, sin el) */
+
+/* Status as text (static storage). */
+const char* ba_status_string(ba_status s);
+
+/* Text of the last error raised on this host thread (static per-thread storage). */
+const char* ba_last_error(void);
+
+/* Library version as text. */
+const char* ba_version(void);
+
+/*
+ * Create a plan: geometry + grid + precision. Builds the steering tables on the
+ * host in FP64 (phase p_m . u_g reduced to [-1/2, 1/2) before the complex
+ * exponential) and uploads them to the current HIP device, which the plan is
+ * then bound to.
+ *   n_elem       M, 1 <= M <= 256.
+ *   elem_pos_wl  host double [M][3], element positions in wavelengths.
+ *   grid_kind    BA_GRID_*; grid host double as described above.
+ *   n_grid       G >= 1, G == grid_shape0 * max(grid_shape1, 1).
+ *   grid_shape0, grid_shape1  adjacency for peak search: flat g = i0*shape1 + i1;
+ *                shape1 <= 1 means a 1-D grid.
+ *   wrap0        0: no wrap; 1: dim0 periodic with period shape0; 2: dim0
+ *                periodic with period shape0-1, its last row duplicating the
+ *                first (never a peak, never a neighbour). Period must be >= 3.
+ *   precision    BA_PREC_*.
+ * Errors: BA_ERR_ARG, BA_ERR_NOMEM, BA_ERR_DEVICE. On error *out is NULL.
+ */
+ba_status ba_plan_create(ba_plan* out, int32_t n_elem, const double* elem_pos_wl,
+                         int32_t grid_kind, int64_t n_grid, const double* grid,
+                         int32_t grid_shape0, int32_t grid_shape1, int32_t wrap0,
+                         int32_t precision);
+
+/* Destroy a plan (NULL is accepted). Synchronises the plan's device first. */
+ba_status ba_plan_destroy(ba_plan p);
+
+/* Plan facts: M, G, number of refined coordinates per peak (1 for 1-D grids, 2 for 2-D). */
+ba_status ba_plan_info(ba_plan p, int32_t* n_elem, int64_t* n_grid, int32_t* ndim);
+
+/*
+ * Workspace bytes that ba_run needs for n_trials trials; with_spectrum_out = 0
+ * means ba_run is called with P == NULL, so the spectrum is staged in the
+ * workspace.
+ */
+ba_status ba_workspace_size(ba_plan p, int32_t n_trials, int32_t n_snap,
+                            int32_t with_spectrum_out, size_t* bytes);
+
+/*
+ * Sample covariance (the R of the Bartlett cost, 1/T normalisation, no mean
+ * removal) of B trials.
+ *   Y  dev c64 [B][T][M], snapshot-major (each snapshot one contiguous M-vector).
+ *   R  dev c64 [B][M][M], row-major R[m][n] = (1/T) sum_t y_t[m] conj(y_t[n]);
+ *      both triangles written, exactly Hermitian.
+ * Requires B >= 0 (0 is a no-op), T >= 1.
+ */
+ba_status ba_covariance(ba_plan p, int32_t n_trials, int32_t n_snap, const void* Y, void* R,
+                        void* stream);
+
+/*
+ * Bartlett spectrum from covariances: P[b][g] = Re(a_g^H R_b a_g) / M^2.
+ *   R  dev c64 [B][M][M] as written by ba_covariance (any Hermitian matrix).
+ *   P  dev float [B][G].
+ */
+ba_status ba_spectrum(ba_plan p, int32_t n_trials, const void* R, float* P, void* stream);
+
+/*
+ * Bartlett spectrum straight from snapshots (snapshot route, cheaper when T < M):
+ * P[b][g] = (1/T) sum_t |a_g^H y_t|^2 / M^2.
+ */
+ba_status ba_spectrum_snapshots(ba_plan p, int32_t n_trials, int32_t n_snap, const void* Y,
+                                float* P, void* stream);
+
+/*
+ * Peak pick and refinement (generalising the paper's argmax candidate to the K
+ * largest local maxima). A point is a local maximum when it is strictly
+ * greater than every neighbour before it in raster order and greater than or
+ * equal to every neighbour after it (8-neighbourhood on 2-D grids, wrap as in
+ * the plan); missing neighbours are not compared and any comparison with NaN
+ * is false. Peaks are ordered by value, ties to the lower index.
+ *   P        dev float [B][G].
+ *   k        1 <= k <= 16.
+ *   idx      dev int32 [B][k] flat grid index, -1 where fewer than k maxima exist.
+ *   val      dev float [B][k] P at the peak, NaN where idx = -1.
+ *   refined  dev double [B][k][ndim] (may be NULL): fractional grid index per
+ *            axis, i + d with the parabolic vertex d = (P- - P+) / (2 (P- - 2 P0 + P+))
+ *            clamped to [-1/2, 1/2], computed in FP64 from the FP32 values; d = 0
+ *            on a non-wrapping edge or a zero denominator; NaN where idx = -1.
+ */
+ba_status ba_peaks(ba_plan p, int32_t n_trials, const float* P, int32_t k, int32_t* idx,
+                   float* val, double* refined, void* stream);
+
+/*
+ * Proposal moments of Sec. IV-D.2: weights w_g = P_g / sum P over the distinct
+ * grid points, mean mu = coordinates of the global maximum (lowest index among
+ * equal maxima), covariance C = sum_g w_g (x_g - mu)(x_g - mu)^T. Coordinates x
+ * are degrees for angle grids (azimuth differences wrapped into [-180, 180))
+ * and the unit vector for BA_GRID_DIRS; d = 1, 2 or 3 accordingly.
+ *   mu_cov  dev double [B][d + d*d]: mu then C row-major.
+ */
+ba_status ba_proposal_moments(ba_plan p, int32_t n_trials, const float* P, double* mu_cov,
+                              void* stream);
+
+/*
+ * The whole path for B trials: covariance -> spectrum -> peaks (+refinement).
+ *   Y          dev c64 [B][T][M].
+ *   P          dev float [B][G] or NULL (then staged in the workspace).
+ *   idx/val/refined as ba_peaks (refined may be NULL).
+ *   workspace  dev, at least ba_workspace_size(p, B, T, P != NULL) bytes,
+ *              256-byte aligned.
+ */
+ba_status ba_run(ba_plan p, int32_t n_trials, int32_t n_snap, const void* Y, int32_t k,
+                 float* P, int32_t* idx, float* val, double* refined,
+                 void* workspace, size_t workspace_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BARTLETT_H */

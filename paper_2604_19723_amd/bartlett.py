@@ -1,0 +1,289 @@
+"""Python binding of libbartlett.so: the C-ABI calls under the same names.
+
+Argument marshalling only. Device buffers are torch tensors on the HIP device
+(their data pointers go through ctypes); host arrays are numpy. Every step of
+the computation runs in the library's HIP kernels. Sizes, dtypes and
+contiguity of the buffers are checked here against what the call will touch,
+so a wrong buffer raises instead of reaching a kernel. If the library is not
+built, every call raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbartlett.so")
+
+BA_OK = 0
+BA_ERR_ARG = -1
+BA_ERR_DEVICE = -2
+BA_ERR_NOMEM = -3
+BA_ERR_UNSUPPORTED = -4
+BA_ERR_STATE = -5
+
+BA_PREC_F32 = 1
+BA_PREC_BF16X3 = 2
+BA_PREC_BF16 = 3
+
+BA_GRID_DIRS = 0
+BA_GRID_ULA_DEG = 1
+BA_GRID_AZEL_DEG = 2
+
+
+class BartlettError(RuntimeError):
+    def __init__(self, fn, status, msg):
+        super().__init__("%s failed: status %d (%s): %s" % (fn, status, _status_text(status), msg))
+        self.status = status
+
+
+_lib = None
+
+_vp = C.c_void_p
+_i32 = C.c_int32
+_i64 = C.c_int64
+_sz = C.c_size_t
+_dp = C.POINTER(C.c_double)
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "ba_status_string": (C.c_char_p, [_i32]),
+    "ba_last_error": (C.c_char_p, []),
+    "ba_version": (C.c_char_p, []),
+    "ba_plan_create": (_i32, [C.POINTER(_vp), _i32, _dp, _i32, _i64, _dp, _i32, _i32, _i32, _i32]),
+    "ba_plan_destroy": (_i32, [_vp]),
+    "ba_plan_info": (_i32, [_vp, C.POINTER(_i32), C.POINTER(_i64), C.POINTER(_i32)]),
+    "ba_workspace_size": (_i32, [_vp, _i32, _i32, _i32, C.POINTER(_sz)]),
+    "ba_covariance": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp]),
+    "ba_spectrum": (_i32, [_vp, _i32, _vp, _vp, _vp]),
+    "ba_spectrum_snapshots": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp]),
+    "ba_peaks": (_i32, [_vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp]),
+    "ba_proposal_moments": (_i32, [_vp, _i32, _vp, _vp, _vp]),
+    "ba_run": (_i32, [_vp, _i32, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+}
+
+
+def lib():
+    """Load the library (once). Raises if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libbartlett.so is not built (%s); run "
+                               "`python -m paper_2604_19723_amd.build`" % LIB_PATH)
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _status_text(s):
+    try:
+        return lib().ba_status_string(s).decode()
+    except Exception:
+        return "?"
+
+
+def _check(fn, status):
+    if status != BA_OK:
+        raise BartlettError(fn, status, lib().ba_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+_TORCH_DT = {"c64": ("complex64", 8), "f32": ("float32", 4), "f64": ("float64", 8),
+             "i32": ("int32", 4), "u8": ("uint8", 1), "bf16": ("bfloat16", 2)}
+
+
+def _dev(t, kind, numel, name, optional=False):
+    """Device pointer of a torch tensor after checking dtype, device, contiguity
+    and that it holds at least ``numel`` elements."""
+    if t is None:
+        if optional:
+            return None
+        raise ValueError("%s is required" % name)
+    dt, _ = _TORCH_DT[kind]
+    if str(t.dtype).replace("torch.", "") != dt:
+        raise TypeError("%s must be %s, got %s" % (name, dt, t.dtype))
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.numel() < numel:
+        raise ValueError("%s holds %d elements, the call needs %d" % (name, t.numel(), numel))
+    return C.c_void_p(t.data_ptr())
+
+
+def _host_f64(a, shape_numel, name):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if a.size != shape_numel:
+        raise ValueError("%s must have %d values, got %d" % (name, shape_numel, a.size))
+    return a
+
+
+# --------------------------------------------------------------------------- plan
+
+class Plan:
+    """Owns a ba_plan handle; holds the facts the binding needs to size buffers."""
+
+    def __init__(self, handle, M, G, ndim, shape, wrap0, grid_kind, precision):
+        self.handle = handle
+        self.M, self.G, self.ndim = M, G, ndim
+        self.shape, self.wrap0, self.grid_kind, self.precision = shape, wrap0, grid_kind, precision
+
+    @property
+    def coord_dim(self):
+        return {BA_GRID_ULA_DEG: 1, BA_GRID_AZEL_DEG: 2, BA_GRID_DIRS: 3}[self.grid_kind]
+
+    def close(self):
+        if self.handle:
+            ba_plan_destroy(self)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ba_version():
+    return lib().ba_version().decode()
+
+
+def ba_plan_create(n_elem, elem_pos_wl, grid_kind, n_grid, grid, grid_shape0, grid_shape1, wrap0,
+                   precision=BA_PREC_F32) -> Plan:
+    pos = _host_f64(elem_pos_wl, 3 * n_elem, "elem_pos_wl")
+    per = {BA_GRID_ULA_DEG: 1, BA_GRID_AZEL_DEG: 2, BA_GRID_DIRS: 3}.get(grid_kind, 1)
+    g = _host_f64(grid, per * n_grid, "grid")
+    h = C.c_void_p()
+    _check("ba_plan_create", lib().ba_plan_create(
+        C.byref(h), n_elem, pos.ctypes.data_as(_dp), grid_kind, n_grid, g.ctypes.data_as(_dp),
+        grid_shape0, grid_shape1, wrap0, precision))
+    M, G, nd = _i32(), _i64(), _i32()
+    _check("ba_plan_info", lib().ba_plan_info(h, C.byref(M), C.byref(G), C.byref(nd)))
+    return Plan(h, M.value, G.value, nd.value, (grid_shape0, max(1, grid_shape1)), wrap0,
+                grid_kind, precision)
+
+
+def ba_plan_destroy(plan: Plan):
+    _check("ba_plan_destroy", lib().ba_plan_destroy(plan.handle))
+
+
+def ba_plan_info(plan: Plan):
+    M, G, nd = _i32(), _i64(), _i32()
+    _check("ba_plan_info", lib().ba_plan_info(plan.handle, C.byref(M), C.byref(G), C.byref(nd)))
+    return M.value, G.value, nd.value
+
+
+def ba_workspace_size(plan: Plan, n_trials, n_snap, with_spectrum_out=True) -> int:
+    b = _sz()
+    _check("ba_workspace_size", lib().ba_workspace_size(plan.handle, n_trials, n_snap,
+                                                        int(bool(with_spectrum_out)), C.byref(b)))
+    return b.value
+
+
+# --------------------------------------------------------------------------- stages
+
+def ba_covariance(plan: Plan, n_trials, n_snap, Y, R, stream=None):
+    M = plan.M
+    _check("ba_covariance", lib().ba_covariance(
+        plan.handle, n_trials, n_snap, _dev(Y, "c64", n_trials * n_snap * M, "Y"),
+        _dev(R, "c64", n_trials * M * M, "R"), _stream(stream)))
+
+
+def ba_spectrum(plan: Plan, n_trials, R, P, stream=None):
+    M, G = plan.M, plan.G
+    _check("ba_spectrum", lib().ba_spectrum(
+        plan.handle, n_trials, _dev(R, "c64", n_trials * M * M, "R"),
+        _dev(P, "f32", n_trials * G, "P"), _stream(stream)))
+
+
+def ba_spectrum_snapshots(plan: Plan, n_trials, n_snap, Y, P, stream=None):
+    M, G = plan.M, plan.G
+    _check("ba_spectrum_snapshots", lib().ba_spectrum_snapshots(
+        plan.handle, n_trials, n_snap, _dev(Y, "c64", n_trials * n_snap * M, "Y"),
+        _dev(P, "f32", n_trials * G, "P"), _stream(stream)))
+
+
+def ba_peaks(plan: Plan, n_trials, P, k, idx, val, refined=None, stream=None):
+    G, nd = plan.G, plan.ndim
+    _check("ba_peaks", lib().ba_peaks(
+        plan.handle, n_trials, _dev(P, "f32", n_trials * G, "P"), k,
+        _dev(idx, "i32", n_trials * k, "idx"), _dev(val, "f32", n_trials * k, "val"),
+        _dev(refined, "f64", n_trials * k * nd, "refined", optional=True), _stream(stream)))
+
+
+def ba_proposal_moments(plan: Plan, n_trials, P, mu_cov, stream=None):
+    d = plan.coord_dim
+    _check("ba_proposal_moments", lib().ba_proposal_moments(
+        plan.handle, n_trials, _dev(P, "f32", n_trials * plan.G, "P"),
+        _dev(mu_cov, "f64", n_trials * (d + d * d), "mu_cov"), _stream(stream)))
+
+
+def ba_run(plan: Plan, n_trials, n_snap, Y, k, P, idx, val, refined, workspace, stream=None):
+    M, G, nd = plan.M, plan.G, plan.ndim
+    need = ba_workspace_size(plan, n_trials, n_snap, P is not None)
+    if workspace is None or workspace.numel() * workspace.element_size() < need:
+        raise ValueError("workspace needs %d bytes" % need)
+    if not workspace.is_cuda or not workspace.is_contiguous():
+        raise ValueError("workspace must be a contiguous device tensor")
+    _check("ba_run", lib().ba_run(
+        plan.handle, n_trials, n_snap, _dev(Y, "c64", n_trials * n_snap * M, "Y"), k,
+        _dev(P, "f32", n_trials * G, "P", optional=True), _dev(idx, "i32", n_trials * k, "idx"),
+        _dev(val, "f32", n_trials * k, "val"),
+        _dev(refined, "f64", n_trials * k * nd, "refined", optional=True),
+        C.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size(),
+        _stream(stream)))
+
+
+# --------------------------------------------------------------------------- convenience
+
+def plan_for(trialset, precision=BA_PREC_F32) -> Plan:
+    """Plan for a workload.TrialSet (geometry + grid + adjacency)."""
+    ts = trialset
+    return ba_plan_create(ts.pos_wl.shape[0], ts.pos_wl, ts.grid_kind, ts.n_grid, ts.grid,
+                          ts.grid_shape[0], ts.grid_shape[1], ts.wrap0, precision)
+
+
+def workspace_for(plan: Plan, n_trials, n_snap, with_spectrum_out=True, device="cuda"):
+    import torch
+    n = ba_workspace_size(plan, n_trials, n_snap, with_spectrum_out)
+    return torch.empty(max(n, 256), dtype=torch.uint8, device=device)
+
+
+def run_grid_search(plan: Plan, Y, k, with_spectrum=True, stream=None):
+    """Allocate outputs and run the whole path on a device tensor Y [B][T][M] c64.
+    Returns a dict of device tensors."""
+    import torch
+    B, T, M = Y.shape
+    dev = Y.device
+    P = torch.empty((B, plan.G), dtype=torch.float32, device=dev) if with_spectrum else None
+    idx = torch.empty((B, k), dtype=torch.int32, device=dev)
+    val = torch.empty((B, k), dtype=torch.float32, device=dev)
+    ref = torch.empty((B, k, plan.ndim), dtype=torch.float64, device=dev)
+    ws = workspace_for(plan, B, T, with_spectrum, dev)
+    ba_run(plan, B, T, Y, k, P, idx, val, ref, ws, stream)
+    return dict(P=P, idx=idx, val=val, refined=ref)

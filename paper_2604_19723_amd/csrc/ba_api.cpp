@@ -1,0 +1,286 @@
+// C-ABI entry points: argument validation, plan lifetime, host-side steering
+// tables, and dispatch to the kernel launchers.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ba_internal.h"
+
+namespace ba {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+static ba_status arg_error(const char* fn, const std::string& what) {
+  set_error(std::string(fn) + ": " + what);
+  return BA_ERR_ARG;
+}
+
+static ba_status dev_error(const char* fn, hipError_t e) {
+  set_error(std::string(fn) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")");
+  return e == hipErrorOutOfMemory ? BA_ERR_NOMEM : BA_ERR_DEVICE;
+}
+
+// Unit propagation direction of grid point g (directional cosines, Suppl. S-II).
+static void grid_direction(int kind, const double* grid, int64_t g, double u[3]) {
+  constexpr double d2r = M_PI / 180.0;
+  if (kind == BA_GRID_ULA_DEG) {
+    const double t = grid[g] * d2r;
+    u[0] = std::cos(t);
+    u[1] = std::sin(t);
+    u[2] = 0.0;
+  } else if (kind == BA_GRID_AZEL_DEG) {
+    const double az = grid[2 * g] * d2r, el = grid[2 * g + 1] * d2r;
+    u[0] = std::cos(el) * std::cos(az);
+    u[1] = std::cos(el) * std::sin(az);
+    u[2] = std::sin(el);
+  } else {
+    u[0] = grid[3 * g];
+    u[1] = grid[3 * g + 1];
+    u[2] = grid[3 * g + 2];
+  }
+}
+
+hipError_t launch_spectrum(const Plan& p, int B, const float2* R, float* P, hipStream_t s) {
+  return launch_spectrum_valu(p, B, R, P, s);
+}
+
+static void free_plan(Plan* p) {
+  if (!p) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(p->device);
+  if (p->d_A) (void)hipFree(p->d_A);
+  if (p->d_X) (void)hipFree(p->d_X);
+  if (p->d_coords) (void)hipFree(p->d_coords);
+  (void)hipSetDevice(cur);
+  delete p;
+}
+
+}  // namespace ba
+
+using namespace ba;
+
+struct ba_plan_s : public ba::Plan {};
+
+static inline Plan* P_(ba_plan p) { return static_cast<Plan*>(p); }
+
+extern "C" {
+
+const char* ba_status_string(ba_status s) {
+  switch (s) {
+    case BA_OK: return "ok";
+    case BA_ERR_ARG: return "invalid argument";
+    case BA_ERR_DEVICE: return "device error";
+    case BA_ERR_NOMEM: return "out of device memory";
+    case BA_ERR_UNSUPPORTED: return "unsupported";
+    case BA_ERR_STATE: return "invalid state";
+    default: return "unknown status";
+  }
+}
+
+const char* ba_last_error(void) { return g_last_error.c_str(); }
+
+const char* ba_version(void) { return "bartlett-mi355x 0.1 (gfx950)"; }
+
+ba_status ba_plan_create(ba_plan* out, int32_t n_elem, const double* elem_pos_wl,
+                         int32_t grid_kind, int64_t n_grid, const double* grid,
+                         int32_t grid_shape0, int32_t grid_shape1, int32_t wrap0,
+                         int32_t precision) {
+  static const char* fn = "ba_plan_create";
+  if (!out) return arg_error(fn, "out is NULL");
+  *out = nullptr;
+  if (n_elem < 1 || n_elem > kMaxElem) return arg_error(fn, "n_elem must be in [1, 256]");
+  if (!elem_pos_wl) return arg_error(fn, "elem_pos_wl is NULL");
+  if (grid_kind != BA_GRID_DIRS && grid_kind != BA_GRID_ULA_DEG && grid_kind != BA_GRID_AZEL_DEG)
+    return arg_error(fn, "unknown grid_kind");
+  if (n_grid < 1 || n_grid > (int64_t(1) << 30)) return arg_error(fn, "n_grid out of range");
+  if (!grid) return arg_error(fn, "grid is NULL");
+  const int s1 = grid_shape1 <= 1 ? 1 : grid_shape1;
+  if (grid_shape0 < 1 || int64_t(grid_shape0) * s1 != n_grid)
+    return arg_error(fn, "grid_shape0 * grid_shape1 must equal n_grid");
+  if (wrap0 < 0 || wrap0 > 2) return arg_error(fn, "wrap0 must be 0, 1 or 2");
+  if (wrap0 && (wrap0 == 2 ? grid_shape0 - 1 : grid_shape0) < 3)
+    return arg_error(fn, "a wrapping dimension needs a period of at least 3");
+  if (precision != BA_PREC_F32 && precision != BA_PREC_BF16X3 && precision != BA_PREC_BF16)
+    return arg_error(fn, "unknown precision");
+  for (int64_t i = 0; i < int64_t(n_elem) * 3; ++i)
+    if (!std::isfinite(elem_pos_wl[i])) return arg_error(fn, "non-finite element position");
+  const int64_t gvals = n_grid * (grid_kind == BA_GRID_ULA_DEG ? 1 : grid_kind == BA_GRID_AZEL_DEG ? 2 : 3);
+  for (int64_t i = 0; i < gvals; ++i)
+    if (!std::isfinite(grid[i])) return arg_error(fn, "non-finite grid value");
+
+  ba_plan_s* p = new (std::nothrow) ba_plan_s();
+  if (!p) return arg_error(fn, "host allocation failed");
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) { delete p; return dev_error(fn, e); }
+  p->M = n_elem;
+  p->G = n_grid;
+  p->kind = grid_kind;
+  p->shape0 = grid_shape0;
+  p->shape1 = s1;
+  p->wrap0 = wrap0;
+  p->rows = wrap0 == 2 ? grid_shape0 - 1 : grid_shape0;
+  p->ndim = s1 == 1 ? 1 : 2;
+  p->coord_dim = grid_kind == BA_GRID_ULA_DEG ? 1 : grid_kind == BA_GRID_AZEL_DEG ? 2 : 3;
+  p->precision = precision;
+  p->pos.assign(elem_pos_wl, elem_pos_wl + 3 * n_elem);
+  p->coords.assign(grid, grid + gvals);
+
+  // Steering table in FP64: phase in cycles reduced to [-1/2, 1/2], then the
+  // complex exponential rounded once to FP32.
+  const int M = n_elem;
+  std::vector<float2> at(size_t(n_grid) * M);   // [M][G]
+  for (int64_t g = 0; g < n_grid; ++g) {
+    double u[3];
+    grid_direction(grid_kind, grid, g, u);
+    for (int m = 0; m < M; ++m) {
+      double ph = p->pos[3 * m] * u[0] + p->pos[3 * m + 1] * u[1] + p->pos[3 * m + 2] * u[2];
+      ph -= std::rint(ph);
+      const double w = 2.0 * M_PI * ph;
+      at[size_t(m) * n_grid + g] = make_float2(float(std::cos(w)), float(std::sin(w)));
+    }
+  }
+  e = hipMalloc(&p->d_A, at.size() * sizeof(float2));
+  if (e == hipSuccess) e = hipMemcpy(p->d_A, at.data(), at.size() * sizeof(float2), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&p->d_coords, p->coords.size() * sizeof(double));
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_coords, p->coords.data(), p->coords.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    ba_status st = dev_error(fn, e);
+    free_plan(p);
+    return st;
+  }
+  *out = p;
+  return BA_OK;
+}
+
+ba_status ba_plan_destroy(ba_plan p) {
+  if (!p) return BA_OK;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(P_(p)->device);
+  (void)hipDeviceSynchronize();
+  (void)hipSetDevice(cur);
+  free_plan(P_(p));
+  return BA_OK;
+}
+
+ba_status ba_plan_info(ba_plan p, int32_t* n_elem, int64_t* n_grid, int32_t* ndim) {
+  if (!p) return arg_error("ba_plan_info", "plan is NULL");
+  if (n_elem) *n_elem = P_(p)->M;
+  if (n_grid) *n_grid = P_(p)->G;
+  if (ndim) *ndim = P_(p)->ndim;
+  return BA_OK;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+ba_status ba_workspace_size(ba_plan p, int32_t n_trials, int32_t n_snap, int32_t with_spectrum_out,
+                            size_t* bytes) {
+  static const char* fn = "ba_workspace_size";
+  if (!p) return arg_error(fn, "plan is NULL");
+  if (!bytes) return arg_error(fn, "bytes is NULL");
+  if (n_trials < 0 || n_snap < 1) return arg_error(fn, "n_trials >= 0 and n_snap >= 1 required");
+  const Plan& q = *P_(p);
+  size_t b = align256(size_t(n_trials) * q.M * q.M * sizeof(float2));
+  if (!with_spectrum_out) b += align256(size_t(n_trials) * q.G * sizeof(float));
+  *bytes = b;
+  return BA_OK;
+}
+
+#define CHECK_PLAN(fn)                                   \
+  if (!p) return arg_error(fn, "plan is NULL");          \
+  const Plan& q = *P_(p);                                \
+  (void)q;
+
+ba_status ba_covariance(ba_plan p, int32_t n_trials, int32_t n_snap, const void* Y, void* R,
+                        void* stream) {
+  static const char* fn = "ba_covariance";
+  CHECK_PLAN(fn);
+  if (n_trials < 0 || n_snap < 1) return arg_error(fn, "n_trials >= 0 and n_snap >= 1 required");
+  if (n_trials == 0) return BA_OK;
+  if (!Y || !R) return arg_error(fn, "null buffer");
+  hipError_t e = launch_covariance(q, n_trials, n_snap, static_cast<const float2*>(Y),
+                                   static_cast<float2*>(R), static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? BA_OK : dev_error(fn, e);
+}
+
+ba_status ba_spectrum(ba_plan p, int32_t n_trials, const void* R, float* P, void* stream) {
+  static const char* fn = "ba_spectrum";
+  CHECK_PLAN(fn);
+  if (n_trials < 0) return arg_error(fn, "n_trials >= 0 required");
+  if (n_trials == 0) return BA_OK;
+  if (!R || !P) return arg_error(fn, "null buffer");
+  hipError_t e = launch_spectrum(q, n_trials, static_cast<const float2*>(R), P,
+                                 static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? BA_OK : dev_error(fn, e);
+}
+
+ba_status ba_spectrum_snapshots(ba_plan p, int32_t n_trials, int32_t n_snap, const void* Y,
+                                float* P, void* stream) {
+  static const char* fn = "ba_spectrum_snapshots";
+  CHECK_PLAN(fn);
+  if (n_trials < 0 || n_snap < 1) return arg_error(fn, "n_trials >= 0 and n_snap >= 1 required");
+  if (n_trials == 0) return BA_OK;
+  if (!Y || !P) return arg_error(fn, "null buffer");
+  hipError_t e = launch_spectrum_snapshots(q, n_trials, n_snap, static_cast<const float2*>(Y), P,
+                                           static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? BA_OK : dev_error(fn, e);
+}
+
+ba_status ba_peaks(ba_plan p, int32_t n_trials, const float* P, int32_t k, int32_t* idx,
+                   float* val, double* refined, void* stream) {
+  static const char* fn = "ba_peaks";
+  CHECK_PLAN(fn);
+  if (n_trials < 0) return arg_error(fn, "n_trials >= 0 required");
+  if (k < 1 || k > kMaxPeaks) return arg_error(fn, "k must be in [1, 16]");
+  if (n_trials == 0) return BA_OK;
+  if (!P || !idx || !val) return arg_error(fn, "null buffer");
+  hipError_t e = launch_peaks(q, n_trials, P, k, idx, val, refined, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? BA_OK : dev_error(fn, e);
+}
+
+ba_status ba_proposal_moments(ba_plan p, int32_t n_trials, const float* P, double* mu_cov,
+                              void* stream) {
+  static const char* fn = "ba_proposal_moments";
+  CHECK_PLAN(fn);
+  if (n_trials < 0) return arg_error(fn, "n_trials >= 0 required");
+  if (n_trials == 0) return BA_OK;
+  if (!P || !mu_cov) return arg_error(fn, "null buffer");
+  hipError_t e = launch_moments(q, n_trials, P, mu_cov, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? BA_OK : dev_error(fn, e);
+}
+
+ba_status ba_run(ba_plan p, int32_t n_trials, int32_t n_snap, const void* Y, int32_t k, float* P,
+                 int32_t* idx, float* val, double* refined, void* workspace, size_t workspace_bytes,
+                 void* stream) {
+  static const char* fn = "ba_run";
+  CHECK_PLAN(fn);
+  if (n_trials < 0 || n_snap < 1) return arg_error(fn, "n_trials >= 0 and n_snap >= 1 required");
+  if (k < 1 || k > kMaxPeaks) return arg_error(fn, "k must be in [1, 16]");
+  if (n_trials == 0) return BA_OK;
+  if (!Y || !idx || !val) return arg_error(fn, "null buffer");
+  size_t need = 0;
+  ba_workspace_size(p, n_trials, n_snap, P != nullptr, &need);
+  if (!workspace || workspace_bytes < need)
+    return arg_error(fn, "workspace missing or smaller than ba_workspace_size");
+  if (reinterpret_cast<uintptr_t>(workspace) & 255) return arg_error(fn, "workspace must be 256-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  float2* R = reinterpret_cast<float2*>(ws);
+  float* Pw = P;
+  if (!Pw) Pw = reinterpret_cast<float*>(ws + align256(size_t(n_trials) * q.M * q.M * sizeof(float2)));
+  hipError_t e = launch_covariance(q, n_trials, n_snap, static_cast<const float2*>(Y), R, s);
+  if (e == hipSuccess) e = launch_spectrum(q, n_trials, R, Pw, s);
+  if (e == hipSuccess) e = launch_peaks(q, n_trials, Pw, k, idx, val, refined, s);
+  return e == hipSuccess ? BA_OK : dev_error(fn, e);
+}
+
+}  // extern "C"

@@ -1,0 +1,50 @@
+// Internal declarations shared by the C-ABI layer and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/bartlett.h"
+
+namespace ba {
+
+constexpr int kMaxElem = 256;
+constexpr int kMaxPeaks = 16;
+
+struct Plan {
+  int device = 0;
+  int M = 0;
+  int64_t G = 0;
+  int kind = 0;
+  int shape0 = 0, shape1 = 1, wrap0 = 0;
+  int rows = 0;        // candidate rows of dim0 (shape0 - 1 when the last row duplicates the first)
+  int ndim = 1;        // refined coordinates per peak
+  int coord_dim = 1;   // moment coordinates per grid point
+  int precision = BA_PREC_F32;
+
+  std::vector<double> pos;     // [M][3]
+  std::vector<double> coords;  // [G][coord_dim]
+
+  // device tables (owned)
+  float2* d_A = nullptr;       // [M][G] complex steering, A[m][g] = exp(+j 2 pi p_m . u_g)
+  float* d_X = nullptr;        // [G/16 tiles][2M][16] real-equivalent steering for the MFMA projection
+  double* d_coords = nullptr;  // [G][coord_dim]
+  int64_t Gpad = 0;            // G rounded up to the projection tile
+};
+
+// launchers: argument validation happens before these are called
+hipError_t launch_covariance(const Plan& p, int B, int T, const float2* Y, float2* R, hipStream_t s);
+hipError_t launch_spectrum(const Plan& p, int B, const float2* R, float* P, hipStream_t s);
+hipError_t launch_spectrum_valu(const Plan& p, int B, const float2* R, float* P, hipStream_t s);
+hipError_t launch_spectrum_snapshots(const Plan& p, int B, int T, const float2* Y, float* P,
+                                     hipStream_t s);
+hipError_t launch_peaks(const Plan& p, int B, const float* P, int k, int* idx, float* val,
+                        double* refined, hipStream_t s);
+hipError_t launch_moments(const Plan& p, int B, const float* P, double* mu_cov, hipStream_t s);
+
+void set_error(const std::string& msg);
+
+}  // namespace ba

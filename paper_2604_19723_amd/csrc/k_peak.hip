@@ -1,0 +1,294 @@
+// Peak pick, parabolic refinement and proposal moments per trial.
+//
+// The paper takes the candidate of maximum Bartlett cost as the proposal mean
+// and the cost-weighted second central moment as its covariance (Sec.
+// IV-D.2). Here the argmax is generalised to the K largest local maxima:
+// a point is a maximum when it is strictly greater than every neighbour
+// before it in raster order and >= every neighbour after it (8-neighbourhood
+// on 2-D grids, optional wrap of dim0); missing neighbours are not compared,
+// and every comparison with NaN is false. Ties in value go to the lower index.
+//
+// One workgroup per trial. Each lane scans a strided slice of the grid
+// (coalesced) and keeps a sorted top-KC list in registers; the lists meet in
+// LDS and K rounds of a wave-shuffle argmax pick the winners in order.
+#include <climits>
+
+#include "ba_internal.h"
+
+namespace ba {
+namespace {
+
+__device__ __forceinline__ bool better(float va, int ia, float vb, int ib) {
+  return va > vb || (va == vb && ia < ib);
+}
+
+__device__ __forceinline__ int wrap_row(int j0, int rows) {
+  return j0 < 0 ? j0 + rows : (j0 >= rows ? j0 - rows : j0);
+}
+
+__device__ bool is_local_max(const float* __restrict__ Pb, int i0, int i1, float p, int s1,
+                             int rows, int wrap0) {
+  if (p != p) return false;
+  bool ok = true;
+  for (int di = -1; di <= 1; ++di) {
+    int j0 = i0 + di;
+    if (wrap0)
+      j0 = wrap_row(j0, rows);
+    else if (j0 < 0 || j0 >= rows)
+      continue;
+    for (int dj = -1; dj <= 1; ++dj) {
+      if (di == 0 && dj == 0) continue;
+      if (s1 == 1 && dj != 0) continue;
+      const int j1 = i1 + dj;
+      if (j1 < 0 || j1 >= s1) continue;
+      const float q = Pb[int64_t(j0) * s1 + j1];
+      const bool earlier = di < 0 || (di == 0 && dj < 0);
+      ok = ok && (earlier ? (p > q) : (p >= q));
+    }
+  }
+  return ok;
+}
+
+// Insert (v, g) into a sorted list of compile-time capacity; the unrolled form
+// keeps the list in registers.
+template <int KC>
+__device__ __forceinline__ void insert(float (&lv)[KC], int (&li)[KC], float v, int g) {
+#pragma unroll
+  for (int j = KC - 1; j >= 0; --j) {
+    if (j > 0 && better(v, g, lv[j - 1], li[j - 1])) {
+      lv[j] = lv[j - 1];
+      li[j] = li[j - 1];
+    } else if (better(v, g, lv[j], li[j])) {
+      lv[j] = v;
+      li[j] = g;
+    }
+  }
+}
+
+__device__ double parabolic(double pm, double p0, double pp) {
+#pragma clang fp contract(off)
+  const double den = pm - 2.0 * p0 + pp;
+  if (den == 0.0 || !isfinite(den)) return 0.0;
+  const double d = 0.5 * (pm - pp) / den;
+  return d > 0.5 ? 0.5 : (d < -0.5 ? -0.5 : d);
+}
+
+template <int KC>
+__global__ __launch_bounds__(256) void k_peaks(const float* __restrict__ P, int64_t G, int s1,
+                                               int rows, int wrap0, int k, int* __restrict__ idx,
+                                               float* __restrict__ val,
+                                               double* __restrict__ refined, int ndim) {
+  const int64_t b = blockIdx.x;
+  const float* Pb = P + b * G;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+  float lv[KC];
+  int li[KC];
+#pragma unroll
+  for (int j = 0; j < KC; ++j) {
+    lv[j] = -INFINITY;
+    li[j] = INT_MAX;
+  }
+  const int64_t ncand = int64_t(rows) * s1;
+  for (int64_t g = tid; g < ncand; g += 256) {
+    const float p = Pb[g];
+    const int i0 = int(g / s1), i1 = int(g % s1);
+    if (is_local_max(Pb, i0, i1, p, s1, rows, wrap0)) insert<KC>(lv, li, p, int(g));
+  }
+
+  __shared__ float sv[256 * KC];
+  __shared__ int si[256 * KC];
+  __shared__ float wv[4];
+  __shared__ int wi[4];
+  __shared__ float selv[kMaxPeaks];
+  __shared__ int seli[kMaxPeaks];
+#pragma unroll
+  for (int j = 0; j < KC; ++j) {
+    sv[tid * KC + j] = lv[j];
+    si[tid * KC + j] = li[j];
+  }
+  __syncthreads();
+
+  int head = 0;
+  for (int r = 0; r < k; ++r) {
+    float v = head < KC ? sv[tid * KC + head] : -INFINITY;
+    int i = head < KC ? si[tid * KC + head] : INT_MAX;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const float ov = __shfl_xor(v, off, 64);
+      const int oi = __shfl_xor(i, off, 64);
+      if (better(ov, oi, v, i)) {
+        v = ov;
+        i = oi;
+      }
+    }
+    if (lane == 0) {
+      wv[wave] = v;
+      wi[wave] = i;
+    }
+    __syncthreads();
+    float bv = wv[0];
+    int bi = wi[0];
+#pragma unroll
+    for (int w = 1; w < 4; ++w)
+      if (better(wv[w], wi[w], bv, bi)) {
+        bv = wv[w];
+        bi = wi[w];
+      }
+    // every grid index lives in exactly one lane's list
+    if (bi != INT_MAX && head < KC && si[tid * KC + head] == bi) ++head;
+    if (tid == 0) {
+      selv[r] = bv;
+      seli[r] = bi;
+    }
+    __syncthreads();
+  }
+
+  if (tid < k) {
+    const int g = seli[tid];
+    int* ob = idx + b * k;
+    float* vb = val + b * k;
+    if (g == INT_MAX) {
+      ob[tid] = -1;
+      vb[tid] = __int_as_float(0x7fc00000);
+      if (refined)
+        for (int a = 0; a < ndim; ++a) refined[(b * k + tid) * ndim + a] = __longlong_as_double(0x7ff8000000000000LL);
+    } else {
+      ob[tid] = g;
+      vb[tid] = selv[tid];
+      if (refined) {
+        const int i0 = g / s1, i1 = g % s1;
+        const double p0 = double(Pb[g]);
+        double d0 = 0.0;
+        if (wrap0 || (i0 > 0 && i0 < rows - 1)) {
+          const int jm = wrap_row(i0 - 1, rows), jp = wrap_row(i0 + 1, rows);
+          d0 = parabolic(double(Pb[int64_t(jm) * s1 + i1]), p0, double(Pb[int64_t(jp) * s1 + i1]));
+        }
+        refined[(b * k + tid) * ndim + 0] = double(i0) + d0;
+        if (ndim == 2) {
+          double d1 = 0.0;
+          if (i1 > 0 && i1 < s1 - 1)
+            d1 = parabolic(double(Pb[int64_t(i0) * s1 + i1 - 1]), p0, double(Pb[int64_t(i0) * s1 + i1 + 1]));
+          refined[(b * k + tid) * ndim + 1] = double(i1) + d1;
+        }
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ double block_sum(double x, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  __syncthreads();
+  if (lane == 0) red[wave] = x;
+  __syncthreads();
+  return red[0] + red[1] + red[2] + red[3];
+}
+
+// Proposal moments: w = P / sum P over the distinct points, mu at the first
+// global maximum, C = sum w (x - mu)(x - mu)^T with azimuth wrap.
+__global__ __launch_bounds__(256) void k_moments(const float* __restrict__ P, int64_t G,
+                                                 int64_t ncand, const double* __restrict__ X,
+                                                 int d, int azwrap, double* __restrict__ out) {
+  const int64_t b = blockIdx.x;
+  const float* Pb = P + b * G;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ double red[4];
+  __shared__ float wv[4];
+  __shared__ int wi[4];
+
+  double s = 0.0;
+  float bv = -INFINITY;
+  int bi = INT_MAX;
+  for (int64_t g = tid; g < ncand; g += 256) {
+    const float p = Pb[g];
+    s += double(p);
+    if (better(p, int(g), bv, bi)) {
+      bv = p;
+      bi = int(g);
+    }
+  }
+  const double S = block_sum(s, red);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const float ov = __shfl_xor(bv, off, 64);
+    const int oi = __shfl_xor(bi, off, 64);
+    if (better(ov, oi, bv, bi)) {
+      bv = ov;
+      bi = oi;
+    }
+  }
+  if (lane == 0) {
+    wv[wave] = bv;
+    wi[wave] = bi;
+  }
+  __syncthreads();
+  float fv = wv[0];
+  int gs = wi[0];
+  for (int w = 1; w < 4; ++w)
+    if (better(wv[w], wi[w], fv, gs)) {
+      fv = wv[w];
+      gs = wi[w];
+    }
+  // all-NaN input leaves no maximum: the moments are NaN
+  const double nan = __longlong_as_double(0x7ff8000000000000LL);
+  double mu[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; a < d; ++a) mu[a] = gs != INT_MAX ? X[int64_t(gs) * d + a] : nan;
+
+  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t g = tid; g < ncand; g += 256) {
+    const double p = double(Pb[g]);
+    double D[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < d; ++a) D[a] = X[g * d + a] - mu[a];
+    if (azwrap) {
+      double r = fmod(D[0] + 180.0, 360.0);
+      if (r < 0.0) r += 360.0;
+      D[0] = r - 180.0;
+    }
+    int c = 0;
+    for (int i = 0; i < d; ++i)
+      for (int j = i; j < d; ++j) acc[c++] += p * D[i] * D[j];
+  }
+  double C[6];
+  const int nc = d * (d + 1) / 2;
+  for (int c = 0; c < nc; ++c) C[c] = block_sum(acc[c], red);
+  if (tid == 0) {
+    double* o = out + b * int64_t(d + d * d);
+    for (int a = 0; a < d; ++a) o[a] = mu[a];
+    int c = 0;
+    for (int i = 0; i < d; ++i)
+      for (int j = i; j < d; ++j) {
+        const double v = C[c++] / S;
+        o[d + i * d + j] = v;
+        o[d + j * d + i] = v;
+      }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_peaks(const Plan& p, int B, const float* P, int k, int* idx, float* val,
+                        double* refined, hipStream_t s) {
+  const dim3 grid{static_cast<uint32_t>(B)}, block{256u};
+  if (k <= 1)
+    hipLaunchKernelGGL(k_peaks<1>, grid, block, 0, s, P, p.G, p.shape1, p.rows, p.wrap0, k, idx, val, refined, p.ndim);
+  else if (k <= 2)
+    hipLaunchKernelGGL(k_peaks<2>, grid, block, 0, s, P, p.G, p.shape1, p.rows, p.wrap0, k, idx, val, refined, p.ndim);
+  else if (k <= 4)
+    hipLaunchKernelGGL(k_peaks<4>, grid, block, 0, s, P, p.G, p.shape1, p.rows, p.wrap0, k, idx, val, refined, p.ndim);
+  else if (k <= 8)
+    hipLaunchKernelGGL(k_peaks<8>, grid, block, 0, s, P, p.G, p.shape1, p.rows, p.wrap0, k, idx, val, refined, p.ndim);
+  else
+    hipLaunchKernelGGL(k_peaks<16>, grid, block, 0, s, P, p.G, p.shape1, p.rows, p.wrap0, k, idx, val, refined, p.ndim);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(const Plan& p, int B, const float* P, double* mu_cov, hipStream_t s) {
+  const int64_t ncand = int64_t(p.rows) * p.shape1;
+  hipLaunchKernelGGL(k_moments, dim3(unsigned(B)), dim3(256), 0, s, P, p.G, ncand, p.d_coords,
+                     p.coord_dim, p.kind == BA_GRID_AZEL_DEG ? 1 : 0, mu_cov);
+  return hipGetLastError();
+}
+
+}  // namespace ba

@@ -20,7 +20,8 @@ Randomness: every trial owns a child seed sequence
 so trial i is the same whatever the batch size. Draw order inside a trial:
 K (if random), M (if random), T (if random), SNR (if random), source angles
 (rejection sampling for the minimum separation), source amplitudes S
-(real parts then imaginary parts), noise N (real then imaginary).
+([T][K] complex, real and imaginary parts interleaved), noise N ([T][M]
+complex, interleaved the same way).
 """
 from __future__ import annotations
 
@@ -179,34 +180,67 @@ def noise_variance(snr_db: float, K: int, snr_def: str) -> float:
 
 
 def _snapshots(rng, A, T, sigma2):
+    """Y [T][M] = S A^T + N with S [T][K] ~ CN(0, 1) and N [T][M] ~ CN(0, sigma2).
+    Draws: S as T*K*2 normals (re, im interleaved, snapshot-major), then N as
+    T*M*2 normals in the same order."""
     M, K = A.shape
-    s = (rng.standard_normal((K, T)) + 1j * rng.standard_normal((K, T))) * math.sqrt(0.5)
-    n = (rng.standard_normal((M, T)) + 1j * rng.standard_normal((M, T))) * math.sqrt(0.5 * sigma2)
-    return (A @ s + n).T  # [T][M]
+    s = rng.standard_normal((T, K, 2)).view(np.complex128)[..., 0]
+    s *= math.sqrt(0.5)
+    n = rng.standard_normal((T, M, 2)).view(np.complex128)[..., 0]
+    n *= math.sqrt(0.5 * sigma2)
+    y = s @ A.T
+    y += n
+    return y
 
 
-def make_ula_trials(n_trials: int, n_elem: int, n_src: int, n_snap: int, snr_db, n_grid: int,
-                    seed_base: int, first_trial: int = 0, ang_lo=-60.0, ang_hi=60.0,
-                    min_sep=5.0, snr_def="per_source", name="") -> TrialSet:
-    """Uniform ULA batch. ``snr_db`` is a scalar or a sequence cycled over trials
-    (trial i takes snr_db[i % len])."""
-    snrs = np.atleast_1d(np.asarray(snr_db, dtype=np.float64))
+def _ula_chunk(args):
+    (i0, i1, n_elem, n_src, n_snap, snrs, seed_base, ang_lo, ang_hi, min_sep, snr_def, dtype) = args
     pos = ula_positions(n_elem)
-    Y = np.empty((n_trials, n_snap, n_elem), dtype=np.complex128)
-    truth = np.empty((n_trials, n_src))
-    snr = np.empty(n_trials)
-    sig = np.empty(n_trials)
-    for b in range(n_trials):
-        i = first_trial + b
+    n = i1 - i0
+    Y = np.empty((n, n_snap, n_elem), dtype=dtype)
+    truth = np.empty((n, n_src))
+    snr = np.empty(n)
+    sig = np.empty(n)
+    for b in range(n):
+        i = i0 + b
         rng = trial_rng(seed_base, i)
         snr[b] = snrs[i % len(snrs)]
         th = _draw_angles_1d(rng, n_src, ang_lo, ang_hi, min_sep)
         sig[b] = noise_variance(snr[b], n_src, snr_def)
         Y[b] = _snapshots(rng, response(pos, ula_dirs(th)), n_snap, sig[b])
         truth[b] = th
-    return TrialSet(Y=Y, pos_wl=pos, grid_kind=GRID_ULA_DEG, grid=ula_grid(n_grid),
-                    grid_shape=(n_grid, 1), wrap0=0, K=n_src, truth=truth, snr_db=snr,
-                    sigma2=sig, name=name)
+    return Y, truth, snr, sig
+
+
+def _parallel_chunks(fn, n_trials, first_trial, rest, workers):
+    bounds = np.linspace(0, n_trials, max(1, workers) * 4 + 1).astype(int)
+    jobs = [(first_trial + int(a), first_trial + int(b)) + rest
+            for a, b in zip(bounds[:-1], bounds[1:]) if b > a]
+    if workers <= 1 or n_trials < 256:
+        return [fn(j) for j in jobs]
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+        return list(ex.map(fn, jobs))
+
+
+def make_ula_trials(n_trials: int, n_elem: int, n_src: int, n_snap: int, snr_db, n_grid: int,
+                    seed_base: int, first_trial: int = 0, ang_lo=-60.0, ang_hi=60.0,
+                    min_sep=5.0, snr_def="per_source", name="", dtype=np.complex128,
+                    workers: int = 1) -> TrialSet:
+    """Uniform ULA batch. ``snr_db`` is a scalar or a sequence cycled over trials
+    (trial i takes snr_db[i % len]). ``dtype=np.complex64`` stores Y rounded to
+    what the device reads; ``workers`` > 1 generates in forked processes (call
+    it before the process touches the GPU)."""
+    snrs = tuple(np.atleast_1d(np.asarray(snr_db, dtype=np.float64)).tolist())
+    parts = _parallel_chunks(_ula_chunk, n_trials, first_trial,
+                             (n_elem, n_src, n_snap, snrs, seed_base, ang_lo, ang_hi, min_sep,
+                              snr_def, dtype), workers)
+    Y = np.concatenate([p[0] for p in parts]) if parts else np.empty((0, n_snap, n_elem), dtype)
+    cat = lambda k, shp: np.concatenate([p[k] for p in parts]) if parts else np.empty(shp)
+    return TrialSet(Y=Y, pos_wl=ula_positions(n_elem), grid_kind=GRID_ULA_DEG,
+                    grid=ula_grid(n_grid), grid_shape=(n_grid, 1), wrap0=0, K=n_src,
+                    truth=cat(1, (0, n_src)), snr_db=cat(2, (0,)), sigma2=cat(3, (0,)), name=name)
 
 
 def make_ura_trials(n_trials: int, nx: int, ny: int, n_src: int, n_snap: int, snr_db: float,
@@ -241,11 +275,12 @@ def config1(n_trials: int = 100, first_trial: int = 0) -> TrialSet:
                            name="ula16_k2_t64_g1801")
 
 
-def config2(n_trials: int = 10000, first_trial: int = 0, snr_db=C2_SNRS) -> TrialSet:
+def config2(n_trials: int = 10000, first_trial: int = 0, snr_db=C2_SNRS, dtype=np.complex128,
+            workers: int = 1) -> TrialSet:
     """64-element ULA, 4 sources, 256 snapshots, 7201-point grid; the SNR sweep
     -10..20 dB in 5 dB steps is cycled over the trials of one batch."""
     return make_ula_trials(n_trials, 64, 4, 256, snr_db, 7201, SEED_BASE + 2, first_trial,
-                           name="ula64_k4_t256_g7201")
+                           name="ula64_k4_t256_g7201", dtype=dtype, workers=workers)
 
 
 def config3(n_trials: int = 2000, first_trial: int = 0) -> TrialSet:
