@@ -94,10 +94,15 @@ def test_zero_trials_is_noop_and_bad_k_raises():
         Y = to_dev(ts)
         idx = torch.empty((1, 2), dtype=torch.int32, device=DEV)
         val = torch.empty((1, 2), dtype=torch.float32, device=DEV)
-        ws = bb.workspace_for(plan, 1, ts.n_snap)
+        ws = bb.workspace_for(plan, 1, ts.n_snap, with_spectrum_out=False)
         bb.ba_run(plan, 0, ts.n_snap, Y, 2, None, idx, val, None, ws)
-        with pytest.raises(bb.BartlettError):
-            bb.ba_run(plan, 1, ts.n_snap, Y, 17, None, idx, val, None, ws)
+        idx17 = torch.empty((1, 17), dtype=torch.int32, device=DEV)
+        val17 = torch.empty((1, 17), dtype=torch.float32, device=DEV)
+        with pytest.raises(bb.BartlettError) as ei:
+            bb.ba_run(plan, 1, ts.n_snap, Y, 17, None, idx17, val17, None, ws)
+        assert ei.value.status == bb.BA_ERR_ARG
+        with pytest.raises(ValueError):       # the binding refuses a short workspace
+            bb.ba_run(plan, 1, ts.n_snap, Y, 2, None, idx, val, None, ws[:16])
 
 
 def test_nan_input_gives_no_peaks_and_no_fault():
