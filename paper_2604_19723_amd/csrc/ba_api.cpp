@@ -48,7 +48,33 @@ static void grid_direction(int kind, const double* grid, int64_t g, double u[3])
 }
 
 hipError_t launch_spectrum(const Plan& p, int B, const float2* R, float* P, hipStream_t s) {
+  if (p.d_X) return launch_spectrum_mfma(p, B, R, P, s);
   return launch_spectrum_valu(p, B, R, P, s);
+}
+
+// Real-equivalent steering table in the B-fragment order of the MFMA
+// projection: column g of block jb = g / 16 sits at lane (k % 4) * 16 + g % 16 of
+// k-step k / 4; four consecutive k-steps of one lane share a 16-byte word.
+static std::vector<float> build_x_table(const std::vector<float2>& at, int M, int64_t G, int Mp,
+                                        int64_t* nblocks) {
+  const int K = 2 * Mp;
+  const int NB = proj_q_blocks_per_chunk(Mp);
+  int64_t Gb = (G + 15) / 16;
+  Gb = (Gb + NB - 1) / NB * NB;
+  *nblocks = Gb;
+  std::vector<float> x(size_t(Gb) * K * 16, 0.f);
+  auto place = [&](int64_t g, int k, float v) {
+    const int64_t jb = g / 16;
+    const int j = int(g % 16), s = k / 4, l = (k % 4) * 16 + j;
+    x[size_t(jb) * K * 16 + size_t(((s / 4) * 64 + l) * 4 + (s % 4))] = v;
+  };
+  for (int m = 0; m < M; ++m)
+    for (int64_t g = 0; g < G; ++g) {
+      const float2 a = at[size_t(m) * G + g];
+      place(g, m, a.x);
+      place(g, Mp + m, a.y);
+    }
+  return x;
 }
 
 static void free_plan(Plan* p) {
@@ -152,6 +178,12 @@ ba_status ba_plan_create(ba_plan* out, int32_t n_elem, const double* elem_pos_wl
   if (e == hipSuccess) e = hipMalloc(&p->d_coords, p->coords.size() * sizeof(double));
   if (e == hipSuccess)
     e = hipMemcpy(p->d_coords, p->coords.data(), p->coords.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess && M <= 64) {
+    p->Mp = M <= 8 ? 8 : M <= 16 ? 16 : M <= 32 ? 32 : 64;
+    std::vector<float> x = build_x_table(at, M, n_grid, p->Mp, &p->Xblocks);
+    e = hipMalloc(&p->d_X, x.size() * sizeof(float));
+    if (e == hipSuccess) e = hipMemcpy(p->d_X, x.data(), x.size() * sizeof(float), hipMemcpyHostToDevice);
+  }
   if (e != hipSuccess) {
     ba_status st = dev_error(fn, e);
     free_plan(p);

@@ -30,15 +30,20 @@ struct Plan {
 
   // device tables (owned)
   float2* d_A = nullptr;       // [M][G] complex steering, A[m][g] = exp(+j 2 pi p_m . u_g)
-  float* d_X = nullptr;        // [G/16 tiles][2M][16] real-equivalent steering for the MFMA projection
+  // real-equivalent steering x_g = [Re a_g; Im a_g] (rows padded to 2*Mp) in the
+  // MFMA B-fragment order of the projection kernel: [Xblocks][2Mp/16][64 lanes][4]
+  float* d_X = nullptr;
+  int Mp = 0;                  // padded element count of d_X (8, 16, 32 or 64); 0 = no table
+  int64_t Xblocks = 0;         // 16-column blocks in d_X (padded to whole chunks)
   double* d_coords = nullptr;  // [G][coord_dim]
-  int64_t Gpad = 0;            // G rounded up to the projection tile
 };
 
 // launchers: argument validation happens before these are called
 hipError_t launch_covariance(const Plan& p, int B, int T, const float2* Y, float2* R, hipStream_t s);
 hipError_t launch_spectrum(const Plan& p, int B, const float2* R, float* P, hipStream_t s);
 hipError_t launch_spectrum_valu(const Plan& p, int B, const float2* R, float* P, hipStream_t s);
+hipError_t launch_spectrum_mfma(const Plan& p, int B, const float2* R, float* P, hipStream_t s);
+int proj_q_blocks_per_chunk(int MP);
 hipError_t launch_spectrum_snapshots(const Plan& p, int B, int T, const float2* Y, float* P,
                                      hipStream_t s);
 hipError_t launch_peaks(const Plan& p, int B, const float* P, int k, int* idx, float* val,

@@ -81,6 +81,8 @@ def test_snapshot_route_matches_oracle():
 
 
 @pytest.mark.parametrize("M,T,G,K", [(1, 1, 5, 1), (2, 1, 3, 2), (5, 3, 64, 3), (7, 33, 1000, 16),
+                                     (8, 4, 17, 2), (16, 20, 4099, 3), (32, 9, 515, 3),
+                                     (48, 40, 1000, 4), (64, 7, 64, 2), (65, 5, 300, 2),
                                      (128, 17, 257, 6), (256, 2, 131, 2)])
 def test_edge_shapes(M, T, G, K):
     ts = wl.make_ula_trials(3, M, 1, T, 10.0, G, 4242, ang_lo=-30, ang_hi=30).rounded()
