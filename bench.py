@@ -24,7 +24,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK = {"f32": ("mfma", 157.3), "bf16x3": ("mfma", 2500.0), "bf16": ("mfma", 2500.0)}
+# dense peaks of the arithmetic each projection kernel runs on
+PEAK = {"f32": ("mfma", 157.3), "bf16x3": ("mfma", 2500.0), "bf16": ("mfma", 2500.0),
+        "f32_valu": ("alu", 157.3)}
 
 
 def log(*a):
@@ -32,14 +34,16 @@ def log(*a):
 
 
 def rmse_by_snr(ts, refined_deg, idx):
-    """1-D association: sort estimates and truths and pair them in order."""
+    """RMSE in degrees per SNR point, estimates associated to the truths
+    (sorted pairing on a line, Hungarian on the sphere)."""
+    from paper_2604_19723_amd import metrics
     out, fails = {}, 0
     err2 = {}
     for b in range(ts.n_trials):
         if np.any(idx[b] < 0):
             fails += 1
             continue
-        e = np.sort(refined_deg[b]) - np.sort(ts.truth[b])
+        e = metrics.associated_errors(refined_deg[b], ts.truth[b])
         err2.setdefault(float(ts.snr_db[b]), []).append(np.mean(e * e))
     for s in sorted(err2):
         out["%g" % s] = float(np.sqrt(np.mean(err2[s])))
@@ -76,6 +80,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--trials", type=int, default=10000)
     ap.add_argument("--precision", default="f32", choices=sorted(PEAK))
+    ap.add_argument("--workload", default="ula64", choices=["ula64", "ura256"],
+                    help="ula64: 64-element ULA, 7201-point grid (default); ura256: 16x16 URA, "
+                         "361x181 az/el grid")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -89,12 +96,16 @@ def main():
     from paper_2604_19723_amd import workload as wl
     workers = min(16, len(os.sched_getaffinity(0)))
     t = time.perf_counter()
-    ts = wl.config2(args.trials, dtype=np.complex64, workers=workers)   # before the GPU is touched
+    if args.workload == "ula64":
+        ts = wl.config2(args.trials, dtype=np.complex64, workers=workers)   # before the GPU is touched
+    else:
+        ts = wl.config3(args.trials, dtype=np.complex64, workers=workers)
     log("generated %d trials in %.1f s" % (ts.n_trials, time.perf_counter() - t))
 
     import torch
     from paper_2604_19723_amd import bartlett as bb
-    prec = {"f32": bb.BA_PREC_F32, "bf16x3": bb.BA_PREC_BF16X3, "bf16": bb.BA_PREC_BF16}[args.precision]
+    prec = {"f32": bb.BA_PREC_F32, "bf16x3": bb.BA_PREC_BF16X3, "bf16": bb.BA_PREC_BF16,
+            "f32_valu": bb.BA_PREC_F32_VALU}[args.precision]
     B, T, M, K = ts.n_trials, ts.n_snap, ts.n_elem, ts.K
     dev = torch.device("cuda:0")
     Y = torch.from_numpy(ts.Y).to(dev)
@@ -104,13 +115,14 @@ def main():
     P = torch.empty((B, G), dtype=torch.float32, device=dev)
     idx = torch.empty((B, K), dtype=torch.int32, device=dev)
     val = torch.empty((B, K), dtype=torch.float32, device=dev)
-    ref = torch.empty((B, K, 1), dtype=torch.float64, device=dev)
+    ref = torch.empty((B, K, plan.ndim), dtype=torch.float64, device=dev)
+    ws = bb.spectrum_workspace_for(plan, B, dev)
 
     def step(ev=None):
         bb.ba_covariance(plan, B, T, Y, R)
         if ev is not None:
             ev[0].record()
-        bb.ba_spectrum(plan, B, R, P)
+        bb.ba_spectrum(plan, B, R, P, ws)
         if ev is not None:
             ev[1].record()
         bb.ba_peaks(plan, B, P, K, idx, val, ref)
@@ -134,17 +146,20 @@ def main():
     bound, peak = PEAK[args.precision]
     achieved = flops_proj / (proj_ms * 1e-3) / 1e12
 
+    from paper_2604_19723_amd import metrics
     idx_h = idx.cpu().numpy()
-    ref_h = ref.cpu().numpy()[..., 0]
-    step_deg = (ts.grid[-1] - ts.grid[0]) / (G - 1)
-    rmse, fails = rmse_by_snr(ts, ts.grid[0] + ref_h * step_deg, idx_h)
+    est_deg = metrics.fractional_index_to_deg(ts.grid_kind, ts.grid, ts.grid_shape, ref.cpu().numpy())
+    rmse, fails = rmse_by_snr(ts, est_deg, idx_h)
 
     # spot parity on a few trials against the oracle
     from oracle import bartlett as ob
     A = ob.steering(ts.pos_wl, ob.directions(ts.grid_kind, ts.grid))
-    P_h = P[:8].cpu().numpy().astype(np.float64)
-    errs = [np.max(np.abs(P_h[b] - ob.spectrum(ob.covariance(ts.Y[b].astype(np.complex128)), A)))
-            / np.max(P_h[b]) for b in range(8)]
+    nspot = 8 if M <= 64 else 2
+    P_h = P[:nspot].cpu().numpy().astype(np.float64)
+    errs = []
+    for b in range(nspot):
+        Pr = ob.spectrum(ob.covariance(ts.Y[b].astype(np.complex128)), A)
+        errs.append(np.max(np.abs(P_h[b] - Pr)) / np.max(Pr))
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(ts, K, args.cpu_seconds)
     value = B * args.steps / dt
@@ -159,10 +174,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision == "f32" else args.precision,
+        "dtype": {"f32": "f32", "f32_valu": "f32", "bf16x3": "bf16x3", "bf16": "bf16"}[args.precision],
         "data": "synthetic (seeded signal model: CN sources + CN noise on a half-wavelength ULA)",
         "config": {"workload": ts.name, "trials": B, "n_elem": M, "n_snap": T, "n_src": K,
-                   "n_grid": G, "snr_db": list(wl.C2_SNRS), "precision": args.precision},
+                   "n_grid": G, "snr_db": sorted(set(float(x) for x in ts.snr_db)),
+                   "precision": args.precision},
         "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None,
                      "kernel": "spectrum projection", "kernel_ms": proj_ms,

@@ -56,6 +56,7 @@ typedef struct ba_plan_s* ba_plan;
 #define BA_PREC_F32     1   /* FP32 operands, FP32 accumulate (MFMA f32) */
 #define BA_PREC_BF16X3  2   /* hi/lo BF16 split, three BF16 MFMA passes, FP32 accumulate */
 #define BA_PREC_BF16    3   /* single BF16 pass (precision ablation only) */
+#define BA_PREC_F32_VALU 4  /* FP32 on the vector ALUs: the unfused reference kernel, for A/B timing */
 
 /* Grid kinds. */
 #define BA_GRID_DIRS      0  /* grid = host double [G][3] unit direction vectors */
@@ -119,11 +120,23 @@ ba_status ba_covariance(ba_plan p, int32_t n_trials, int32_t n_snap, const void*
                         void* stream);
 
 /*
- * Bartlett spectrum from covariances: P[b][g] = Re(a_g^H R_b a_g) / M^2.
- *   R  dev c64 [B][M][M] as written by ba_covariance (any Hermitian matrix).
- *   P  dev float [B][G].
+ * Workspace bytes ba_spectrum needs for n_trials trials (0 for FP32 plans of
+ * up to 64 elements; otherwise the real-equivalent covariance of every trial,
+ * (2 Mp)^2 * 4 bytes per trial with Mp the padded element count).
  */
-ba_status ba_spectrum(ba_plan p, int32_t n_trials, const void* R, float* P, void* stream);
+ba_status ba_spectrum_workspace_size(ba_plan p, int32_t n_trials, size_t* bytes);
+
+/*
+ * Bartlett spectrum from covariances: P[b][g] = Re(a_g^H R_b a_g) / M^2, computed
+ * as x_g^T Q_b x_g / M^2 with x_g = [Re a_g; Im a_g] and Q_b = [[Re R_b, -Im R_b],
+ * [Im R_b, Re R_b]] on the matrix cores, in the plan's precision.
+ *   R          dev c64 [B][M][M] as written by ba_covariance (any Hermitian matrix).
+ *   P          dev float [B][G].
+ *   workspace  dev, >= ba_spectrum_workspace_size bytes, 256-byte aligned (may be
+ *              NULL when that size is 0).
+ */
+ba_status ba_spectrum(ba_plan p, int32_t n_trials, const void* R, float* P, void* workspace,
+                      size_t workspace_bytes, void* stream);
 
 /*
  * Bartlett spectrum straight from snapshots (snapshot route, cheaper when T < M):

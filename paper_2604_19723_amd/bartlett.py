@@ -28,6 +28,7 @@ BA_ERR_STATE = -5
 BA_PREC_F32 = 1
 BA_PREC_BF16X3 = 2
 BA_PREC_BF16 = 3
+BA_PREC_F32_VALU = 4
 
 BA_GRID_DIRS = 0
 BA_GRID_ULA_DEG = 1
@@ -58,7 +59,8 @@ _SIGS = {
     "ba_plan_info": (_i32, [_vp, C.POINTER(_i32), C.POINTER(_i64), C.POINTER(_i32)]),
     "ba_workspace_size": (_i32, [_vp, _i32, _i32, _i32, C.POINTER(_sz)]),
     "ba_covariance": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp]),
-    "ba_spectrum": (_i32, [_vp, _i32, _vp, _vp, _vp]),
+    "ba_spectrum_workspace_size": (_i32, [_vp, _i32, C.POINTER(_sz)]),
+    "ba_spectrum": (_i32, [_vp, _i32, _vp, _vp, _vp, _sz, _vp]),
     "ba_spectrum_snapshots": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp]),
     "ba_peaks": (_i32, [_vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp]),
     "ba_proposal_moments": (_i32, [_vp, _i32, _vp, _vp, _vp]),
@@ -214,11 +216,20 @@ def ba_covariance(plan: Plan, n_trials, n_snap, Y, R, stream=None):
         _dev(R, "c64", n_trials * M * M, "R"), _stream(stream)))
 
 
-def ba_spectrum(plan: Plan, n_trials, R, P, stream=None):
+def ba_spectrum_workspace_size(plan: Plan, n_trials) -> int:
+    b = _sz()
+    _check("ba_spectrum_workspace_size",
+           lib().ba_spectrum_workspace_size(plan.handle, n_trials, C.byref(b)))
+    return b.value
+
+
+def ba_spectrum(plan: Plan, n_trials, R, P, workspace=None, stream=None):
     M, G = plan.M, plan.G
+    need = ba_spectrum_workspace_size(plan, n_trials)
+    ws, nbytes = _workspace(workspace, need)
     _check("ba_spectrum", lib().ba_spectrum(
         plan.handle, n_trials, _dev(R, "c64", n_trials * M * M, "R"),
-        _dev(P, "f32", n_trials * G, "P"), _stream(stream)))
+        _dev(P, "f32", n_trials * G, "P"), ws, nbytes, _stream(stream)))
 
 
 def ba_spectrum_snapshots(plan: Plan, n_trials, n_snap, Y, P, stream=None):
@@ -241,6 +252,20 @@ def ba_proposal_moments(plan: Plan, n_trials, P, mu_cov, stream=None):
     _check("ba_proposal_moments", lib().ba_proposal_moments(
         plan.handle, n_trials, _dev(P, "f32", n_trials * plan.G, "P"),
         _dev(mu_cov, "f64", n_trials * (d + d * d), "mu_cov"), _stream(stream)))
+
+
+def _workspace(workspace, need):
+    """(pointer, bytes) of a workspace tensor after checking it holds ``need`` bytes."""
+    if workspace is None:
+        if need:
+            raise ValueError("workspace of %d bytes required" % need)
+        return None, 0
+    if not workspace.is_cuda or not workspace.is_contiguous():
+        raise ValueError("workspace must be a contiguous device tensor")
+    nbytes = workspace.numel() * workspace.element_size()
+    if nbytes < need:
+        raise ValueError("workspace needs %d bytes, got %d" % (need, nbytes))
+    return C.c_void_p(workspace.data_ptr()), nbytes
 
 
 def ba_run(plan: Plan, n_trials, n_snap, Y, k, P, idx, val, refined, workspace, stream=None):
@@ -272,6 +297,12 @@ def workspace_for(plan: Plan, n_trials, n_snap, with_spectrum_out=True, device="
     import torch
     n = ba_workspace_size(plan, n_trials, n_snap, with_spectrum_out)
     return torch.empty(max(n, 256), dtype=torch.uint8, device=device)
+
+
+def spectrum_workspace_for(plan: Plan, n_trials, device="cuda"):
+    import torch
+    n = ba_spectrum_workspace_size(plan, n_trials)
+    return torch.empty(max(n, 256), dtype=torch.uint8, device=device) if n else None
 
 
 def run_grid_search(plan: Plan, Y, k, with_spectrum=True, stream=None):

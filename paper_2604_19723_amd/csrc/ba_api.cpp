@@ -47,22 +47,57 @@ static void grid_direction(int kind, const double* grid, int64_t g, double u[3])
   }
 }
 
-hipError_t launch_spectrum(const Plan& p, int B, const float2* R, float* P, hipStream_t s) {
-  if (p.d_X) return launch_spectrum_mfma(p, B, R, P, s);
-  return launch_spectrum_valu(p, B, R, P, s);
+// Which projection kernel a plan uses. FP32 up to 64 elements: Q in registers
+// (k_proj_q). Otherwise the streaming kernel, which first writes Q to the
+// workspace in fragment order.
+static bool uses_stream(const Plan& p) {
+  return p.precision != BA_PREC_F32_VALU && !(p.precision == BA_PREC_F32 && p.Mp <= 64);
 }
 
-// Real-equivalent steering table in the B-fragment order of the MFMA
-// projection: column g of block jb = g / 16 sits at lane (k % 4) * 16 + g % 16 of
-// k-step k / 4; four consecutive k-steps of one lane share a 16-byte word.
-static std::vector<float> build_x_table(const std::vector<float2>& at, int M, int64_t G, int Mp,
-                                        int64_t* nblocks) {
+size_t spectrum_ws_bytes(const Plan& p, int B) { return uses_stream(p) ? qprep_bytes(p, B) : 0; }
+
+hipError_t launch_spectrum(const Plan& p, int B, const float2* R, float* P, void* ws, hipStream_t s) {
+  if (p.precision == BA_PREC_F32_VALU) return launch_spectrum_valu(p, B, R, P, s);
+  if (!uses_stream(p)) return launch_spectrum_mfma(p, B, R, P, s);
+  return launch_spectrum_stream(p, B, R, ws, P, s);
+}
+
+// Steering value a_g[m] = exp(+j 2 pi p_m . u_g) in FP64, the phase in cycles
+// reduced to [-1/2, 1/2] before the complex exponential.
+struct Steer {
+  const std::vector<double>& pos;
+  const std::vector<double>& u;  // [G][3]
+  void operator()(int m, int64_t g, double* re, double* im) const {
+    double ph = pos[3 * m] * u[3 * g] + pos[3 * m + 1] * u[3 * g + 1] + pos[3 * m + 2] * u[3 * g + 2];
+    ph -= std::rint(ph);
+    const double w = 2.0 * M_PI * ph;
+    *re = std::cos(w);
+    *im = std::sin(w);
+  }
+};
+
+static uint16_t bf16_rne_host(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+
+static float bf16_to_float_host(uint16_t h) {
+  const uint32_t u = uint32_t(h) << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+// Real-equivalent steering x_g = [Re a_g; Im a_g] (rows padded to 2 Mp with
+// zeros) in the MFMA B-fragment order shared by the projection kernels:
+// column g of block jb = g / 16 sits at lane (k % 4) * 16 + g % 16 of k-step
+// k / 4, and four consecutive k-steps of one lane share a 16-byte word.
+static std::vector<float> build_x_table(const Steer& st, int M, int64_t G, int Mp, int64_t nblocks) {
   const int K = 2 * Mp;
-  const int NB = proj_q_blocks_per_chunk(Mp);
-  int64_t Gb = (G + 15) / 16;
-  Gb = (Gb + NB - 1) / NB * NB;
-  *nblocks = Gb;
-  std::vector<float> x(size_t(Gb) * K * 16, 0.f);
+  std::vector<float> x(size_t(nblocks) * K * 16, 0.f);
   auto place = [&](int64_t g, int k, float v) {
     const int64_t jb = g / 16;
     const int j = int(g % 16), s = k / 4, l = (k % 4) * 16 + j;
@@ -70,9 +105,38 @@ static std::vector<float> build_x_table(const std::vector<float2>& at, int M, in
   };
   for (int m = 0; m < M; ++m)
     for (int64_t g = 0; g < G; ++g) {
-      const float2 a = at[size_t(m) * G + g];
-      place(g, m, a.x);
-      place(g, Mp + m, a.y);
+      double re, im;
+      st(m, g, &re, &im);
+      place(g, m, float(re));
+      place(g, Mp + m, float(im));
+    }
+  return x;
+}
+
+// The same steering split into BF16 hi = bf16(x), lo = bf16(x - hi) from the
+// FP64 value, in the B-fragment order of v_mfma_f32_16x16x32_bf16:
+// [block][k-chunk of 32][hi, lo][lane][8], lane l element e holding
+// x[32 kc + 8 (l / 16) + e] of column 16 block + l % 16.
+static std::vector<uint16_t> build_xb_table(const Steer& st, int M, int64_t G, int Mp,
+                                            int64_t nblocks) {
+  const int K = 2 * Mp, nkc = K / 32;
+  std::vector<uint16_t> x(size_t(nblocks) * K * 16 * 2, 0);
+  auto place = [&](int64_t g, int k, double v) {
+    const int64_t jb = g / 16;
+    const int j = int(g % 16), kc = k / 32, kk = k % 32;
+    const int l = (kk / 8) * 16 + j, e = kk % 8;
+    const uint16_t hi = bf16_rne_host(float(v));
+    const uint16_t lo = bf16_rne_host(float(v - double(bf16_to_float_host(hi))));
+    const size_t base = ((size_t(jb) * nkc + kc) * 2) * 512;
+    x[base + size_t(l) * 8 + e] = hi;
+    x[base + 512 + size_t(l) * 8 + e] = lo;
+  };
+  for (int m = 0; m < M; ++m)
+    for (int64_t g = 0; g < G; ++g) {
+      double re, im;
+      st(m, g, &re, &im);
+      place(g, m, re);
+      place(g, Mp + m, im);
     }
   return x;
 }
@@ -84,6 +148,7 @@ static void free_plan(Plan* p) {
   (void)hipSetDevice(p->device);
   if (p->d_A) (void)hipFree(p->d_A);
   if (p->d_X) (void)hipFree(p->d_X);
+  if (p->d_Xb) (void)hipFree(p->d_Xb);
   if (p->d_coords) (void)hipFree(p->d_coords);
   (void)hipSetDevice(cur);
   delete p;
@@ -134,7 +199,8 @@ ba_status ba_plan_create(ba_plan* out, int32_t n_elem, const double* elem_pos_wl
   if (wrap0 < 0 || wrap0 > 2) return arg_error(fn, "wrap0 must be 0, 1 or 2");
   if (wrap0 && (wrap0 == 2 ? grid_shape0 - 1 : grid_shape0) < 3)
     return arg_error(fn, "a wrapping dimension needs a period of at least 3");
-  if (precision != BA_PREC_F32 && precision != BA_PREC_BF16X3 && precision != BA_PREC_BF16)
+  if (precision != BA_PREC_F32 && precision != BA_PREC_BF16X3 && precision != BA_PREC_BF16 &&
+      precision != BA_PREC_F32_VALU)
     return arg_error(fn, "unknown precision");
   for (int64_t i = 0; i < int64_t(n_elem) * 3; ++i)
     if (!std::isfinite(elem_pos_wl[i])) return arg_error(fn, "non-finite element position");
@@ -159,30 +225,39 @@ ba_status ba_plan_create(ba_plan* out, int32_t n_elem, const double* elem_pos_wl
   p->pos.assign(elem_pos_wl, elem_pos_wl + 3 * n_elem);
   p->coords.assign(grid, grid + gvals);
 
-  // Steering table in FP64: phase in cycles reduced to [-1/2, 1/2], then the
-  // complex exponential rounded once to FP32.
+  // Steering tables, all from FP64 values: the complex [M][G] table of the
+  // vector-ALU kernels, the FP32 real-equivalent table in MFMA fragment order,
+  // and (split precisions) its BF16 hi/lo split.
   const int M = n_elem;
-  std::vector<float2> at(size_t(n_grid) * M);   // [M][G]
-  for (int64_t g = 0; g < n_grid; ++g) {
-    double u[3];
-    grid_direction(grid_kind, grid, g, u);
-    for (int m = 0; m < M; ++m) {
-      double ph = p->pos[3 * m] * u[0] + p->pos[3 * m + 1] * u[1] + p->pos[3 * m + 2] * u[2];
-      ph -= std::rint(ph);
-      const double w = 2.0 * M_PI * ph;
-      at[size_t(m) * n_grid + g] = make_float2(float(std::cos(w)), float(std::sin(w)));
+  std::vector<double> u(size_t(n_grid) * 3);
+  for (int64_t g = 0; g < n_grid; ++g) grid_direction(grid_kind, grid, g, &u[3 * g]);
+  const Steer st{p->pos, u};
+  std::vector<float2> at(size_t(n_grid) * M);  // [M][G]
+  for (int m = 0; m < M; ++m)
+    for (int64_t g = 0; g < n_grid; ++g) {
+      double re, im;
+      st(m, g, &re, &im);
+      at[size_t(m) * n_grid + g] = make_float2(float(re), float(im));
     }
-  }
+  const bool split = precision == BA_PREC_BF16X3 || precision == BA_PREC_BF16;
+  p->Mp = M <= 8 ? 8 : M <= 16 ? 16 : M <= 32 ? 32 : M <= 64 ? 64 : M <= 128 ? 128 : 256;
+  if (split && p->Mp < 64) p->Mp = 64;
+  p->Gb = (n_grid + 15) / 16;
+  p->Xblocks = (p->Gb + 31) / 32 * 32;
   e = hipMalloc(&p->d_A, at.size() * sizeof(float2));
   if (e == hipSuccess) e = hipMemcpy(p->d_A, at.data(), at.size() * sizeof(float2), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMalloc(&p->d_coords, p->coords.size() * sizeof(double));
   if (e == hipSuccess)
     e = hipMemcpy(p->d_coords, p->coords.data(), p->coords.size() * sizeof(double), hipMemcpyHostToDevice);
-  if (e == hipSuccess && M <= 64) {
-    p->Mp = M <= 8 ? 8 : M <= 16 ? 16 : M <= 32 ? 32 : 64;
-    std::vector<float> x = build_x_table(at, M, n_grid, p->Mp, &p->Xblocks);
+  if (e == hipSuccess) {
+    std::vector<float> x = build_x_table(st, M, n_grid, p->Mp, p->Xblocks);
     e = hipMalloc(&p->d_X, x.size() * sizeof(float));
     if (e == hipSuccess) e = hipMemcpy(p->d_X, x.data(), x.size() * sizeof(float), hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess && split) {
+    std::vector<uint16_t> xb = build_xb_table(st, M, n_grid, p->Mp, p->Xblocks);
+    e = hipMalloc(&p->d_Xb, xb.size() * sizeof(uint16_t));
+    if (e == hipSuccess) e = hipMemcpy(p->d_Xb, xb.data(), xb.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
   }
   if (e != hipSuccess) {
     ba_status st = dev_error(fn, e);
@@ -222,8 +297,18 @@ ba_status ba_workspace_size(ba_plan p, int32_t n_trials, int32_t n_snap, int32_t
   if (n_trials < 0 || n_snap < 1) return arg_error(fn, "n_trials >= 0 and n_snap >= 1 required");
   const Plan& q = *P_(p);
   size_t b = align256(size_t(n_trials) * q.M * q.M * sizeof(float2));
+  b += align256(spectrum_ws_bytes(q, n_trials));
   if (!with_spectrum_out) b += align256(size_t(n_trials) * q.G * sizeof(float));
   *bytes = b;
+  return BA_OK;
+}
+
+ba_status ba_spectrum_workspace_size(ba_plan p, int32_t n_trials, size_t* bytes) {
+  static const char* fn = "ba_spectrum_workspace_size";
+  if (!p) return arg_error(fn, "plan is NULL");
+  if (!bytes) return arg_error(fn, "bytes is NULL");
+  if (n_trials < 0) return arg_error(fn, "n_trials >= 0 required");
+  *bytes = spectrum_ws_bytes(*P_(p), n_trials);
   return BA_OK;
 }
 
@@ -244,13 +329,18 @@ ba_status ba_covariance(ba_plan p, int32_t n_trials, int32_t n_snap, const void*
   return e == hipSuccess ? BA_OK : dev_error(fn, e);
 }
 
-ba_status ba_spectrum(ba_plan p, int32_t n_trials, const void* R, float* P, void* stream) {
+ba_status ba_spectrum(ba_plan p, int32_t n_trials, const void* R, float* P, void* workspace,
+                      size_t workspace_bytes, void* stream) {
   static const char* fn = "ba_spectrum";
   CHECK_PLAN(fn);
   if (n_trials < 0) return arg_error(fn, "n_trials >= 0 required");
   if (n_trials == 0) return BA_OK;
   if (!R || !P) return arg_error(fn, "null buffer");
-  hipError_t e = launch_spectrum(q, n_trials, static_cast<const float2*>(R), P,
+  const size_t need = spectrum_ws_bytes(q, n_trials);
+  if (need && (!workspace || workspace_bytes < need))
+    return arg_error(fn, "workspace missing or smaller than ba_spectrum_workspace_size");
+  if (reinterpret_cast<uintptr_t>(workspace) & 255) return arg_error(fn, "workspace must be 256-byte aligned");
+  hipError_t e = launch_spectrum(q, n_trials, static_cast<const float2*>(R), P, workspace,
                                  static_cast<hipStream_t>(stream));
   return e == hipSuccess ? BA_OK : dev_error(fn, e);
 }
@@ -307,10 +397,11 @@ ba_status ba_run(ba_plan p, int32_t n_trials, int32_t n_snap, const void* Y, int
   hipStream_t s = static_cast<hipStream_t>(stream);
   char* ws = static_cast<char*>(workspace);
   float2* R = reinterpret_cast<float2*>(ws);
+  char* Qws = ws + align256(size_t(n_trials) * q.M * q.M * sizeof(float2));
   float* Pw = P;
-  if (!Pw) Pw = reinterpret_cast<float*>(ws + align256(size_t(n_trials) * q.M * q.M * sizeof(float2)));
+  if (!Pw) Pw = reinterpret_cast<float*>(Qws + align256(spectrum_ws_bytes(q, n_trials)));
   hipError_t e = launch_covariance(q, n_trials, n_snap, static_cast<const float2*>(Y), R, s);
-  if (e == hipSuccess) e = launch_spectrum(q, n_trials, R, Pw, s);
+  if (e == hipSuccess) e = launch_spectrum(q, n_trials, R, Pw, Qws, s);
   if (e == hipSuccess) e = launch_peaks(q, n_trials, Pw, k, idx, val, refined, s);
   return e == hipSuccess ? BA_OK : dev_error(fn, e);
 }

@@ -33,17 +33,22 @@ struct Plan {
   // real-equivalent steering x_g = [Re a_g; Im a_g] (rows padded to 2*Mp) in the
   // MFMA B-fragment order of the projection kernel: [Xblocks][2Mp/16][64 lanes][4]
   float* d_X = nullptr;
-  int Mp = 0;                  // padded element count of d_X (8, 16, 32 or 64); 0 = no table
-  int64_t Xblocks = 0;         // 16-column blocks in d_X (padded to whole chunks)
+  uint16_t* d_Xb = nullptr;    // the same split into BF16 hi/lo (split precisions only)
+  int Mp = 0;                  // padded element count of the tables (8 .. 256)
+  int64_t Gb = 0;              // 16-column blocks that hold grid points
+  int64_t Xblocks = 0;         // 16-column blocks in the tables (Gb padded to a multiple of 32)
   double* d_coords = nullptr;  // [G][coord_dim]
 };
 
 // launchers: argument validation happens before these are called
 hipError_t launch_covariance(const Plan& p, int B, int T, const float2* Y, float2* R, hipStream_t s);
-hipError_t launch_spectrum(const Plan& p, int B, const float2* R, float* P, hipStream_t s);
+hipError_t launch_spectrum(const Plan& p, int B, const float2* R, float* P, void* ws, hipStream_t s);
+size_t spectrum_ws_bytes(const Plan& p, int B);
+size_t qprep_bytes(const Plan& p, int B);
+hipError_t launch_spectrum_stream(const Plan& p, int B, const float2* R, void* Qws, float* P,
+                                  hipStream_t s);
 hipError_t launch_spectrum_valu(const Plan& p, int B, const float2* R, float* P, hipStream_t s);
 hipError_t launch_spectrum_mfma(const Plan& p, int B, const float2* R, float* P, hipStream_t s);
-int proj_q_blocks_per_chunk(int MP);
 hipError_t launch_spectrum_snapshots(const Plan& p, int B, int T, const float2* Y, float* P,
                                      hipStream_t s);
 hipError_t launch_peaks(const Plan& p, int B, const float* P, int k, int* idx, float* val,

@@ -147,7 +147,7 @@ __global__ __launch_bounds__(256, 2) void k_proj_q(const float2* __restrict__ R,
 template <int MP>
 hipError_t launch_q(const Plan& p, int B, const float2* R, float* P, hipStream_t s) {
   using C = QCfg<MP>;
-  const int nchunk = int(p.Xblocks / C::NB);
+  const int nchunk = int((p.Gb + C::NB - 1) / C::NB);  // the table holds Xblocks >= nchunk * NB
   // split the grid columns over several workgroups when there are few trials
   int nsplit = 1;
   while (int64_t(B) * nsplit < 2048 && nsplit < nchunk) nsplit *= 2;
@@ -161,15 +161,6 @@ hipError_t launch_q(const Plan& p, int B, const float2* R, float* P, hipStream_t
 }
 
 }  // namespace
-
-int proj_q_blocks_per_chunk(int MP) {
-  switch (MP) {
-    case 8: return QCfg<8>::NB;
-    case 16: return QCfg<16>::NB;
-    case 32: return QCfg<32>::NB;
-    default: return QCfg<64>::NB;
-  }
-}
 
 hipError_t launch_spectrum_mfma(const Plan& p, int B, const float2* R, float* P, hipStream_t s) {
   switch (p.Mp) {

@@ -243,24 +243,35 @@ def make_ula_trials(n_trials: int, n_elem: int, n_src: int, n_snap: int, snr_db,
                     truth=cat(1, (0, n_src)), snr_db=cat(2, (0,)), sigma2=cat(3, (0,)), name=name)
 
 
-def make_ura_trials(n_trials: int, nx: int, ny: int, n_src: int, n_snap: int, snr_db: float,
-                    n_az: int, n_el: int, seed_base: int, first_trial: int = 0,
-                    el_lo=0.0, el_hi=80.0, min_sep=5.0, snr_def="per_source",
-                    name="") -> TrialSet:
+def _ura_chunk(args):
+    (i0, i1, nx, ny, n_src, n_snap, sig, seed_base, el_lo, el_hi, min_sep, dtype) = args
     pos = ura_positions(nx, ny)
-    M = nx * ny
-    Y = np.empty((n_trials, n_snap, M), dtype=np.complex128)
-    truth = np.empty((n_trials, n_src, 2))
-    sig = noise_variance(snr_db, n_src, snr_def)
-    for b in range(n_trials):
-        rng = trial_rng(seed_base, first_trial + b)
+    n = i1 - i0
+    Y = np.empty((n, n_snap, nx * ny), dtype=dtype)
+    truth = np.empty((n, n_src, 2))
+    for b in range(n):
+        rng = trial_rng(seed_base, i0 + b)
         ae = _draw_angles_azel(rng, n_src, el_lo, el_hi, min_sep)
         Y[b] = _snapshots(rng, response(pos, azel_dirs(ae[:, 0], ae[:, 1])), n_snap, sig)
         truth[b] = ae
-    return TrialSet(Y=Y, pos_wl=pos, grid_kind=GRID_AZEL_DEG, grid=azel_grid(n_az, n_el),
-                    grid_shape=(n_az, n_el), wrap0=2, K=n_src, truth=truth,
-                    snr_db=np.full(n_trials, float(snr_db)), sigma2=np.full(n_trials, sig),
-                    name=name)
+    return Y, truth
+
+
+def make_ura_trials(n_trials: int, nx: int, ny: int, n_src: int, n_snap: int, snr_db: float,
+                    n_az: int, n_el: int, seed_base: int, first_trial: int = 0,
+                    el_lo=0.0, el_hi=80.0, min_sep=5.0, snr_def="per_source",
+                    name="", dtype=np.complex128, workers: int = 1) -> TrialSet:
+    sig = noise_variance(snr_db, n_src, snr_def)
+    parts = _parallel_chunks(_ura_chunk, n_trials, first_trial,
+                             (nx, ny, n_src, n_snap, sig, seed_base, el_lo, el_hi, min_sep, dtype),
+                             workers)
+    M = nx * ny
+    Y = np.concatenate([p[0] for p in parts]) if parts else np.empty((0, n_snap, M), dtype)
+    truth = np.concatenate([p[1] for p in parts]) if parts else np.empty((0, n_src, 2))
+    return TrialSet(Y=Y, pos_wl=ura_positions(nx, ny), grid_kind=GRID_AZEL_DEG,
+                    grid=azel_grid(n_az, n_el), grid_shape=(n_az, n_el), wrap0=2, K=n_src,
+                    truth=truth, snr_db=np.full(n_trials, float(snr_db)),
+                    sigma2=np.full(n_trials, sig), name=name)
 
 
 # --------------------------------------------------------------------------- the five workloads
@@ -283,11 +294,12 @@ def config2(n_trials: int = 10000, first_trial: int = 0, snr_db=C2_SNRS, dtype=n
                            name="ula64_k4_t256_g7201", dtype=dtype, workers=workers)
 
 
-def config3(n_trials: int = 2000, first_trial: int = 0) -> TrialSet:
+def config3(n_trials: int = 2000, first_trial: int = 0, dtype=np.complex128,
+            workers: int = 1) -> TrialSet:
     """16x16 horizontal URA, 3 sources (az U[0,360), el U[0,80]), 512 snapshots,
     SNR 0 dB, 361x181 az/el grid."""
     return make_ura_trials(n_trials, 16, 16, 3, 512, 0.0, 361, 181, SEED_BASE + 3, first_trial,
-                           name="ura16x16_k3_t512_g361x181")
+                           name="ura16x16_k3_t512_g361x181", dtype=dtype, workers=workers)
 
 
 # ------------------------------------------------------------------ ragged (uneven) batches
