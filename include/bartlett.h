@@ -187,6 +187,71 @@ ba_status ba_run(ba_plan p, int32_t n_trials, int32_t n_snap, const void* Y, int
                  float* P, int32_t* idx, float* val, double* refined,
                  void* workspace, size_t workspace_bytes, void* stream);
 
+
+/* ------------------------------------------------------------------ ragged batches */
+
+/* Route of one trial through the spectrum: the covariance form a^H R a, or the
+ * snapshot form (1/T) sum_t |a^H y_t|^2 (fewer flops when T < M). Both give the
+ * same Bartlett cost. */
+#define BA_ROUTE_AUTO      -1   /* tuned table if ba_ragged_autotune ran, else snapshots iff T < M */
+#define BA_ROUTE_COV        0
+#define BA_ROUTE_SNAPSHOTS  1
+
+/* One trial of an uneven batch. */
+typedef struct {
+  int64_t y_offset;  /* complex offset of the trial's [T][M] snapshot block in the pool */
+  int32_t n_elem;    /* M, 1 <= M <= min(128, plan elements): the plan's first M elements */
+  int32_t n_snap;    /* T >= 1 */
+  int32_t k;         /* peaks wanted, 1 <= k <= kmax */
+  int32_t route;     /* BA_ROUTE_*; the snapshot route needs T <= the padded size (8, 16, 32, 64, 128) */
+} ba_trial;
+
+typedef struct ba_ragged_s* ba_ragged;
+
+/*
+ * Prepare an uneven batch of trials (different M, T and K) that share the
+ * plan's grid and the first elements of its geometry (a uniform array sliced
+ * to M elements is the same array up to a phase centre, which leaves the
+ * Bartlett cost unchanged). Builds per-size-class steering tables, orders the
+ * trials longest first, and captures one persistent fused launch
+ * (covariance -> spectrum -> peaks per trial, trials taken from an atomic
+ * ticket) in a HIP graph. Buffers are bound here; ba_ragged_launch replays.
+ *   plan        FP32 plan, G <= 16384, 1-D or 2-D grid.
+ *   desc        host, n_trials entries (copied).
+ *   kmax        1..8: output row width; entries past a trial's k are -1 / NaN.
+ *   Y_pool      dev c64 [pool_elems]; every trial's block must lie inside.
+ *   P           dev float [B][G] or NULL; idx dev int32 [B][kmax]; val dev float
+ *               [B][kmax]; refined dev double [B][kmax][ndim] or NULL.
+ * Allocates device memory (tables, descriptors); errors: BA_ERR_ARG,
+ * BA_ERR_NOMEM, BA_ERR_DEVICE.
+ */
+ba_status ba_ragged_create(ba_ragged* out, ba_plan plan, int32_t n_trials, const ba_trial* desc,
+                           int32_t kmax, const void* Y_pool, int64_t pool_elems, float* P,
+                           int32_t* idx, float* val, double* refined);
+
+/* Replay the captured launch on a stream. The plan and the bound buffers must
+ * stay alive; replays on one handle must not overlap. */
+ba_status ba_ragged_launch(ba_ragged r, void* stream);
+
+/*
+ * Autotune on this batch: per size class, the MFMA tile (waves along rows vs
+ * along grid columns); per (size class, log2 T bucket), the route. Candidates
+ * are timed with HIP events on up to max_probe trials each (best of `repeats`
+ * launches after one warm-up). Results are cached in cache_path (text, may be
+ * NULL) keyed by device, grid size and class/bucket; the graph is re-captured.
+ * Synchronous; writes outputs of the probed trials as a side effect.
+ */
+ba_status ba_ragged_autotune(ba_ragged r, const char* cache_path, int32_t repeats, int32_t max_probe);
+
+/* Route each trial takes (host int32 [B], BA_ROUTE_COV or BA_ROUTE_SNAPSHOTS). */
+ba_status ba_ragged_routes(ba_ragged r, int32_t* routes);
+
+/* Waves along rows chosen per size class (host int32 [5], classes 8..128). */
+ba_status ba_ragged_config(ba_ragged r, int32_t* wr_per_class);
+
+/* Destroy (NULL accepted); synchronises the device first. */
+ba_status ba_ragged_destroy(ba_ragged r);
+
 #ifdef __cplusplus
 }
 #endif

@@ -65,7 +65,21 @@ _SIGS = {
     "ba_peaks": (_i32, [_vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp]),
     "ba_proposal_moments": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "ba_run": (_i32, [_vp, _i32, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "ba_ragged_create": (_i32, [C.POINTER(_vp), _vp, _i32, _vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp]),
+    "ba_ragged_launch": (_i32, [_vp, _vp]),
+    "ba_ragged_autotune": (_i32, [_vp, C.c_char_p, _i32, _i32]),
+    "ba_ragged_routes": (_i32, [_vp, _vp]),
+    "ba_ragged_config": (_i32, [_vp, _vp]),
+    "ba_ragged_destroy": (_i32, [_vp]),
 }
+
+BA_ROUTE_AUTO = -1
+BA_ROUTE_COV = 0
+BA_ROUTE_SNAPSHOTS = 1
+
+# host layout of ba_trial
+TRIAL_DTYPE = np.dtype([("y_offset", np.int64), ("n_elem", np.int32), ("n_snap", np.int32),
+                        ("k", np.int32), ("route", np.int32)])
 
 
 def lib():
@@ -318,3 +332,80 @@ def run_grid_search(plan: Plan, Y, k, with_spectrum=True, stream=None):
     ws = workspace_for(plan, B, T, with_spectrum, dev)
     ba_run(plan, B, T, Y, k, P, idx, val, ref, ws, stream)
     return dict(P=P, idx=idx, val=val, refined=ref)
+
+
+# --------------------------------------------------------------------------- ragged batches
+
+class Ragged:
+    """Owns a ba_ragged handle and keeps the buffers it is bound to alive."""
+
+    def __init__(self, handle, plan, n_trials, kmax, keep):
+        self.handle, self.plan, self.n_trials, self.kmax = handle, plan, n_trials, kmax
+        self._keep = keep
+
+    def close(self):
+        if self.handle:
+            ba_ragged_destroy(self)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ba_ragged_create(plan: Plan, desc, kmax, Y_pool, P, idx, val, refined=None) -> Ragged:
+    d = np.ascontiguousarray(np.asarray(desc, dtype=TRIAL_DTYPE))
+    B = d.shape[0]
+    h = C.c_void_p()
+    _check("ba_ragged_create", lib().ba_ragged_create(
+        C.byref(h), plan.handle, B, d.ctypes.data_as(_vp), kmax,
+        _dev(Y_pool, "c64", 1, "Y_pool"), Y_pool.numel(),
+        _dev(P, "f32", B * plan.G, "P", optional=True), _dev(idx, "i32", B * kmax, "idx"),
+        _dev(val, "f32", B * kmax, "val"),
+        _dev(refined, "f64", B * kmax * plan.ndim, "refined", optional=True)))
+    return Ragged(h, plan, B, kmax, (plan, Y_pool, P, idx, val, refined))
+
+
+def ba_ragged_launch(r: Ragged, stream=None):
+    _check("ba_ragged_launch", lib().ba_ragged_launch(r.handle, _stream(stream)))
+
+
+def ba_ragged_autotune(r: Ragged, cache_path=None, repeats=2, max_probe=512):
+    _check("ba_ragged_autotune", lib().ba_ragged_autotune(
+        r.handle, cache_path.encode() if cache_path else None, repeats, max_probe))
+
+
+def ba_ragged_routes(r: Ragged):
+    out = np.empty(r.n_trials, np.int32)
+    _check("ba_ragged_routes", lib().ba_ragged_routes(r.handle, out.ctypes.data_as(_vp)))
+    return out
+
+
+def ba_ragged_config(r: Ragged):
+    out = np.empty(5, np.int32)
+    _check("ba_ragged_config", lib().ba_ragged_config(r.handle, out.ctypes.data_as(_vp)))
+    return out
+
+
+def ba_ragged_destroy(r: Ragged):
+    _check("ba_ragged_destroy", lib().ba_ragged_destroy(r.handle))
+
+
+def ragged_descriptors(rs, route=BA_ROUTE_AUTO):
+    """ba_trial records for a workload.RaggedSet."""
+    d = np.zeros(rs.n_trials, TRIAL_DTYPE)
+    d["y_offset"] = rs.y_offset
+    d["n_elem"] = rs.n_elem
+    d["n_snap"] = rs.n_snap
+    d["k"] = rs.k
+    d["route"] = route
+    return d
+

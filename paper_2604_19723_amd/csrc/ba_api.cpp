@@ -154,11 +154,18 @@ static void free_plan(Plan* p) {
   delete p;
 }
 
+// FP32 fragment-order table of the first Mrows elements of a plan, padded to Mp
+// element rows and nblocks column blocks (used by the ragged path per size class).
+std::vector<float> plan_x_table(const Plan& p, int Mrows, int Mp, int64_t nblocks) {
+  std::vector<double> u(size_t(p.G) * 3);
+  for (int64_t g = 0; g < p.G; ++g) grid_direction(p.kind, p.coords.data(), g, &u[3 * g]);
+  const Steer st{p.pos, u};
+  return build_x_table(st, Mrows, p.G, Mp, nblocks);
+}
+
 }  // namespace ba
 
 using namespace ba;
-
-struct ba_plan_s : public ba::Plan {};
 
 static inline Plan* P_(ba_plan p) { return static_cast<Plan*>(p); }
 

@@ -56,5 +56,9 @@ hipError_t launch_peaks(const Plan& p, int B, const float* P, int k, int* idx, f
 hipError_t launch_moments(const Plan& p, int B, const float* P, double* mu_cov, hipStream_t s);
 
 void set_error(const std::string& msg);
+std::vector<float> plan_x_table(const Plan& p, int Mrows, int Mp, int64_t nblocks);
 
 }  // namespace ba
+
+// the opaque C handle is the plan itself
+struct ba_plan_s : public ba::Plan {};

@@ -1,0 +1,496 @@
+// Uneven batches in one persistent launch: covariance -> Bartlett spectrum ->
+// peaks, trial by trial, for trials of different element counts, snapshot
+// counts and source counts (the Sec. IV-D.2 grid search run for many
+// heterogeneous realisations at once).
+//
+// Each workgroup (8 waves, 160 KB LDS) takes the next trial from an atomic
+// ticket; trials are ordered longest first on the host, so the tail of the
+// launch is made of short trials. Per trial, everything stays on the CU:
+//  1. covariance route: R = (1/T) sum_t y_t y_t^H into LDS on the vector ALUs
+//     (snapshot chunks staged in LDS, 4 x BN register blocks over the upper
+//     triangle, the snapshot range split over thread groups when the matrix
+//     is small, partial sums combined in a fixed order); Q = [[Rr, -Ri],
+//     [Ri, Rr]] then goes into MFMA A-operand registers;
+//     snapshot route (few snapshots): the A operand is S = [[Yr, Yi],
+//     [Yi, -Yr]] read straight from the snapshots, rows 2T instead of 2M;
+//  2. projection on v_mfma_f32_16x16x4f32 against the steering table of the
+//     trial's size class (the first Mp elements of the plan's geometry:
+//     exact, a per-point phase common to all elements cancels in |a^H y|^2),
+//     the epilogue forming x^T (Q x) or sum |S x|^2 into an LDS spectrum row;
+//  3. peak pick and FP64 refinement from that LDS row.
+#include <climits>
+
+#include "ragged.h"
+
+namespace ba {
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 512;
+constexpr int kOffP = 64 * 1024;      // spectrum row (<= 64 KB)
+constexpr int kOffRed = 128 * 1024;   // cross-wave partial sums (<= 32 KB)
+constexpr int kOffY = 128 * 1024;     // snapshot staging during the covariance (24 KB)
+constexpr int kStageBytes = 24 * 1024;
+
+template <int MP>
+struct RC {
+  static constexpr int K = 2 * MP;
+  static constexpr int KS = K / 4;
+  static constexpr int NRB = K / 16;
+  static constexpr int BLK = K * 16;
+  static constexpr int NB = 8192 / BLK;
+  static constexpr int CH4 = 2048;
+  static constexpr int F4 = CH4 / kThreads;
+};
+
+__device__ __forceinline__ bool better(float va, int ia, float vb, int ib) {
+  return va > vb || (va == vb && ia < ib);
+}
+
+__device__ __forceinline__ int wrap_row(int j0, int rows) {
+  return j0 < 0 ? j0 + rows : (j0 >= rows ? j0 - rows : j0);
+}
+
+__device__ double parabolic(double pm, double p0, double pp) {
+#pragma clang fp contract(off)
+  const double den = pm - 2.0 * p0 + pp;
+  if (den == 0.0 || !isfinite(den)) return 0.0;
+  const double d = 0.5 * (pm - pp) / den;
+  return d > 0.5 ? 0.5 : (d < -0.5 ? -0.5 : d);
+}
+
+// ---------------------------------------------------------------- covariance
+
+template <int BN>
+__device__ void covariance_lds(const float2* __restrict__ Yb, int M, int T, unsigned char* smem) {
+  constexpr int BM = 4;
+  float2* sR = reinterpret_cast<float2*>(smem);
+  float2* sPart = sR + M * M;
+  float2* sY = reinterpret_cast<float2*>(smem + kOffY);
+  const int tid = threadIdx.x;
+  const int nbm = (M + BM - 1) / BM, nbn = (M + BN - 1) / BN;
+  int n_bp = 0;
+  for (int bn = 0; bn < nbn; ++bn) n_bp += min(nbm - 1, (BN * bn + BN - 1) / BM) + 1;
+  // thread groups split the snapshots when the matrix is small; their partial
+  // sums must fit between R and the snapshot staging area
+  const int part_bytes = n_bp * BM * BN * 8;
+  const int room = (kOffY - M * M * 8) / part_bytes;
+  const int n_tg = max(1, min(kThreads / n_bp, 1 + room));
+  const int bp = tid % n_bp, tg = tid / n_bp;
+  const bool active = tg < n_tg && tid < n_bp * n_tg;
+  int bm = 0, bn = 0;
+  {
+    int r = bp;
+    for (bn = 0; bn < nbn; ++bn) {
+      const int c = min(nbm - 1, (BN * bn + BN - 1) / BM) + 1;
+      if (r < c) break;
+      r -= c;
+    }
+    bm = r;
+  }
+  float ar[BM][BN], ai[BM][BN];
+#pragma unroll
+  for (int i = 0; i < BM; ++i)
+#pragma unroll
+    for (int j = 0; j < BN; ++j) ar[i][j] = ai[i][j] = 0.f;
+
+  const int TC = kStageBytes / (M * 8);
+  for (int t0 = 0; t0 < T; t0 += TC) {
+    const int nt = min(TC, T - t0);
+    for (int v = tid; v < TC * M; v += kThreads) {
+      const int tt = v / M;
+      sY[v] = tt < nt ? Yb[int64_t(t0) * M + v] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    if (active) {
+      for (int tt = tg; tt < nt; tt += n_tg) {
+        const float2* yt = sY + tt * M;
+        float2 ym[BM], yn[BN];
+#pragma unroll
+        for (int i = 0; i < BM; ++i) {
+          const int m = BM * bm + i;
+          ym[i] = m < M ? yt[m] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int j = 0; j < BN; ++j) {
+          const int n = BN * bn + j;
+          yn[j] = n < M ? yt[n] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int i = 0; i < BM; ++i)
+#pragma unroll
+          for (int j = 0; j < BN; ++j) {
+            // ym * conj(yn)
+            ar[i][j] += ym[i].x * yn[j].x + ym[i].y * yn[j].y;
+            ai[i][j] += ym[i].y * yn[j].x - ym[i].x * yn[j].y;
+          }
+      }
+    }
+    __syncthreads();
+  }
+  // combine the thread groups in a fixed order
+  if (active && tg > 0) {
+    float2* dst = sPart + (int64_t(tg - 1) * n_bp + bp) * (BM * BN);
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+      for (int j = 0; j < BN; ++j) dst[i * BN + j] = make_float2(ar[i][j], ai[i][j]);
+  }
+  __syncthreads();
+  if (active && tg == 0) {
+    for (int g2 = 1; g2 < n_tg; ++g2) {
+      const float2* src = sPart + (int64_t(g2 - 1) * n_bp + bp) * (BM * BN);
+#pragma unroll
+      for (int i = 0; i < BM; ++i)
+#pragma unroll
+        for (int j = 0; j < BN; ++j) {
+          ar[i][j] += src[i * BN + j].x;
+          ai[i][j] += src[i * BN + j].y;
+        }
+    }
+  }
+  __syncthreads();
+  if (active && tg == 0) {
+    const float invT = 1.0f / float(T);
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+      for (int j = 0; j < BN; ++j) {
+        const int m = BM * bm + i, n = BN * bn + j;
+        if (m < M && n < M && m <= n) {
+          const float re = ar[i][j] * invT;
+          const float im = (m == n) ? 0.f : ai[i][j] * invT;
+          sR[m * M + n] = make_float2(re, im);
+          sR[n * M + m] = make_float2(re, -im);
+        }
+      }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- one trial
+
+template <int MP, int WR>
+__device__ void trial_impl(const RArgs& A, const RItem& it, unsigned char* smem) {
+  using C = RC<MP>;
+  constexpr int RB = (C::NRB + WR - 1) / WR;  // row blocks per wave (round-robin)
+  constexpr int WC = (kThreads / 64) / WR;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wr = wave % WR, wc = wave / WR;
+  const int M = it.M, T = it.T;
+  const float2* Yb = A.Y + it.y_off;
+  const bool cov = it.route == kRouteCov;
+  const int Tp = (T + 7) & ~7;
+  const int nrb_act = cov ? C::NRB : min(C::NRB, Tp / 8);
+
+  // 1. A operand
+  float a[RB][C::KS];
+  if (cov) {
+    covariance_lds<(MP >= 128 ? 8 : 4)>(Yb, M, T, smem);
+    const float2* sR = reinterpret_cast<const float2*>(smem);
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int s = 0; s < C::KS; ++s) {
+        const int i = 16 * (rb * WR + wr) + (lane & 15);
+        const int k = 4 * s + (lane >> 4);
+        const bool iim = i >= MP, kim = k >= MP;
+        const int ir = iim ? i - MP : i, kr = kim ? k - MP : k;
+        float q = 0.f;
+        if (i < C::K && ir < M && kr < M) {
+          const float2 r = sR[ir * M + kr];
+          q = (iim == kim) ? r.x : (iim ? r.y : -r.y);
+        }
+        a[rb][s] = q;
+      }
+  } else {
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int s = 0; s < C::KS; ++s) {
+        const int i = 16 * (rb * WR + wr) + (lane & 15);
+        const int k = 4 * s + (lane >> 4);
+        const bool second = i >= Tp;
+        const int t = second ? i - Tp : i;
+        const bool kim = k >= MP;
+        const int m = kim ? k - MP : k;
+        float q = 0.f;
+        if (i < 2 * Tp && t < T && m < M) {
+          const float2 y = Yb[int64_t(t) * M + m];
+          // rows t: [Yr, Yi]; rows Tp + t: [Yi, -Yr]
+          q = second ? (kim ? -y.x : y.y) : (kim ? y.y : y.x);
+        }
+        a[rb][s] = q;
+      }
+  }
+  __syncthreads();  // LDS covariance consumed
+
+  // 2. projection
+  float4* sX = reinterpret_cast<float4*>(smem);
+  float* sP = reinterpret_cast<float*>(smem + kOffP);
+  float* red = reinterpret_cast<float*>(smem + kOffRed);  // [2][WR][NB*16]
+  const float4* Xg = A.X[it.cls];
+  const int nchunk = A.nchunk[it.cls];
+  const float scale = cov ? 1.0f / float(M * M) : 1.0f / (float(T) * float(M * M));
+  float* Pout = A.P ? A.P + int64_t(it.trial) * A.G : nullptr;
+
+  float4 pre[C::F4];
+#pragma unroll
+  for (int f = 0; f < C::F4; ++f) pre[f] = Xg[f * kThreads + threadIdx.x];
+#pragma unroll
+  for (int f = 0; f < C::F4; ++f) sX[f * kThreads + threadIdx.x] = pre[f];
+  __syncthreads();
+  for (int c = 0; c < nchunk; ++c) {
+    const int buf = c & 1;
+    const bool more = c + 1 < nchunk;
+    if (more) {
+#pragma unroll
+      for (int f = 0; f < C::F4; ++f) pre[f] = Xg[int64_t(c + 1) * C::CH4 + f * kThreads + threadIdx.x];
+    }
+    const float4* xb4 = sX + buf * C::CH4;
+    const float* xbf = reinterpret_cast<const float*>(xb4);
+    for (int jb = wc; jb < C::NB; jb += WC) {
+      floatx4 acc[RB];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) acc[rb] = floatx4{0.f, 0.f, 0.f, 0.f};
+      const float4* bx = xb4 + jb * (C::BLK / 4);
+#pragma unroll
+      for (int s4 = 0; s4 < C::KS / 4; ++s4) {
+        const float4 bv = bx[s4 * 64 + lane];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          if (rb * WR + wr < nrb_act) {
+            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 0], bv.x, acc[rb], 0, 0, 0);
+            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 1], bv.y, acc[rb], 0, 0, 0);
+            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 2], bv.z, acc[rb], 0, 0, 0);
+            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 3], bv.w, acc[rb], 0, 0, 0);
+          }
+        }
+      }
+      float part = 0.f;
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        const int rbg = rb * WR + wr;
+        if (rbg < nrb_act) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            if (cov) {
+              const int i = 16 * rbg + 4 * (lane >> 4) + r;
+              const int s = i >> 2;
+              const float xv = xbf[jb * C::BLK + ((s >> 2) * 64 + r * 16 + (lane & 15)) * 4 + (s & 3)];
+              part += xv * acc[rb][r];
+            } else {
+              part += acc[rb][r] * acc[rb][r];
+            }
+          }
+        }
+      }
+      part += __shfl_xor(part, 16, 64);
+      part += __shfl_xor(part, 32, 64);
+      if (lane < 16) red[(buf * WR + wr) * (C::NB * 16) + jb * 16 + lane] = part;
+    }
+    if (more) {
+#pragma unroll
+      for (int f = 0; f < C::F4; ++f) sX[(buf ^ 1) * C::CH4 + f * kThreads + threadIdx.x] = pre[f];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < C::NB * 16; t += kThreads) {
+      float s = 0.f;
+#pragma unroll
+      for (int w = 0; w < WR; ++w) s += red[(buf * WR + w) * (C::NB * 16) + t];
+      const int64_t g = int64_t(c) * C::NB * 16 + t;
+      if (g < A.G) {
+        const float p = s * scale;
+        sP[g] = p;
+        if (Pout) Pout[g] = p;
+      }
+    }
+  }
+  __syncthreads();  // spectrum row complete
+
+  // 3. peaks from the LDS row (same rule as the standalone peak kernel)
+  constexpr int KC = kRaggedMaxPeaks;
+  float lv[KC];
+  int li[KC];
+#pragma unroll
+  for (int j = 0; j < KC; ++j) {
+    lv[j] = -INFINITY;
+    li[j] = INT_MAX;
+  }
+  const int s1 = A.s1, rows = A.rows, wrap0 = A.wrap0;
+  const int64_t ncand = int64_t(rows) * s1;
+  for (int64_t g = threadIdx.x; g < ncand; g += kThreads) {
+    const float p = sP[g];
+    if (p != p) continue;
+    const int i0 = int(g / s1), i1 = int(g % s1);
+    bool ok = true;
+    for (int di = -1; di <= 1; ++di) {
+      int j0 = i0 + di;
+      if (wrap0)
+        j0 = wrap_row(j0, rows);
+      else if (j0 < 0 || j0 >= rows)
+        continue;
+      for (int dj = -1; dj <= 1; ++dj) {
+        if ((di == 0 && dj == 0) || (s1 == 1 && dj != 0)) continue;
+        const int j1 = i1 + dj;
+        if (j1 < 0 || j1 >= s1) continue;
+        const float q = sP[int64_t(j0) * s1 + j1];
+        const bool earlier = di < 0 || (di == 0 && dj < 0);
+        ok = ok && (earlier ? (p > q) : (p >= q));
+      }
+    }
+    if (ok) {
+#pragma unroll
+      for (int j = KC - 1; j >= 0; --j) {
+        if (j > 0 && better(p, int(g), lv[j - 1], li[j - 1])) {
+          lv[j] = lv[j - 1];
+          li[j] = li[j - 1];
+        } else if (better(p, int(g), lv[j], li[j])) {
+          lv[j] = p;
+          li[j] = int(g);
+        }
+      }
+    }
+  }
+  float* sv = reinterpret_cast<float*>(smem);                     // [512][KC]
+  int* si = reinterpret_cast<int*>(smem + kThreads * KC * 4);     // [512][KC]
+  float* wv = reinterpret_cast<float*>(smem + kOffRed);           // [8]
+  int* wi = reinterpret_cast<int*>(smem + kOffRed + 64);          // [8]
+  float* selv = reinterpret_cast<float*>(smem + kOffRed + 128);   // [KC]
+  int* seli = reinterpret_cast<int*>(smem + kOffRed + 192);       // [KC]
+#pragma unroll
+  for (int j = 0; j < KC; ++j) {
+    sv[threadIdx.x * KC + j] = lv[j];
+    si[threadIdx.x * KC + j] = li[j];
+  }
+  __syncthreads();
+  int head = 0;
+  for (int r = 0; r < it.K; ++r) {
+    float v = head < KC ? sv[threadIdx.x * KC + head] : -INFINITY;
+    int i = head < KC ? si[threadIdx.x * KC + head] : INT_MAX;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const float ov = __shfl_xor(v, off, 64);
+      const int oi = __shfl_xor(i, off, 64);
+      if (better(ov, oi, v, i)) {
+        v = ov;
+        i = oi;
+      }
+    }
+    if (lane == 0) {
+      wv[wave] = v;
+      wi[wave] = i;
+    }
+    __syncthreads();
+    float bv = wv[0];
+    int bi = wi[0];
+#pragma unroll
+    for (int w = 1; w < kThreads / 64; ++w)
+      if (better(wv[w], wi[w], bv, bi)) {
+        bv = wv[w];
+        bi = wi[w];
+      }
+    if (bi != INT_MAX && head < KC && si[threadIdx.x * KC + head] == bi) ++head;
+    if (threadIdx.x == 0) {
+      selv[r] = bv;
+      seli[r] = bi;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < A.kmax) {
+    const int j = threadIdx.x;
+    const int64_t o = int64_t(it.trial) * A.kmax + j;
+    const int g = j < it.K ? seli[j] : INT_MAX;
+    const double nan = __longlong_as_double(0x7ff8000000000000LL);
+    if (g == INT_MAX) {
+      A.idx[o] = -1;
+      A.val[o] = __int_as_float(0x7fc00000);
+      if (A.refined)
+        for (int d = 0; d < A.ndim; ++d) A.refined[o * A.ndim + d] = nan;
+    } else {
+      A.idx[o] = g;
+      A.val[o] = selv[j];
+      if (A.refined) {
+        const int i0 = g / s1, i1 = g % s1;
+        const double p0 = double(sP[g]);
+        double d0 = 0.0;
+        if (wrap0 || (i0 > 0 && i0 < rows - 1)) {
+          const int jm = wrap_row(i0 - 1, rows), jp = wrap_row(i0 + 1, rows);
+          d0 = parabolic(double(sP[int64_t(jm) * s1 + i1]), p0, double(sP[int64_t(jp) * s1 + i1]));
+        }
+        A.refined[o * A.ndim] = double(i0) + d0;
+        if (A.ndim == 2) {
+          double d1 = 0.0;
+          if (i1 > 0 && i1 < s1 - 1)
+            d1 = parabolic(double(sP[int64_t(i0) * s1 + i1 - 1]), p0, double(sP[int64_t(i0) * s1 + i1 + 1]));
+          A.refined[o * A.ndim + 1] = double(i1) + d1;
+        }
+      }
+    }
+  }
+  __syncthreads();  // LDS reused by the next trial
+}
+
+__global__ __launch_bounds__(kThreads, 1) void k_ragged(RArgs A) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  __shared__ int s_ticket;
+  for (;;) {
+    if (threadIdx.x == 0) s_ticket = atomicAdd(A.counter, 1);
+    __syncthreads();
+    const int t = s_ticket;
+    __syncthreads();
+    if (t >= A.n_items) break;  // uniform: every wave leaves
+    const RItem it = A.items[t];
+    const int wr = A.wr[it.cls];
+    switch (it.cls) {
+      case 0: trial_impl<8, 1>(A, it, smem); break;
+      case 1:
+        if (wr == 1) trial_impl<16, 1>(A, it, smem);
+        else trial_impl<16, 2>(A, it, smem);
+        break;
+      case 2:
+        if (wr == 2) trial_impl<32, 2>(A, it, smem);
+        else trial_impl<32, 4>(A, it, smem);
+        break;
+      case 3:
+        if (wr == 4) trial_impl<64, 4>(A, it, smem);
+        else trial_impl<64, 8>(A, it, smem);
+        break;
+      default: trial_impl<128, 8>(A, it, smem); break;
+    }
+  }
+}
+
+__global__ void k_ragged_reset(int32_t* counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+}
+
+}  // namespace
+
+int ragged_blocks_per_chunk(int cls) {
+  switch (cls) {
+    case 0: return RC<8>::NB;
+    case 1: return RC<16>::NB;
+    case 2: return RC<32>::NB;
+    case 3: return RC<64>::NB;
+    default: return RC<128>::NB;
+  }
+}
+
+hipError_t ragged_prepare() {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_ragged),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, kRaggedLds);
+}
+
+hipError_t launch_ragged(const RArgs& a, int n_wg, hipStream_t s) {
+  hipLaunchKernelGGL(k_ragged, dim3(unsigned(n_wg)), dim3(kThreads), kRaggedLds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_ragged_reset(int32_t* counter, hipStream_t s) {
+  hipLaunchKernelGGL(k_ragged_reset, dim3(1), dim3(64), 0, s, counter);
+  return hipGetLastError();
+}
+
+}  // namespace ba

@@ -1,0 +1,138 @@
+"""Uneven batches in one persistent launch under a HIP graph: every trial
+against the FP64 oracle on its own centred array, both routes, graph replay
+determinism, and the autotuner."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import bartlett as ob
+from paper_2604_19723_amd import bartlett as bb
+from paper_2604_19723_amd import workload as wl
+
+from parity_util import check_peaks_same_precision, normwise_err, peak_agreement_fp64
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+KMAX = 8
+
+
+def ragged_plan(G=3601, M=128):
+    return bb.ba_plan_create(M, wl.ula_positions(M), bb.BA_GRID_ULA_DEG, G, wl.ula_grid(G), G, 1, 0)
+
+
+def run(rs, route=bb.BA_ROUTE_AUTO, autotune=None, replays=1):
+    B, G = rs.n_trials, len(rs.grid)
+    plan = ragged_plan(G)
+    Y = torch.from_numpy(rs.pool_c64()).to(DEV)
+    P = torch.full((B, G), -1.0, dtype=torch.float32, device=DEV)
+    idx = torch.empty((B, KMAX), dtype=torch.int32, device=DEV)
+    val = torch.empty((B, KMAX), dtype=torch.float32, device=DEV)
+    ref = torch.empty((B, KMAX, 1), dtype=torch.float64, device=DEV)
+    desc = bb.ragged_descriptors(rs, route)
+    with bb.ba_ragged_create(plan, desc, KMAX, Y, P, idx, val, ref) as r:
+        if autotune is not None:
+            bb.ba_ragged_autotune(r, autotune, repeats=1, max_probe=64)
+        outs = []
+        for _ in range(replays):
+            bb.ba_ragged_launch(r)
+            torch.cuda.synchronize()
+            outs.append((P.clone(), idx.clone(), val.clone(), ref.clone()))
+            # eager work on the same stream between replays
+            x = torch.randn(512, 512, device=DEV)
+            (x @ x).sum().item()
+        routes = bb.ba_ragged_routes(r)
+        cfg = bb.ba_ragged_config(r)
+    plan.close()
+    P, idx, val, ref = [t.cpu().numpy() for t in outs[0]]
+    return dict(P=P, idx=idx, val=val, ref=ref, routes=routes, cfg=cfg, outs=outs)
+
+
+def check(rs, o, fp64_peaks=True):
+    pool = rs.pool_c64().astype(np.complex128)
+    bad, ncmp = [], 0
+    emax = 0.0
+    for i in range(rs.n_trials):
+        M, T, K = int(rs.n_elem[i]), int(rs.n_snap[i]), int(rs.k[i])
+        Yi = pool[rs.y_offset[i]:rs.y_offset[i] + M * T].reshape(T, M)
+        A = ob.steering(wl.ula_positions(M), ob.directions(ob.GRID_ULA_DEG, rs.grid))
+        Pref = ob.spectrum(ob.covariance(Yi), A)
+        e = normwise_err(o["P"][i][None], Pref[None])[0]
+        emax = max(emax, e)
+        assert e <= 1e-5, (i, M, T, K, e, o["routes"][i])
+        G = len(rs.grid)
+        check_peaks_same_precision(o["P"][i][None], o["idx"][i][None, :K], o["val"][i][None, :K],
+                                   o["ref"][i][None, :K], K, (G, 1), 0)
+        assert np.all(o["idx"][i, K:] == -1) and np.all(np.isnan(o["val"][i, K:]))
+        if fp64_peaks:
+            n, _, b = peak_agreement_fp64(Pref[None], o["idx"][i][None, :K], K, (G, 1), 0, 1e-5)
+            ncmp += n
+            bad += b
+    assert not bad, bad[:3]
+    return emax
+
+
+def test_config4_subset_auto_routes():
+    rs = wl.config4(400)
+    o = run(rs)
+    assert 0 < np.sum(o["routes"] == bb.BA_ROUTE_SNAPSHOTS) < rs.n_trials
+    print("ragged normwise max", check(rs, o))
+
+
+@pytest.mark.parametrize("route", [bb.BA_ROUTE_COV, bb.BA_ROUTE_SNAPSHOTS])
+def test_forced_routes(route):
+    rs = wl.config4(150, first_trial=1000)
+    if route == bb.BA_ROUTE_SNAPSHOTS:
+        keep = [i for i in range(rs.n_trials)
+                if ((int(rs.n_snap[i]) + 7) & ~7) <= (8 << [8, 16, 32, 64, 128].index(
+                    next(c for c in (8, 16, 32, 64, 128) if rs.n_elem[i] <= c)))]
+        rs = _subset(rs, keep)
+    o = run(rs, route=route)
+    assert np.all(o["routes"] == route)
+    check(rs, o)
+
+
+def _subset(rs, keep):
+    blocks = [rs.trial_y(i).reshape(-1) for i in keep]
+    sizes = np.array([b.size for b in blocks], np.int64)
+    off = np.zeros(len(keep), np.int64)
+    off[1:] = np.cumsum(sizes)[:-1]
+    return wl.RaggedSet(pool=np.concatenate(blocks), y_offset=off, n_elem=rs.n_elem[keep],
+                        n_snap=rs.n_snap[keep], k=rs.k[keep], truth=[rs.truth[i] for i in keep],
+                        snr_db=rs.snr_db[keep], grid=rs.grid)
+
+
+def test_edge_trials():
+    rng = np.random.default_rng(5)
+    Ms = [1, 3, 8, 9, 17, 33, 100, 128, 128, 64]
+    Ts = [1, 2, 7, 300, 1, 5, 40, 24, 200, 64]
+    Ks = [1, 8, 2, 8, 3, 1, 6, 4, 8, 5]
+    blocks = [(rng.standard_normal((T, M)) + 1j * rng.standard_normal((T, M))).reshape(-1)
+              for M, T in zip(Ms, Ts)]
+    sizes = np.array([b.size for b in blocks], np.int64)
+    off = np.zeros(len(Ms), np.int64)
+    off[1:] = np.cumsum(sizes)[:-1]
+    rs = wl.RaggedSet(pool=np.concatenate(blocks), y_offset=off, n_elem=np.array(Ms, np.int32),
+                      n_snap=np.array(Ts, np.int32), k=np.array(Ks, np.int32), truth=[None] * len(Ms),
+                      snr_db=np.zeros(len(Ms)), grid=wl.ula_grid(1001))
+    o = run(rs)
+    check(rs, o, fp64_peaks=False)
+
+
+def test_graph_replays_are_bitwise_identical():
+    rs = wl.config4(120, first_trial=5000)
+    o = run(rs, replays=3)
+    for later in o["outs"][1:]:
+        for a, b in zip(o["outs"][0], later):
+            assert torch.equal(a, b)
+
+
+def test_autotune_keeps_parity_and_uses_cache(tmp_path):
+    rs = wl.config4(200, first_trial=9000)
+    cache = str(tmp_path / "tune.txt")
+    o = run(rs, autotune=cache)
+    check(rs, o)
+    text = open(cache).read()
+    assert "|wr|" in text
+    o2 = run(rs, autotune=cache)          # second run reads the cache
+    assert np.array_equal(o["cfg"], o2["cfg"])
