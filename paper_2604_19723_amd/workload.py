@@ -334,34 +334,56 @@ class RaggedSet:
         return self.pool[o:o + M * T].reshape(T, M)
 
     def pool_c64(self) -> np.ndarray:
+        if self.pool.dtype == np.complex64:
+            return self.pool
         return np.ascontiguousarray(self.pool.astype(np.complex64))
 
 
+def _ragged_sizes(rng, t_max):
+    K = int(rng.integers(1, 7))
+    M = int(C4_SIZES[int(rng.integers(0, len(C4_SIZES)))])
+    T = int(np.clip(np.rint(np.exp(rng.uniform(math.log(16.0), math.log(t_max)))), 16, t_max))
+    return K, M, T
+
+
 def config4(n_trials: int = 50000, first_trial: int = 0, n_grid: int = 3601,
-            t_max: int = 2048) -> RaggedSet:
+            t_max: int = 2048, dtype=np.complex128, workers: int = 1) -> RaggedSet:
     """Uneven batch: M uniform over {8,16,32,64,128}, K uniform over 1..6,
-    T = clip(rint(exp(U[ln 16, ln t_max])), 16, t_max), SNR ~ U[-10, 20] dB."""
+    T = clip(rint(exp(U[ln 16, ln t_max])), 16, t_max), SNR ~ U[-10, 20] dB.
+    Sizes are drawn first (the head of each trial's stream) to lay out the
+    pool; then ``workers`` threads fill their trials in place."""
     seed = SEED_BASE + 4
     Ms = np.empty(n_trials, np.int32)
     Ts = np.empty(n_trials, np.int32)
     Ks = np.empty(n_trials, np.int32)
-    snr = np.empty(n_trials)
-    blocks, truth = [], []
     for b in range(n_trials):
-        rng = trial_rng(seed, first_trial + b)
-        K = int(rng.integers(1, 7))
-        M = int(C4_SIZES[int(rng.integers(0, len(C4_SIZES)))])
-        T = int(np.clip(np.rint(np.exp(rng.uniform(math.log(16.0), math.log(t_max)))), 16, t_max))
-        s = float(rng.uniform(-10.0, 20.0))
-        th = _draw_angles_1d(rng, K, -60.0, 60.0, 5.0)
-        y = _snapshots(rng, response(ula_positions(M), ula_dirs(th)), T, noise_variance(s, K, "per_source"))
-        Ms[b], Ts[b], Ks[b], snr[b] = M, T, K, s
-        blocks.append(y.reshape(-1))
-        truth.append(th)
-    sizes = np.array([x.size for x in blocks], dtype=np.int64)
+        Ks[b], Ms[b], Ts[b] = _ragged_sizes(trial_rng(seed, first_trial + b), t_max)
+    sizes = Ms.astype(np.int64) * Ts
     off = np.zeros(n_trials, np.int64)
     off[1:] = np.cumsum(sizes)[:-1]
-    pool = np.concatenate(blocks) if blocks else np.zeros(0, np.complex128)
+    pool = np.empty(int(sizes.sum()), dtype)
+    snr = np.empty(n_trials)
+    truth = [None] * n_trials
+
+    def fill(lo, hi):
+        for b in range(lo, hi):
+            rng = trial_rng(seed, first_trial + b)
+            K, M, T = _ragged_sizes(rng, t_max)
+            s = float(rng.uniform(-10.0, 20.0))
+            th = _draw_angles_1d(rng, K, -60.0, 60.0, 5.0)
+            y = _snapshots(rng, response(ula_positions(M), ula_dirs(th)), T,
+                           noise_variance(s, K, "per_source"))
+            pool[off[b]:off[b] + M * T] = y.reshape(-1)
+            snr[b] = s
+            truth[b] = th
+
+    if workers <= 1 or n_trials < 64:
+        fill(0, n_trials)
+    else:
+        import concurrent.futures as cf
+        bounds = np.linspace(0, n_trials, workers * 8 + 1).astype(int)
+        with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+            list(ex.map(lambda ab: fill(*ab), zip(bounds[:-1], bounds[1:])))
     return RaggedSet(pool=pool, y_offset=off, n_elem=Ms, n_snap=Ts, k=Ks, truth=truth,
                      snr_db=snr, grid=ula_grid(n_grid), name="ragged_m8-128_t16-2048_g3601")
 
