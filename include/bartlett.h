@@ -252,6 +252,86 @@ ba_status ba_ragged_config(ba_ragged r, int32_t* wr_per_class);
 /* Destroy (NULL accepted); synchronises the device first. */
 ba_status ba_ragged_destroy(ba_ragged r);
 
+/* ------------------------------------------------------------------ learned proposal network */
+
+/* The paper has no learned part (hybrid learned / model-based processing is
+ * named as future work in its conclusions). This network predicts coarse
+ * directions from the sample covariance so that only narrow windows of the
+ * Bartlett grid are scanned; the full grid search is its fallback. */
+
+typedef struct ba_mlp_s* ba_mlp;
+
+/*
+ * Pack covariances for the network: per trial, M diagonal real parts, then the
+ * strict upper triangle's real parts, then its imaginary parts (row-major),
+ * all times M / tr(R): M^2 floats.
+ *   R  dev c64 [B][M][M];  X  dev float [B][M*M].
+ */
+ba_status ba_pack_covariance(int32_t n_elem, int32_t n_trials, const void* R, float* X, void* stream);
+
+/*
+ * Network d_in -> n_hidden x (affine + exact GELU, d_hidden wide) -> affine ->
+ * d_out, weights W [out][in] and biases, FP32 master copies. precision
+ * BA_PREC_BF16: GEMM operands rounded to BF16 (round to nearest even), FP32
+ * accumulate; BA_PREC_F32: FP32 throughout. Allocates parameters, Adam moments
+ * and activations for up to max_batch rows; the calls below allocate nothing.
+ * Weights start uniform in +-1/sqrt(fan_in) from `seed`.
+ */
+ba_status ba_mlp_create(ba_mlp* out, int32_t d_in, int32_t d_hidden, int32_t n_hidden, int32_t d_out,
+                        int32_t max_batch, int32_t precision, uint64_t seed);
+ba_status ba_mlp_destroy(ba_mlp n);
+ba_status ba_mlp_num_params(ba_mlp n, int64_t* count);
+
+/* Host copies of all parameters, in the order W1, b1, W2, b2, ... (row-major).
+ * set_weights also clears the Adam moments and step count. Synchronous. */
+ba_status ba_mlp_get_weights(ba_mlp n, float* host, int64_t count);
+ba_status ba_mlp_set_weights(ba_mlp n, const float* host, int64_t count);
+
+/* Y = net(X) for B rows (any B >= 0; processed max_batch rows at a time).
+ * X dev float [B][d_in]; Y dev float [B][d_out]. */
+ba_status ba_mlp_forward(ba_mlp n, int32_t B, const float* X, float* Y, void* stream);
+
+/*
+ * Masked mean-squared error L = sum m (y - t)^2 / sum m and its gradient with
+ * respect to every parameter (same order as the weights), B <= max_batch.
+ *   T, mask  dev float [B][d_out] (mask may be NULL = all ones);
+ *   grads_out dev float [num_params]; loss_out dev float scalar or NULL.
+ */
+ba_status ba_mlp_gradients(ba_mlp n, int32_t B, const float* X, const float* T, const float* mask,
+                           float* grads_out, float* loss_out, void* stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the
+ * gradients of the loss above, B <= max_batch. */
+ba_status ba_mlp_train_step(ba_mlp n, int32_t B, const float* X, const float* T, const float* mask,
+                            float lr, float* loss_out, void* stream);
+
+/* Input and output widths of a network. */
+ba_status ba_mlp_dims(ba_mlp n, int32_t* d_in, int32_t* d_out);
+
+/* Workspace bytes of ba_propose_refine. */
+ba_status ba_propose_workspace_size(ba_plan plan, int32_t n_trials, int32_t d_out, int32_t k, size_t* bytes);
+
+/*
+ * Learned proposal + refinement: pack R, run the network (its first k outputs
+ * are sin(direction) of the sources), scan only the full-grid points within
+ * +-half_window of each proposal (nearest full-grid index), and take each
+ * window's maximum as a peak, refined as on the full grid. A trial falls back
+ * to the full-grid search (covariance already given) when a window maximum
+ * lies on a window edge that is not a grid edge, when two windows find the
+ * same point, on NaN, or when a peak's normalised cost P M / tr(R) is below
+ * tau. Outputs are then the full-grid ones.
+ *   plan        FP32 plan, M <= 64, uniform 1-D angle grid (BA_GRID_ULA_DEG).
+ *   net         d_in = M^2, d_out >= k.
+ *   R           dev c64 [B][M][M]; k in [1, 8]; half_window in [1, 100]; tau in [0, 1].
+ *   idx, val, refined  dev [B][k] (refined in grid units); fell_back dev uint8 [B].
+ *   n_fallback  host int32 (may be NULL): trials that fell back.
+ * Synchronises the stream once (to size the fallback batch).
+ */
+ba_status ba_propose_refine(ba_plan plan, ba_mlp net, int32_t n_trials, const void* R, int32_t k,
+                            int32_t half_window, float tau, int32_t* idx, float* val, double* refined,
+                            uint8_t* fell_back, int32_t* n_fallback, void* workspace, size_t workspace_bytes,
+                            void* stream);
+
 #ifdef __cplusplus
 }
 #endif

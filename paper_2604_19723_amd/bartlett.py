@@ -71,6 +71,19 @@ _SIGS = {
     "ba_ragged_routes": (_i32, [_vp, _vp]),
     "ba_ragged_config": (_i32, [_vp, _vp]),
     "ba_ragged_destroy": (_i32, [_vp]),
+    "ba_pack_covariance": (_i32, [_i32, _i32, _vp, _vp, _vp]),
+    "ba_mlp_create": (_i32, [C.POINTER(_vp), _i32, _i32, _i32, _i32, _i32, _i32, C.c_uint64]),
+    "ba_mlp_destroy": (_i32, [_vp]),
+    "ba_mlp_num_params": (_i32, [_vp, C.POINTER(_i64)]),
+    "ba_mlp_get_weights": (_i32, [_vp, _vp, _i64]),
+    "ba_mlp_set_weights": (_i32, [_vp, _vp, _i64]),
+    "ba_mlp_forward": (_i32, [_vp, _i32, _vp, _vp, _vp]),
+    "ba_mlp_gradients": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "ba_mlp_train_step": (_i32, [_vp, _i32, _vp, _vp, _vp, C.c_float, _vp, _vp]),
+    "ba_mlp_dims": (_i32, [_vp, C.POINTER(_i32), C.POINTER(_i32)]),
+    "ba_propose_workspace_size": (_i32, [_vp, _i32, _i32, _i32, C.POINTER(_sz)]),
+    "ba_propose_refine": (_i32, [_vp, _vp, _i32, _vp, _i32, _i32, C.c_float, _vp, _vp, _vp, _vp,
+                                 C.POINTER(_i32), _vp, _sz, _vp]),
 }
 
 BA_ROUTE_AUTO = -1
@@ -408,4 +421,125 @@ def ragged_descriptors(rs, route=BA_ROUTE_AUTO):
     d["k"] = rs.k
     d["route"] = route
     return d
+
+
+# --------------------------------------------------------------------------- proposal network
+
+class Mlp:
+    """Owns a ba_mlp handle."""
+
+    def __init__(self, handle, dims, max_batch, precision):
+        self.handle, self.dims, self.max_batch, self.precision = handle, dims, max_batch, precision
+        n = _i64()
+        _check("ba_mlp_num_params", lib().ba_mlp_num_params(handle, C.byref(n)))
+        self.n_params = n.value
+
+    def close(self):
+        if self.handle:
+            _check("ba_mlp_destroy", lib().ba_mlp_destroy(self.handle))
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ba_pack_covariance(n_elem, n_trials, R, X, stream=None):
+    _check("ba_pack_covariance", lib().ba_pack_covariance(
+        n_elem, n_trials, _dev(R, "c64", n_trials * n_elem * n_elem, "R"),
+        _dev(X, "f32", n_trials * n_elem * n_elem, "X"), _stream(stream)))
+
+
+def ba_mlp_create(d_in, d_hidden, n_hidden, d_out, max_batch, precision=BA_PREC_BF16, seed=0) -> Mlp:
+    h = C.c_void_p()
+    _check("ba_mlp_create", lib().ba_mlp_create(C.byref(h), d_in, d_hidden, n_hidden, d_out, max_batch,
+                                                precision, seed))
+    return Mlp(h, [d_in] + [d_hidden] * n_hidden + [d_out], max_batch, precision)
+
+
+def ba_mlp_get_weights(net: Mlp) -> np.ndarray:
+    w = np.empty(net.n_params, np.float32)
+    _check("ba_mlp_get_weights", lib().ba_mlp_get_weights(net.handle, w.ctypes.data_as(_vp), net.n_params))
+    return w
+
+
+def ba_mlp_set_weights(net: Mlp, w):
+    w = np.ascontiguousarray(np.asarray(w, np.float32))
+    if w.size != net.n_params:
+        raise ValueError("need %d parameters" % net.n_params)
+    _check("ba_mlp_set_weights", lib().ba_mlp_set_weights(net.handle, w.ctypes.data_as(_vp), net.n_params))
+
+
+def ba_mlp_forward(net: Mlp, B, X, Y, stream=None):
+    _check("ba_mlp_forward", lib().ba_mlp_forward(
+        net.handle, B, _dev(X, "f32", B * net.dims[0], "X"), _dev(Y, "f32", B * net.dims[-1], "Y"),
+        _stream(stream)))
+
+
+def ba_mlp_gradients(net: Mlp, B, X, T, mask, grads, loss=None, stream=None):
+    _check("ba_mlp_gradients", lib().ba_mlp_gradients(
+        net.handle, B, _dev(X, "f32", B * net.dims[0], "X"), _dev(T, "f32", B * net.dims[-1], "T"),
+        _dev(mask, "f32", B * net.dims[-1], "mask", optional=True),
+        _dev(grads, "f32", net.n_params, "grads"), _dev(loss, "f32", 1, "loss", optional=True),
+        _stream(stream)))
+
+
+def ba_mlp_train_step(net: Mlp, B, X, T, mask, lr, loss=None, stream=None):
+    _check("ba_mlp_train_step", lib().ba_mlp_train_step(
+        net.handle, B, _dev(X, "f32", B * net.dims[0], "X"), _dev(T, "f32", B * net.dims[-1], "T"),
+        _dev(mask, "f32", B * net.dims[-1], "mask", optional=True), float(lr),
+        _dev(loss, "f32", 1, "loss", optional=True), _stream(stream)))
+
+
+def mlp_params_to_list(w, dims):
+    """Flat parameter vector -> [(W [out][in], b [out])] (the oracle's layout)."""
+    out, o = [], 0
+    for i in range(len(dims) - 1):
+        n_w = dims[i + 1] * dims[i]
+        W = np.asarray(w[o:o + n_w]).reshape(dims[i + 1], dims[i])
+        o += n_w
+        b = np.asarray(w[o:o + dims[i + 1]])
+        o += dims[i + 1]
+        out.append((W, b))
+    return out
+
+
+def mlp_list_to_params(params):
+    return np.concatenate([np.concatenate([W.reshape(-1), b.reshape(-1)]) for W, b in params])
+
+
+def ba_mlp_dims(net: Mlp):
+    a, b = _i32(), _i32()
+    _check("ba_mlp_dims", lib().ba_mlp_dims(net.handle, C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+def ba_propose_workspace_size(plan: Plan, n_trials, d_out, k) -> int:
+    b = _sz()
+    _check("ba_propose_workspace_size", lib().ba_propose_workspace_size(plan.handle, n_trials, d_out, k,
+                                                                        C.byref(b)))
+    return b.value
+
+
+def ba_propose_refine(plan: Plan, net: Mlp, n_trials, R, k, half_window, tau, idx, val, refined,
+                      fell_back, workspace, stream=None) -> int:
+    """Returns the number of trials that fell back to the full grid."""
+    M = plan.M
+    need = ba_propose_workspace_size(plan, n_trials, net.dims[-1], k)
+    ws, nbytes = _workspace(workspace, need)
+    nf = _i32()
+    _check("ba_propose_refine", lib().ba_propose_refine(
+        plan.handle, net.handle, n_trials, _dev(R, "c64", n_trials * M * M, "R"), k, half_window,
+        float(tau), _dev(idx, "i32", n_trials * k, "idx"), _dev(val, "f32", n_trials * k, "val"),
+        _dev(refined, "f64", n_trials * k, "refined"), _dev(fell_back, "u8", n_trials, "fell_back"),
+        C.byref(nf), ws, nbytes, _stream(stream)))
+    return nf.value
 

@@ -74,8 +74,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
         const float* br = &Bs[wn * 32 + i * 16 + (lane & 15)][8 * (lane >> 4)];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          af[i][e] = __float2bfloat16(ar[e]);
-          bf[i][e] = __float2bfloat16(br[e]);
+          af[i][e] = static_cast<__bf16>(ar[e]);  // exact: staged values are already BF16
+          bf[i][e] = static_cast<__bf16>(br[e]);
         }
       }
 #pragma unroll
@@ -185,8 +185,18 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float
 }
 
 // packed covariance: [diag re (M)] [strict upper re (M(M-1)/2)] [strict upper im], x M / tr R
-__global__ __launch_bounds__(256) void k_pack(const float2* __restrict__ R, float* __restrict__ X, int M,
-                                              const int2* __restrict__ upper) {
+// strict-upper index u (row-major) -> (m, n): row m starts at m (2M - m - 1) / 2
+__device__ __forceinline__ int2 upper_mn(int u, int M) {
+  const double a = 2.0 * M - 1.0;
+  int m = int((a - sqrt(a * a - 8.0 * u)) * 0.5);
+  m = max(0, min(m, M - 2));
+  while (m > 0 && m * (2 * M - m - 1) / 2 > u) --m;
+  while ((m + 1) * (2 * M - m - 2) / 2 <= u) ++m;
+  const int start = m * (2 * M - m - 1) / 2;
+  return make_int2(m, m + 1 + (u - start));
+}
+
+__global__ __launch_bounds__(256) void k_pack(const float2* __restrict__ R, float* __restrict__ X, int M) {
   const int64_t b = blockIdx.x;
   const float2* Rb = R + b * int64_t(M) * M;
   __shared__ float red[4];
@@ -205,10 +215,10 @@ __global__ __launch_bounds__(256) void k_pack(const float2* __restrict__ R, floa
     if (e < M) {
       x = Rb[e * M + e].x;
     } else if (e < M + nu) {
-      const int2 mn = upper[e - M];
+      const int2 mn = upper_mn(e - M, M);
       x = Rb[mn.x * M + mn.y].x;
     } else {
-      const int2 mn = upper[e - M - nu];
+      const int2 mn = upper_mn(e - M - nu, M);
       x = Rb[mn.x * M + mn.y].y;
     }
     Xb[e] = x * s;
@@ -244,8 +254,8 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, 
   return hipGetLastError();
 }
 
-hipError_t launch_pack(const float2* R, float* X, int M, int B, const int2* upper, hipStream_t s) {
-  hipLaunchKernelGGL(k_pack, dim3(unsigned(B)), dim3(256), 0, s, R, X, M, upper);
+hipError_t launch_pack(const float2* R, float* X, int M, int B, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack, dim3(unsigned(B)), dim3(256), 0, s, R, X, M);
   return hipGetLastError();
 }
 

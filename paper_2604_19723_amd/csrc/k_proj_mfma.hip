@@ -20,35 +20,10 @@
 //    same LDS tile, reduced across the 4 row-groups of a wave by two lane
 //    shuffles and across waves through LDS, then scaled by 1/M^2.
 // Element counts up to 64 are padded to MP in {8, 16, 32, 64} with zero rows.
-#include "ba_internal.h"
+#include "proj_common.h"
 
 namespace ba {
 namespace {
-
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-
-template <int MP>
-struct QCfg {
-  static constexpr int K = 2 * MP;                 // GEMM depth = rows of Q
-  static constexpr int KS = K / 4;                 // MFMA k-steps
-  static constexpr int RBLK = K / 16;              // 16-row blocks of Q
-  static constexpr int WR = RBLK >= 8 ? 4 : (RBLK >= 4 ? 2 : 1);  // waves along rows
-  static constexpr int RB = RBLK / WR;             // row blocks per wave
-  static constexpr int WC = 4 / WR;                // waves along columns
-  static constexpr int BLK = K * 16;               // floats per 16-column block
-  static constexpr int NB = 8192 / BLK;            // blocks per 32 KB chunk
-  static constexpr int CH4 = 8192 / 4;             // float4 per chunk
-  static constexpr int F4 = CH4 / 256;             // float4 per thread per chunk
-};
-
-__device__ __forceinline__ float qval(const float2* __restrict__ Rb, int M, int MP, int i, int k) {
-  const bool iim = i >= MP, kim = k >= MP;
-  const int ir = iim ? i - MP : i, kr = kim ? k - MP : k;
-  if (ir >= M || kr >= M) return 0.f;
-  const float2 r = Rb[ir * M + kr];
-  // Q = [[Rr, -Ri], [Ri, Rr]]
-  return (iim == kim) ? r.x : (iim ? r.y : -r.y);
-}
 
 template <int MP>
 __global__ __launch_bounds__(256, 2) void k_proj_q(const float2* __restrict__ R,
@@ -66,14 +41,8 @@ __global__ __launch_bounds__(256, 2) void k_proj_q(const float2* __restrict__ R,
   const int c1 = min(c0 + chunks_per_wg, nchunk);
   if (c0 >= c1) return;  // uniform across the workgroup
 
-  // A operand: rows i = wr*RB*16 + rb*16 + lane%16, k = 4s + lane/16
   float a[C::RB][C::KS];
-  const float2* Rb = R + b * int64_t(M) * M;
-#pragma unroll
-  for (int rb = 0; rb < C::RB; ++rb)
-#pragma unroll
-    for (int s = 0; s < C::KS; ++s)
-      a[rb][s] = qval(Rb, M, MP, wr * C::RB * 16 + rb * 16 + (lane & 15), 4 * s + (lane >> 4));
+  load_q_fragments<MP>(R + b * int64_t(M) * M, M, wr, lane, a);
 
   float4 pre[C::F4];
 #pragma unroll
@@ -92,34 +61,7 @@ __global__ __launch_bounds__(256, 2) void k_proj_q(const float2* __restrict__ R,
     }
     const float* sx = reinterpret_cast<const float*>(sX[buf]);
     for (int jb = wc; jb < C::NB; jb += C::WC) {
-      floatx4 acc[C::RB];
-#pragma unroll
-      for (int rb = 0; rb < C::RB; ++rb) acc[rb] = floatx4{0.f, 0.f, 0.f, 0.f};
-      const float4* bx = sX[buf] + jb * (C::BLK / 4);
-#pragma unroll
-      for (int s4 = 0; s4 < C::KS / 4; ++s4) {
-        const float4 bv = bx[s4 * 64 + lane];
-#pragma unroll
-        for (int rb = 0; rb < C::RB; ++rb) {
-          acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 0], bv.x, acc[rb], 0, 0, 0);
-          acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 1], bv.y, acc[rb], 0, 0, 0);
-          acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 2], bv.z, acc[rb], 0, 0, 0);
-          acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 3], bv.w, acc[rb], 0, 0, 0);
-        }
-      }
-      // epilogue: acc[rb][r] = (Q X)[i][g0 + lane%16] with i = row(rb) + 4*(lane/16) + r
-      float part = 0.f;
-#pragma unroll
-      for (int rb = 0; rb < C::RB; ++rb)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = wr * C::RB * 16 + rb * 16 + 4 * (lane >> 4) + r;
-          const int s = i >> 2;
-          const float xv = sx[jb * C::BLK + ((s >> 2) * 64 + r * 16 + (lane & 15)) * 4 + (s & 3)];
-          part += xv * acc[rb][r];
-        }
-      part += __shfl_xor(part, 16, 64);
-      part += __shfl_xor(part, 32, 64);
+      const float part = block_quadratic<MP>(a, sX[buf] + jb * (C::BLK / 4), sx + jb * C::BLK, wr, lane);
       if (C::WR == 1) {
         const int64_t g = int64_t(c) * C::NB * 16 + jb * 16 + lane;
         if (lane < 16 && g < G) P[b * G + g] = part * invM2;
