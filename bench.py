@@ -148,6 +148,60 @@ def bench_ragged(args, workers):
     return 0
 
 
+def bench_learned(args, workers):
+    """Learned proposal vs plain FP32 grid search on the 64-element ULA: train
+    on method-labelled trials, pick the fallback threshold on a validation set
+    (smallest tau whose RMSE equals the plain RMSE), report the test set."""
+    from paper_2604_19723_amd import workload as wl
+    n_test = args.trials
+    t = time.perf_counter()
+    val = wl.config5(2000, seed_offset=1, dtype=np.complex64, workers=workers)
+    test = wl.config5(n_test, seed_offset=2, snr_db=wl.C2_SNRS, dtype=np.complex64, workers=workers)
+    log("generated validation/test sets in %.1f s" % (time.perf_counter() - t))
+    import torch
+    from paper_2604_19723_amd import bartlett as bb
+    from paper_2604_19723_amd import learned as L
+    dev = torch.device("cuda:0")
+    plan = bb.plan_for(test)
+    t = time.perf_counter()
+    X, U, Mk = L.make_training_set(plan, args.train_trials, 1234, dev, log=log)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t
+    net = bb.ba_mlp_create(4096, 512, 3, 4, 1024, bb.BA_PREC_BF16, 99)
+    t = time.perf_counter()
+    hist = L.train(net, X, U, Mk, args.epochs, 1024, 1e-3, 7, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t
+    del X, U, Mk
+    taus = [0.0, 0.02, 0.05, 0.08, 0.1, 0.12, 0.15, 0.2]
+    ev = L.evaluate(plan, net, val, taus, dev)
+    chosen = next((r for r in ev["learned"] if L.equal_rmse(r["rmse"], ev["plain"]["rmse"])), ev["learned"][-1])
+    log("validation: plain %s; chosen tau %.2f (fallback %.3f, rmse %s)" % (
+        ev["plain"]["rmse"], chosen["tau"], chosen["fallback"], chosen["rmse"]))
+    et = L.evaluate(plan, net, test, [chosen["tau"]], dev)
+    lt, pt = et["learned"][0], et["plain"]
+    line = {
+        "metric": "MC trials/sec and grid-points*trials/sec at fixed RMSE; % MFMA/HBM peak",
+        "value": lt["trials_per_s"], "unit": "trials/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": lt["seconds"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16 network + f32 windows",
+        "data": "synthetic (seeded signal model; training stream drawn on the device)",
+        "config": {"workload": test.name + "_learned", "test_trials": n_test,
+                   "train_trials": args.train_trials, "epochs": args.epochs, "tau": chosen["tau"],
+                   "half_window": 50},
+        "roofline": None, "cpu_baseline": None,
+        "plain_trials_per_s": pt["trials_per_s"], "speedup_vs_plain": lt["trials_per_s"] / pt["trials_per_s"],
+        "rmse_deg": lt["rmse"], "plain_rmse_deg": pt["rmse"],
+        "equal_rmse": L.equal_rmse(lt["rmse"], pt["rmse"]), "fallback_rate": lt["fallback"],
+        "train_seconds": t_train, "data_seconds": t_data, "final_loss": hist[-1] if hist else None,
+        "validation": ev,
+    }
+    print(json.dumps(line), flush=True)
+    net.close()
+    plan.close()
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -155,11 +209,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--trials", type=int, default=10000)
     ap.add_argument("--precision", default="f32", choices=sorted(PEAK))
-    ap.add_argument("--workload", default="ula64", choices=["ula64", "ura256", "ragged"],
+    ap.add_argument("--workload", default="ula64", choices=["ula64", "ura256", "ragged", "learned"],
                     help="ula64: 64-element ULA, 7201-point grid (default); ura256: 16x16 URA, "
                          "361x181 az/el grid; ragged: 50 000 uneven trials (M 8..128, T 16..2048) "
                          "in one persistent launch under a HIP graph")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--train-trials", type=int, default=1000000)
+    ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -174,6 +230,8 @@ def main():
     workers = min(16, len(os.sched_getaffinity(0)))
     if args.workload == "ragged":
         return bench_ragged(args, workers)
+    if args.workload == "learned":
+        return bench_learned(args, workers)
     t = time.perf_counter()
     if args.workload == "ula64":
         ts = wl.config2(args.trials, dtype=np.complex64, workers=workers)   # before the GPU is touched

@@ -388,25 +388,34 @@ def config4(n_trials: int = 50000, first_trial: int = 0, n_grid: int = 3601,
                      snr_db=snr, grid=ula_grid(n_grid), name="ragged_m8-128_t16-2048_g3601")
 
 
-def config5(n_trials: int, first_trial: int = 0, seed_offset: int = 0, K: int = 4,
-            snr_db: Optional[Sequence[float]] = None) -> TrialSet:
-    """Learned-proposal workload: 64-element ULA, K sources, 256 snapshots, SNR
-    ~ U[-10, 20] dB per trial (or cycled over ``snr_db``), 7201-point grid.
-    ``seed_offset`` separates the training, validation and test streams."""
-    seed = SEED_BASE + 5 + (seed_offset << 8)
+def _c5_chunk(args):
+    (i0, i1, seed, K, snr_db, dtype) = args
     pos = ula_positions(64)
-    Y = np.empty((n_trials, 256, 64), dtype=np.complex128)
-    truth = np.empty((n_trials, K))
-    snr = np.empty(n_trials)
-    sig = np.empty(n_trials)
-    for b in range(n_trials):
-        i = first_trial + b
+    n = i1 - i0
+    Y = np.empty((n, 256, 64), dtype=dtype)
+    truth = np.empty((n, K))
+    snr = np.empty(n)
+    sig = np.empty(n)
+    for b in range(n):
+        i = i0 + b
         rng = trial_rng(seed, i)
         snr[b] = rng.uniform(-10.0, 20.0) if snr_db is None else snr_db[i % len(snr_db)]
         th = _draw_angles_1d(rng, K, -60.0, 60.0, 5.0)
         sig[b] = noise_variance(snr[b], K, "per_source")
         Y[b] = _snapshots(rng, response(pos, ula_dirs(th)), 256, sig[b])
         truth[b] = th
-    return TrialSet(Y=Y, pos_wl=pos, grid_kind=GRID_ULA_DEG, grid=ula_grid(7201),
-                    grid_shape=(7201, 1), wrap0=0, K=K, truth=truth, snr_db=snr, sigma2=sig,
+    return Y, truth, snr, sig
+
+
+def config5(n_trials: int, first_trial: int = 0, seed_offset: int = 0, K: int = 4,
+            snr_db: Optional[Sequence[float]] = None, dtype=np.complex128, workers: int = 1) -> TrialSet:
+    """Learned-proposal workload: 64-element ULA, K sources, 256 snapshots, SNR
+    ~ U[-10, 20] dB per trial (or cycled over ``snr_db``), 7201-point grid.
+    ``seed_offset`` separates the training, validation and test streams."""
+    seed = SEED_BASE + 5 + (seed_offset << 8)
+    snrs = None if snr_db is None else tuple(float(x) for x in snr_db)
+    parts = _parallel_chunks(_c5_chunk, n_trials, first_trial, (seed, K, snrs, dtype), workers)
+    cat = lambda k: np.concatenate([p[k] for p in parts])
+    return TrialSet(Y=cat(0), pos_wl=ula_positions(64), grid_kind=GRID_ULA_DEG, grid=ula_grid(7201),
+                    grid_shape=(7201, 1), wrap0=0, K=K, truth=cat(1), snr_db=cat(2), sigma2=cat(3),
                     name="learned_ula64_k4_t256_g7201")
