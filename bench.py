@@ -215,6 +215,9 @@ def main():
                          "in one persistent launch under a HIP graph")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--train-trials", type=int, default=1000000)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after timing, copy a buffer of this many MiB once (a plain copy kernel "
+                         "of known size, to scale hardware byte counters)")
     ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -298,6 +301,15 @@ def main():
         Pr = ob.spectrum(ob.covariance(ts.Y[b].astype(np.complex128)), A)
         errs.append(np.max(np.abs(P_h[b] - Pr)) / np.max(Pr))
 
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib * 1024 * 256
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: %d MiB read + %d MiB written" % (args.calib_copy_mib, args.calib_copy_mib))
+        del src, dst
     cpu = None if args.no_cpu_baseline else cpu_baseline(ts, K, args.cpu_seconds)
     value = B * args.steps / dt
     line = {

@@ -126,6 +126,139 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       }
 }
 
+// ---------------------------------------------------------------- BF16 GEMM, 128 x 128 tiles
+//
+// 4 waves, each a 64 x 64 sub-tile (4 x 4 MFMA blocks). Operand tiles are
+// stored in LDS as BF16, k-contiguous, rows padded to 40 elements (80 bytes):
+// a fragment (8 consecutive k of one row) is one conflict-free 16-byte read.
+// Global loads go 4 elements at a time along whichever dimension is
+// contiguous and are issued one k-tile ahead (double buffering through
+// registers).
+constexpr int BT = 128, BK = 32, BLD = 40;
+
+__device__ __forceinline__ void load4(const float* __restrict__ p, int64_t so, int64_t sc, int r, int c,
+                                      int nr, int nc, float (&v)[4]) {
+  // 4 consecutive elements along the contiguous index c (stride sc == 1 when vectorisable)
+  const bool inr = r < nr;
+  if (inr && sc == 1 && c + 3 < nc) {
+    const float* q = p + int64_t(r) * so + c;
+    if ((reinterpret_cast<uintptr_t>(q) & 15) == 0) {
+      const float4 x = *reinterpret_cast<const float4*>(q);
+      v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+      return;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) v[e] = (inr && c + e < nc) ? p[int64_t(r) * so + int64_t(c + e) * sc] : 0.f;
+}
+
+// tile loader: operand X(i, k) = P[i si + k sk] for i in [i0, i0+128), k in [k0, k0+32);
+// each of 256 threads loads 4 groups of 4 elements
+struct TileLoad {
+  float v[4][4];
+  __device__ void load(const float* P, int64_t si, int64_t sk, int i0, int k0, int ni, int nk, int tid) {
+    if (sk == 1) {  // k contiguous: groups of 4 k
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int g = j * 256 + tid, i = g >> 3, k4 = (g & 7) * 4;
+        load4(P, si, 1, i0 + i, k0 + k4, ni, nk, v[j]);
+      }
+    } else {        // i contiguous: groups of 4 i
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int g = j * 256 + tid, k = g >> 5, i4 = (g & 31) * 4;
+        load4(P, sk, si, k0 + k, i0 + i4, nk, ni, v[j]);
+      }
+    }
+  }
+  __device__ void store(__bf16 (*S)[BLD], bool kcontig, int tid) const {
+    if (kcontig) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int g = j * 256 + tid, i = g >> 3, k4 = (g & 7) * 4;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) S[i][k4 + e] = static_cast<__bf16>(v[j][e]);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int g = j * 256 + tid, k = g >> 5, i4 = (g & 31) * 4;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) S[i4 + e][k] = static_cast<__bf16>(v[j][e]);
+      }
+    }
+  }
+};
+
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) __bf16 As[2][BT][BLD];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][BT][BLD];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int m0 = blockIdx.y * BT, n0 = blockIdx.x * BT;
+  const bool a_k = g.sak == 1, b_k = g.sbk == 1;
+  floatx4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  TileLoad la, lb;
+  // B(k, n) = B[k sbk + n sbn]: as an operand indexed (n, k) it has si = sbn, sk = sbk
+  la.load(g.A, g.sam, g.sak, m0, 0, g.M, g.K, tid);
+  lb.load(g.B, g.sbn, g.sbk, n0, 0, g.N, g.K, tid);
+  la.store(As[0], a_k, tid);
+  lb.store(Bs[0], b_k, tid);
+  __syncthreads();
+  const int nk = (g.K + BK - 1) / BK;
+  for (int t = 0; t < nk; ++t) {
+    const int buf = t & 1;
+    const bool more = t + 1 < nk;
+    if (more) {
+      la.load(g.A, g.sam, g.sak, m0, (t + 1) * BK, g.M, g.K, tid);
+      lb.load(g.B, g.sbn, g.sbk, n0, (t + 1) * BK, g.N, g.K, tid);
+    }
+    bf16x8 af[4], bfr[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      af[i] = *reinterpret_cast<const bf16x8*>(&As[buf][wm * 64 + i * 16 + (lane & 15)][8 * (lane >> 4)]);
+      bfr[i] = *reinterpret_cast<const bf16x8*>(&Bs[buf][wn * 64 + i * 16 + (lane & 15)][8 * (lane >> 4)]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    if (more) {
+      la.store(As[buf ^ 1], a_k, tid);
+      lb.store(Bs[buf ^ 1], b_k, tid);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
+        const int n = n0 + wn * 64 + j * 16 + (lane & 15);
+        if (m >= g.M || n >= g.N) continue;
+        float v = acc[i][j][r];
+        const int64_t o = int64_t(m) * g.ldc + n;
+        switch (g.mode) {
+          case kGemmHidden: {
+            v += g.bias[n];
+            g.Z[o] = v;
+            g.C[o] = gelu(v);
+            break;
+          }
+          case kGemmBias: g.C[o] = v + g.bias[n]; break;
+          case kGemmGeluGrad: g.C[o] = v * gelu_grad(g.Z[o]); break;
+          default: g.C[o] = v; break;
+        }
+      }
+}
+
 // db[n] = sum_m dZ[m][n], fixed summation order
 __global__ __launch_bounds__(256) void k_colsum(const float* __restrict__ dZ, float* __restrict__ db, int M, int N) {
   const int n = blockIdx.x * 256 + threadIdx.x;
@@ -229,9 +362,10 @@ __global__ __launch_bounds__(256) void k_pack(const float2* __restrict__ R, floa
 
 hipError_t launch_gemm(const GemmArgs& g, int prec, hipStream_t s) {
   const dim3 grid(unsigned((g.N + TN - 1) / TN), unsigned((g.M + TM - 1) / TM));
-  if (prec == BA_PREC_BF16)
-    hipLaunchKernelGGL(k_gemm<BA_PREC_BF16>, grid, dim3(256), 0, s, g);
-  else
+  if (prec == BA_PREC_BF16) {
+    const dim3 gb(unsigned((g.N + BT - 1) / BT), unsigned((g.M + BT - 1) / BT));
+    hipLaunchKernelGGL(k_gemm_bf16, gb, dim3(256), 0, s, g);
+  } else
     hipLaunchKernelGGL(k_gemm<BA_PREC_F32>, grid, dim3(256), 0, s, g);
   return hipGetLastError();
 }
