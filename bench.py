@@ -155,7 +155,8 @@ def bench_learned(args, workers):
     from paper_2604_19723_amd import workload as wl
     n_test = args.trials
     t = time.perf_counter()
-    val = wl.config5(2000, seed_offset=1, dtype=np.complex64, workers=workers)
+    # validation and test sets share the SNR sweep of the plain-method workload
+    val = wl.config5(4000, seed_offset=1, snr_db=wl.C2_SNRS, dtype=np.complex64, workers=workers)
     test = wl.config5(n_test, seed_offset=2, snr_db=wl.C2_SNRS, dtype=np.complex64, workers=workers)
     log("generated validation/test sets in %.1f s" % (time.perf_counter() - t))
     import torch
@@ -173,7 +174,7 @@ def bench_learned(args, workers):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t
     del X, U, Mk
-    taus = [0.0, 0.02, 0.05, 0.08, 0.1, 0.12, 0.15, 0.2]
+    taus = [0.0, 0.02, 0.04, 0.06, 0.08, 0.1, 0.12, 0.14, 0.16, 0.18, 0.2, 0.22, 0.25]
     ev = L.evaluate(plan, net, val, taus, dev)
     chosen = next((r for r in ev["learned"] if L.equal_rmse(r["rmse"], ev["plain"]["rmse"])), ev["learned"][-1])
     log("validation: plain %s; chosen tau %.2f (fallback %.3f, rmse %s)" % (

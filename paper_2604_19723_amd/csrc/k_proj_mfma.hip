@@ -14,8 +14,9 @@
 //    registers (each wave owns RB row blocks of 16 rows, all K);
 //  * the steering table is stored in HBM already in B-fragment order (16
 //    columns per block, 4 k-steps per lane per 16-byte word), so one chunk of
-//    32 KB is a straight coalesced copy into LDS and every fragment read is a
-//    conflict-free ds_read_b128; chunks are double-buffered through registers;
+//    32 KB is a straight copy into LDS, done by the gfx950 LDS DMA
+//    (global_load_lds_dwordx4, no registers involved) one chunk ahead, and
+//    every fragment read is a conflict-free ds_read_b128;
 //  * epilogue: the accumulator tile is multiplied by the matching rows of the
 //    same LDS tile, reduced across the 4 row-groups of a wave by two lane
 //    shuffles and across waves through LDS, then scaled by 1/M^2.
@@ -31,7 +32,7 @@ __global__ __launch_bounds__(256, 2) void k_proj_q(const float2* __restrict__ R,
                                                    float* __restrict__ P, int M, int64_t G,
                                                    int nchunk, int chunks_per_wg, int nsplit) {
   using C = QCfg<MP>;
-  __shared__ float4 sX[2][C::CH4];
+  extern __shared__ __attribute__((aligned(16))) float4 sX[];   // [2][CH4], dynamic: filled by LDS DMA
   __shared__ float red[2][C::WR][C::NB * 16];
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -41,27 +42,30 @@ __global__ __launch_bounds__(256, 2) void k_proj_q(const float2* __restrict__ R,
   const int c1 = min(c0 + chunks_per_wg, nchunk);
   if (c0 >= c1) return;  // uniform across the workgroup
 
+  // each wave copies its quarter of a chunk, 64 lanes x 16 bytes per DMA
+  auto fetch = [&](int c, int buf) {
+#pragma unroll
+    for (int f = 0; f < C::CH4 / 4 / 64; ++f) {
+      const int o = wave * (C::CH4 / 4) + f * 64;
+      lds_dma16(Xg + int64_t(c) * C::CH4 + o + lane, sX + buf * C::CH4 + o);
+    }
+  };
+
   float a[C::RB][C::KS];
   load_q_fragments<MP>(R + b * int64_t(M) * M, M, wr, lane, a);
-
-  float4 pre[C::F4];
-#pragma unroll
-  for (int f = 0; f < C::F4; ++f) pre[f] = Xg[int64_t(c0) * C::CH4 + f * 256 + threadIdx.x];
-#pragma unroll
-  for (int f = 0; f < C::F4; ++f) sX[0][f * 256 + threadIdx.x] = pre[f];
+  fetch(c0, 0);
+  lds_dma_wait();
   __syncthreads();
 
   const float invM2 = 1.0f / float(M * M);
   for (int c = c0; c < c1; ++c) {
     const int buf = (c - c0) & 1;
     const bool more = c + 1 < c1;
-    if (more) {
-#pragma unroll
-      for (int f = 0; f < C::F4; ++f) pre[f] = Xg[int64_t(c + 1) * C::CH4 + f * 256 + threadIdx.x];
-    }
-    const float* sx = reinterpret_cast<const float*>(sX[buf]);
+    if (more) fetch(c + 1, buf ^ 1);  // the other buffer was last read before the previous barrier
+    const float4* sxb = sX + buf * C::CH4;
+    const float* sx = reinterpret_cast<const float*>(sxb);
     for (int jb = wc; jb < C::NB; jb += C::WC) {
-      const float part = block_quadratic<MP>(a, sX[buf] + jb * (C::BLK / 4), sx + jb * C::BLK, wr, lane);
+      const float part = block_quadratic<MP>(a, sxb + jb * (C::BLK / 4), sx + jb * C::BLK, wr, lane);
       if (C::WR == 1) {
         const int64_t g = int64_t(c) * C::NB * 16 + jb * 16 + lane;
         if (lane < 16 && g < G) P[b * G + g] = part * invM2;
@@ -69,10 +73,7 @@ __global__ __launch_bounds__(256, 2) void k_proj_q(const float2* __restrict__ R,
         red[buf][wr][jb * 16 + lane] = part;
       }
     }
-    if (more) {
-#pragma unroll
-      for (int f = 0; f < C::F4; ++f) sX[buf ^ 1][f * 256 + threadIdx.x] = pre[f];
-    }
+    lds_dma_wait();
     __syncthreads();
     if (C::WR > 1) {
       for (int t = threadIdx.x; t < C::NB * 16; t += 256) {
@@ -97,7 +98,7 @@ hipError_t launch_q(const Plan& p, int B, const float2* R, float* P, hipStream_t
   nsplit = (nchunk + per - 1) / per;
   const int64_t nblk = int64_t(B) * nsplit;
   if (nblk > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_proj_q<MP>, dim3(unsigned(nblk)), dim3(256), 0, s, R,
+  hipLaunchKernelGGL(k_proj_q<MP>, dim3(unsigned(nblk)), dim3(256), 2 * C::CH4 * sizeof(float4), s, R,
                      reinterpret_cast<const float4*>(p.d_X), P, p.M, p.G, nchunk, per, nsplit);
   return hipGetLastError();
 }

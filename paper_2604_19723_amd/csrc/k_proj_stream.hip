@@ -7,10 +7,11 @@
 // BF16 hi/lo split (hi = bf16(q), lo = bf16(q - hi), round to nearest even)
 // for v_mfma_f32_16x16x32_bf16.
 //
-// Stage 2, k_proj_s: one workgroup of 8 waves computes a tile of 128 grid
-// columns of one trial over all 2*Mp rows. Each wave owns 2*Mp/8 rows and
-// streams its own A fragments straight from L2; the steering fragments of the
-// tile go through LDS in chunks of 32 k values, double-buffered. The
+// Stage 2, k_proj_s: one workgroup of 8 waves computes a
+// tile of 128 grid columns of one trial over all 2*Mp rows. Each wave owns
+// 2*Mp/waves rows and streams its own A fragments straight from L2, one
+// chunk ahead; the steering fragments of the tile go through LDS in chunks
+// of 32 k values, double-buffered by the LDS DMA. The
 // accumulators never leave the registers: the epilogue multiplies them by the
 // FP32 steering rows of the same tile and reduces over rows (lane shuffles,
 // then LDS across waves). Tiles are ordered so that each XCD walks through
@@ -19,17 +20,19 @@
 //
 // BF16X3: Q X ~= Qh Xh + Qh Xl + Ql Xh (the lo*lo term dropped), FP32 accumulate.
 // BF16 (one pass, Qh Xh) exists as a precision ablation only.
-#include "ba_internal.h"
+#include "proj_common.h"
 
 namespace ba {
 namespace {
 
-typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short ushort8 __attribute__((ext_vector_type(8)));
 
 constexpr int kCB = 8;     // 16-column blocks per tile (128 columns)
-constexpr int kWaves = 8;  // waves per workgroup
+
+// waves per workgroup (2 per SIMD, up to 256 registers each)
+template <int PREC>
+constexpr int waves_for() { return 8; }
 
 __device__ __forceinline__ unsigned short bf16_rne(float x) {
   unsigned u = __float_as_uint(x);
@@ -87,11 +90,12 @@ __global__ __launch_bounds__(256) void k_qprep(const float2* __restrict__ R, voi
 }
 
 template <int MP, int PREC>
-__global__ __launch_bounds__(512) void k_proj_s(const void* __restrict__ Qin,
+__global__ __launch_bounds__(64 * waves_for<PREC>(), 1) void k_proj_s(const void* __restrict__ Qin,
                                                 const float4* __restrict__ Xf,   // FP32 table (fragment order)
                                                 const uint4* __restrict__ Xb,    // BF16 hi/lo table
                                                 float* __restrict__ P, int M, int64_t G, int ntile,
                                                 int64_t nlogical) {
+  constexpr int kWaves = waves_for<PREC>();
   constexpr int K = 2 * MP;
   constexpr int NKC = K / 32;            // k-chunks
   constexpr int NRB = K / 16;            // row blocks
@@ -99,7 +103,7 @@ __global__ __launch_bounds__(512) void k_proj_s(const void* __restrict__ Qin,
   constexpr int CHUNK16 = kCB * 64 * 2;  // 16-byte words of B per chunk (16 KB)
   static_assert(RBW >= 1, "rows per wave");
 
-  __shared__ uint4 sB[2][CHUNK16];
+  extern __shared__ __attribute__((aligned(16))) uint4 sBd[];  // [2][CHUNK16], filled by LDS DMA
   __shared__ float red[kWaves][kCB * 16];
 
   // XCD-aware order: hardware places workgroup i on XCD i % 8, so logical tile
@@ -120,49 +124,40 @@ __global__ __launch_bounds__(512) void k_proj_s(const void* __restrict__ Qin,
 #pragma unroll
     for (int c = 0; c < kCB; ++c) acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  // B source for chunk kc: column block (tile*8 + cb), 2 KB per (block, chunk)
-  auto load_b = [&](int kc, uint4 (&pre)[2]) {
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int w = h * 512 + threadIdx.x;       // 0..1023 words of 16 B
-      const int cb = w >> 7, off = w & 127;      // 128 words per block-chunk
-      const int64_t blk = int64_t(tile) * kCB + cb;
-      if (PREC == BA_PREC_F32)
-        pre[h] = reinterpret_cast<const uint4*>(Xf)[(blk * NKC + kc) * 128 + off];
-      else
-        pre[h] = Xb[(blk * NKC + kc) * 128 + off];
-    }
-  };
-  auto store_b = [&](int buf, const uint4 (&pre)[2]) {
-#pragma unroll
-    for (int h = 0; h < 2; ++h) sB[buf][h * 512 + threadIdx.x] = pre[h];
-  };
+  // B chunk kc: 8 column blocks x 2 KB = 16 DMAs of 64 lanes x 16 bytes, spread over the waves
+  const uint4* Xsrc = PREC == BA_PREC_F32 ? reinterpret_cast<const uint4*>(Xf) : Xb;
+  constexpr int DPW = 16 / kWaves;  // DMAs per wave
+#define BA_FETCH_B(kc, buf)                                                                     \
+  do {                                                                                          \
+    _Pragma("unroll") for (int d_ = 0; d_ < DPW; ++d_) {                                        \
+      const int q_ = wave * DPW + d_;                /* 0..15: block q_/2, half q_%2 */        \
+      const int64_t blk_ = int64_t(tile) * kCB + (q_ >> 1);                                     \
+      lds_dma16(Xsrc + (blk_ * NKC + (kc)) * 128 + (q_ & 1) * 64 + lane,                        \
+                sBd + (buf) * CHUNK16 + q_ * 64);                                               \
+    }                                                                                           \
+  } while (0)
 
-  uint4 preB[2];
-  load_b(0, preB);
-  store_b(0, preB);
+  BA_FETCH_B(0, 0);
 
   if (PREC == BA_PREC_F32) {
+    // A fragments of a chunk come as two halves (k-steps 0..3 and 4..7); the
+    // next chunk's half h is loaded as soon as this chunk is done with it, so
+    // each load has half a chunk of MFMA work to land in, with no extra registers
     const float4* Qw = static_cast<const float4*>(Qin) + b * (int64_t(K) * K / 4);
-    float4 a[RBW][2], an[RBW][2];
+    float4 a[RBW][2];
 #pragma unroll
     for (int r = 0; r < RBW; ++r)
 #pragma unroll
       for (int h = 0; h < 2; ++h) a[r][h] = Qw[(int64_t(0) * NRB + rb0 + r) * 128 + h * 64 + lane];
+    lds_dma_wait();
     __syncthreads();
     for (int kc = 0; kc < NKC; ++kc) {
       const int buf = kc & 1;
       const bool more = kc + 1 < NKC;
-      if (more) {
-        load_b(kc + 1, preB);
+      if (more) BA_FETCH_B(kc + 1, buf ^ 1);
+      const float4* sb = reinterpret_cast<const float4*>(sBd + buf * CHUNK16);
 #pragma unroll
-        for (int r = 0; r < RBW; ++r)
-#pragma unroll
-          for (int h = 0; h < 2; ++h) an[r][h] = Qw[(int64_t(kc + 1) * NRB + rb0 + r) * 128 + h * 64 + lane];
-      }
-      const float4* sb = reinterpret_cast<const float4*>(sB[buf]);
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
+      for (int h = 0; h < 2; ++h) {
 #pragma unroll
         for (int c = 0; c < kCB; ++c) {
           const float4 bv = sb[c * 128 + h * 64 + lane];
@@ -174,14 +169,12 @@ __global__ __launch_bounds__(512) void k_proj_s(const void* __restrict__ Qin,
             acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r][h].w, bv.w, acc[r][c], 0, 0, 0);
           }
         }
-      if (more) {
-        store_b(buf ^ 1, preB);
+        if (more) {
 #pragma unroll
-        for (int r = 0; r < RBW; ++r) {
-          a[r][0] = an[r][0];
-          a[r][1] = an[r][1];
+          for (int r = 0; r < RBW; ++r) a[r][h] = Qw[(int64_t(kc + 1) * NRB + rb0 + r) * 128 + h * 64 + lane];
         }
       }
+      lds_dma_wait();
       __syncthreads();
     }
   } else {
@@ -192,12 +185,13 @@ __global__ __launch_bounds__(512) void k_proj_s(const void* __restrict__ Qin,
       ah[r] = Qw[(int64_t(0) * NRB + rb0 + r) * 128 + lane];
       al[r] = Qw[(int64_t(0) * NRB + rb0 + r) * 128 + 64 + lane];
     }
+    lds_dma_wait();
     __syncthreads();
     for (int kc = 0; kc < NKC; ++kc) {
       const int buf = kc & 1;
       const bool more = kc + 1 < NKC;
       if (more) {
-        load_b(kc + 1, preB);
+        BA_FETCH_B(kc + 1, buf ^ 1);
 #pragma unroll
         for (int r = 0; r < RBW; ++r) {
           anh[r] = Qw[(int64_t(kc + 1) * NRB + rb0 + r) * 128 + lane];
@@ -206,8 +200,8 @@ __global__ __launch_bounds__(512) void k_proj_s(const void* __restrict__ Qin,
       }
 #pragma unroll
       for (int c = 0; c < kCB; ++c) {
-        const uint4 bh = sB[buf][c * 128 + lane];
-        const uint4 bl = sB[buf][c * 128 + 64 + lane];
+        const uint4 bh = sBd[buf * CHUNK16 + c * 128 + lane];
+        const uint4 bl = sBd[buf * CHUNK16 + c * 128 + 64 + lane];
         const bf16x8 vbh = __builtin_bit_cast(bf16x8, bh);
         const bf16x8 vbl = __builtin_bit_cast(bf16x8, bl);
 #pragma unroll
@@ -222,17 +216,18 @@ __global__ __launch_bounds__(512) void k_proj_s(const void* __restrict__ Qin,
         }
       }
       if (more) {
-        store_b(buf ^ 1, preB);
 #pragma unroll
         for (int r = 0; r < RBW; ++r) {
           ah[r] = anh[r];
           al[r] = anl[r];
         }
       }
+      lds_dma_wait();
       __syncthreads();
     }
   }
 
+#undef BA_FETCH_B
   // epilogue: rows i = 16 (rb0 + r) + 4 (lane/16) + e, column 16 c + lane%16
   float part[kCB];
 #pragma unroll
@@ -272,11 +267,12 @@ __global__ __launch_bounds__(512) void k_proj_s(const void* __restrict__ Qin,
 
 template <int MP, int PREC>
 hipError_t launch_s(const Plan& p, int B, const void* Q, float* P, hipStream_t s) {
+  constexpr int kWaves = waves_for<PREC>();
   const int ntile = int((p.Gb + kCB - 1) / kCB);  // <= Xblocks / kCB
   const int64_t nlog = int64_t(B) * ntile;
   const int64_t nphys = (nlog + 7) / 8 * 8;
   if (nphys > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_proj_s<MP, PREC>), dim3(unsigned(nphys)), dim3(512), 0, s, Q,
+  hipLaunchKernelGGL((k_proj_s<MP, PREC>), dim3(unsigned(nphys)), dim3(64 * kWaves), 2 * 1024 * sizeof(uint4), s, Q,
                      reinterpret_cast<const float4*>(p.d_X), reinterpret_cast<const uint4*>(p.d_Xb),
                      P, p.M, p.G, ntile, nlog);
   return hipGetLastError();
@@ -306,7 +302,9 @@ hipError_t launch_spectrum_stream(const Plan& p, int B, const float2* R, void* Q
     if (p.precision == BA_PREC_BF16X3) return launch_s<MPV, BA_PREC_BF16X3>(p, B, Qws, P, s); \
     return launch_s<MPV, BA_PREC_BF16>(p, B, Qws, P, s);                                   \
   }
-  BA_S(64)
+  // FP32 plans of up to 64 elements use the register-resident kernel instead
+  if (p.Mp == 64 && p.precision == BA_PREC_BF16X3) return launch_s<64, BA_PREC_BF16X3>(p, B, Qws, P, s);
+  if (p.Mp == 64 && p.precision == BA_PREC_BF16) return launch_s<64, BA_PREC_BF16>(p, B, Qws, P, s);
   BA_S(128)
   BA_S(256)
 #undef BA_S

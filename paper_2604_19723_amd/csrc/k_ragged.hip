@@ -20,12 +20,11 @@
 //  3. peak pick and FP64 refinement from that LDS row.
 #include <climits>
 
+#include "proj_common.h"
 #include "ragged.h"
 
 namespace ba {
 namespace {
-
-typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 512;
 constexpr int kOffP = 64 * 1024;      // spectrum row (<= 64 KB)
@@ -63,7 +62,7 @@ __device__ double parabolic(double pm, double p0, double pp) {
 // ---------------------------------------------------------------- covariance
 
 template <int BN>
-__device__ void covariance_lds(const float2* __restrict__ Yb, int M, int T, unsigned char* smem) {
+__device__ __forceinline__ void covariance_lds(const float2* __restrict__ Yb, int M, int T, unsigned char* smem) {
   constexpr int BM = 4;
   float2* sR = reinterpret_cast<float2*>(smem);
   float2* sPart = sR + M * M;
@@ -172,7 +171,8 @@ __device__ void covariance_lds(const float2* __restrict__ Yb, int M, int T, unsi
 // ---------------------------------------------------------------- one trial
 
 template <int MP, int WR>
-__device__ void trial_impl(const RArgs& A, const RItem& it, unsigned char* smem) {
+__device__ void trial_impl(const RArgs& A, const RItem& it, const float4* __restrict__ Xg, int nchunk,
+                           unsigned char* smem) {
   using C = RC<MP>;
   constexpr int RB = (C::NRB + WR - 1) / WR;  // row blocks per wave (round-robin)
   constexpr int WC = (kThreads / 64) / WR;
@@ -230,24 +230,25 @@ __device__ void trial_impl(const RArgs& A, const RItem& it, unsigned char* smem)
   float4* sX = reinterpret_cast<float4*>(smem);
   float* sP = reinterpret_cast<float*>(smem + kOffP);
   float* red = reinterpret_cast<float*>(smem + kOffRed);  // [2][WR][NB*16]
-  const float4* Xg = A.X[it.cls];
-  const int nchunk = A.nchunk[it.cls];
   const float scale = cov ? 1.0f / float(M * M) : 1.0f / (float(T) * float(M * M));
   float* Pout = A.P ? A.P + int64_t(it.trial) * A.G : nullptr;
 
-  float4 pre[C::F4];
-#pragma unroll
-  for (int f = 0; f < C::F4; ++f) pre[f] = Xg[f * kThreads + threadIdx.x];
-#pragma unroll
-  for (int f = 0; f < C::F4; ++f) sX[f * kThreads + threadIdx.x] = pre[f];
+  // table chunks (32 KB) arrive by LDS DMA, one chunk ahead: 8 waves x 4 x 64 lanes x 16 bytes
+  const int wave_dma = threadIdx.x >> 6, lane_dma = threadIdx.x & 63;
+#define BA_FETCH_X(c, buf)                                                                    \
+  do {                                                                                        \
+    _Pragma("unroll") for (int f_ = 0; f_ < C::CH4 / kThreads; ++f_) {                        \
+      const int o_ = wave_dma * (C::CH4 / 8) + f_ * 64;                                       \
+      lds_dma16(Xg + int64_t(c) * C::CH4 + o_ + lane_dma, sX + (buf) * C::CH4 + o_);          \
+    }                                                                                         \
+  } while (0)
+  BA_FETCH_X(0, 0);
+  lds_dma_wait();
   __syncthreads();
   for (int c = 0; c < nchunk; ++c) {
     const int buf = c & 1;
     const bool more = c + 1 < nchunk;
-    if (more) {
-#pragma unroll
-      for (int f = 0; f < C::F4; ++f) pre[f] = Xg[int64_t(c + 1) * C::CH4 + f * kThreads + threadIdx.x];
-    }
+    if (more) BA_FETCH_X(c + 1, buf ^ 1);
     const float4* xb4 = sX + buf * C::CH4;
     const float* xbf = reinterpret_cast<const float*>(xb4);
     for (int jb = wc; jb < C::NB; jb += WC) {
@@ -290,10 +291,7 @@ __device__ void trial_impl(const RArgs& A, const RItem& it, unsigned char* smem)
       part += __shfl_xor(part, 32, 64);
       if (lane < 16) red[(buf * WR + wr) * (C::NB * 16) + jb * 16 + lane] = part;
     }
-    if (more) {
-#pragma unroll
-      for (int f = 0; f < C::F4; ++f) sX[(buf ^ 1) * C::CH4 + f * kThreads + threadIdx.x] = pre[f];
-    }
+    lds_dma_wait();
     __syncthreads();
     for (int t = threadIdx.x; t < C::NB * 16; t += kThreads) {
       float s = 0.f;
@@ -307,6 +305,7 @@ __device__ void trial_impl(const RArgs& A, const RItem& it, unsigned char* smem)
       }
     }
   }
+#undef BA_FETCH_X
   __syncthreads();  // spectrum row complete
 
   // 3. peaks from the LDS row (same rule as the standalone peak kernel)
@@ -432,7 +431,11 @@ __device__ void trial_impl(const RArgs& A, const RItem& it, unsigned char* smem)
   __syncthreads();  // LDS reused by the next trial
 }
 
-__global__ __launch_bounds__(kThreads, 1) void k_ragged(RArgs A) {
+// The arguments live in device memory (a pointer, not a by-value struct):
+// the per-trial routine takes them by reference, which would otherwise force
+// a private copy of the whole struct.
+__global__ __launch_bounds__(kThreads, 1) void k_ragged(const RArgs* __restrict__ pargs) {
+  const RArgs& A = *pargs;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   __shared__ int s_ticket;
   for (;;) {
@@ -442,22 +445,22 @@ __global__ __launch_bounds__(kThreads, 1) void k_ragged(RArgs A) {
     __syncthreads();
     if (t >= A.n_items) break;  // uniform: every wave leaves
     const RItem it = A.items[t];
-    const int wr = A.wr[it.cls];
+    // class parameters picked with constant indices (no local copy of the arguments)
     switch (it.cls) {
-      case 0: trial_impl<8, 1>(A, it, smem); break;
+      case 0: trial_impl<8, 1>(A, it, A.X[0], A.nchunk[0], smem); break;
       case 1:
-        if (wr == 1) trial_impl<16, 1>(A, it, smem);
-        else trial_impl<16, 2>(A, it, smem);
+        if (A.wr[1] == 1) trial_impl<16, 1>(A, it, A.X[1], A.nchunk[1], smem);
+        else trial_impl<16, 2>(A, it, A.X[1], A.nchunk[1], smem);
         break;
       case 2:
-        if (wr == 2) trial_impl<32, 2>(A, it, smem);
-        else trial_impl<32, 4>(A, it, smem);
+        if (A.wr[2] == 2) trial_impl<32, 2>(A, it, A.X[2], A.nchunk[2], smem);
+        else trial_impl<32, 4>(A, it, A.X[2], A.nchunk[2], smem);
         break;
       case 3:
-        if (wr == 4) trial_impl<64, 4>(A, it, smem);
-        else trial_impl<64, 8>(A, it, smem);
+        if (A.wr[3] == 4) trial_impl<64, 4>(A, it, A.X[3], A.nchunk[3], smem);
+        else trial_impl<64, 8>(A, it, A.X[3], A.nchunk[3], smem);
         break;
-      default: trial_impl<128, 8>(A, it, smem); break;
+      default: trial_impl<128, 8>(A, it, A.X[4], A.nchunk[4], smem); break;
     }
   }
 }
@@ -483,8 +486,8 @@ hipError_t ragged_prepare() {
                              hipFuncAttributeMaxDynamicSharedMemorySize, kRaggedLds);
 }
 
-hipError_t launch_ragged(const RArgs& a, int n_wg, hipStream_t s) {
-  hipLaunchKernelGGL(k_ragged, dim3(unsigned(n_wg)), dim3(kThreads), kRaggedLds, s, a);
+hipError_t launch_ragged(const RArgs* d_args, int n_wg, hipStream_t s) {
+  hipLaunchKernelGGL(k_ragged, dim3(unsigned(n_wg)), dim3(kThreads), kRaggedLds, s, d_args);
   return hipGetLastError();
 }
 

@@ -22,6 +22,18 @@ struct QCfg {
   static constexpr int F4 = CH4 / 256;             // float4 per thread per chunk
 };
 
+// Direct global -> LDS copy of 16 bytes per lane (global_load_lds_dwordx4):
+// lane i's word lands at lds_wave + 16 i. lds_wave must be wave-uniform and
+// point into dynamic shared memory. Completion is tracked by vmcnt; callers
+// wait with lds_dma_wait() before the barrier that publishes the data.
+__device__ __forceinline__ void lds_dma16(const void* gsrc_lane, void* lds_wave) {
+  __builtin_amdgcn_global_load_lds(gsrc_lane, reinterpret_cast<__attribute__((address_space(3))) void*>(
+                                                  reinterpret_cast<uintptr_t>(lds_wave)),
+                                   16, 0, 0);
+}
+
+__device__ __forceinline__ void lds_dma_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); /* vmcnt(0) */ }
+
 // Q = [[Rr, -Ri], [Ri, Rr]] element (i, k) for an element count padded to MP
 __device__ __forceinline__ float qval(const float2* __restrict__ Rb, int M, int MP, int i, int k) {
   const bool iim = i >= MP, kim = k >= MP;

@@ -36,6 +36,8 @@ struct Ragged {
   int wr[kRaggedClasses] = {1, 1, 2, 4, 8};
   std::map<std::pair<int, int>, int> route_table;  // (class, log2 T bucket) -> route
   RItem* d_items = nullptr;
+  RArgs* d_args = nullptr;        // arguments of the captured launch (device copy)
+  RArgs* d_args_probe = nullptr;  // arguments of autotuner probes
   int32_t* d_counter = nullptr;
   int n_wg = 1;
   hipStream_t cap = nullptr;
@@ -138,11 +140,13 @@ hipError_t capture(Ragged& r) {
     r.graph = nullptr;
   }
   const RArgs a = make_args(r, r.d_items, int(r.desc.size()));
-  hipError_t e = hipStreamBeginCapture(r.cap, hipStreamCaptureModeThreadLocal);
+  hipError_t e = hipMemcpy(r.d_args, &a, sizeof(RArgs), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
+  e = hipStreamBeginCapture(r.cap, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return e;
   // the ticket counter is cleared by a kernel, not a memset node
   hipError_t e1 = launch_ragged_reset(r.d_counter, r.cap);
-  hipError_t e2 = e1 == hipSuccess ? launch_ragged(a, r.n_wg, r.cap) : e1;
+  hipError_t e2 = e1 == hipSuccess ? launch_ragged(r.d_args, r.n_wg, r.cap) : e1;
   e = hipStreamEndCapture(r.cap, &r.graph);
   if (e2 != hipSuccess) return e2;
   if (e != hipSuccess) return e;
@@ -159,12 +163,13 @@ hipError_t time_subset(Ragged& r, const std::vector<RItem>& items, int repeats, 
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   const RArgs a = make_args(r, d, int(items.size()));
+  if (e == hipSuccess) e = hipMemcpy(r.d_args_probe, &a, sizeof(RArgs), hipMemcpyHostToDevice);
   const int nwg = std::min<int>(r.n_wg, int(items.size()));
   float best = 1e30f;
   for (int rep = 0; e == hipSuccess && rep < repeats + 1; ++rep) {
     e = launch_ragged_reset(r.d_counter, r.cap);
     if (e == hipSuccess) e = hipEventRecord(e0, r.cap);
-    if (e == hipSuccess) e = launch_ragged(a, nwg, r.cap);
+    if (e == hipSuccess) e = launch_ragged(r.d_args_probe, nwg, r.cap);
     if (e == hipSuccess) e = hipEventRecord(e1, r.cap);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float t = 0.f;
@@ -212,6 +217,8 @@ static void rg_free(ba_ragged r) {
   for (int c = 0; c < kRaggedClasses; ++c)
     if (r->X[c]) (void)hipFree(r->X[c]);
   if (r->d_items) (void)hipFree(r->d_items);
+  if (r->d_args) (void)hipFree(r->d_args);
+  if (r->d_args_probe) (void)hipFree(r->d_args_probe);
   if (r->d_counter) (void)hipFree(r->d_counter);
   delete r;
 }
@@ -282,6 +289,8 @@ ba_status ba_ragged_create(ba_ragged* out, ba_plan plan, int32_t n_trials, const
   r->n_wg = std::max(1, std::min(ncu, n_trials));
   if (e == hipSuccess) e = hipMalloc(&r->d_items, size_t(n_trials) * sizeof(RItem));
   if (e == hipSuccess) e = hipMalloc(&r->d_counter, 256);
+  if (e == hipSuccess) e = hipMalloc(&r->d_args, sizeof(RArgs));
+  if (e == hipSuccess) e = hipMalloc(&r->d_args_probe, sizeof(RArgs));
   if (e == hipSuccess) e = hipStreamCreate(&r->cap);
   if (e == hipSuccess) {
     std::vector<size_t> all(n_trials);

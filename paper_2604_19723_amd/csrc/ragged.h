@@ -52,7 +52,7 @@ inline int ragged_wr_options(int cls, int* out) {
 
 int ragged_blocks_per_chunk(int cls);
 hipError_t ragged_prepare();
-hipError_t launch_ragged(const RArgs& a, int n_wg, hipStream_t s);
+hipError_t launch_ragged(const RArgs* d_args, int n_wg, hipStream_t s);
 hipError_t launch_ragged_reset(int32_t* counter, hipStream_t s);
 
 }  // namespace ba
