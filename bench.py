@@ -33,6 +33,34 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(key):
+    """HBM bytes per launch of a kernel from the committed counter record
+    (profiles/traffic.json: FETCH_SIZE + WRITE_SIZE, each scaled by what the
+    counter reads for a copy of known size), or None when the record is
+    missing or the kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(path))[key]
+        h = hashlib.sha256()
+        for f in rec["sources"]:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest() != rec["source_sha256"]:
+            return None
+        return rec["fetch_bytes"] + rec["write_bytes"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def proj_kernel_name(precision, n_elem):
+    """The kernel that evaluates the projection for a precision and array size."""
+    if precision == "f32_valu":
+        return "k_spec_cov_valu"
+    if n_elem > 64:
+        return "k_proj_s"
+    return "k_proj_q" if precision == "f32" else "k_proj_qb"
+
+
 def rmse_by_snr(ts, refined_deg, idx):
     """RMSE in degrees per SNR point, estimates associated to the truths
     (sorted pairing on a line, Hungarian on the sphere)."""
@@ -330,8 +358,10 @@ def main():
                    "n_grid": G, "snr_db": sorted(set(float(x) for x in ts.snr_db)),
                    "precision": args.precision},
         "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
-                     "kernel": "spectrum projection", "kernel_ms": proj_ms,
+                     "frac": achieved / peak,
+                     "traffic": measured_traffic("%s|%s|%s|b%d" % (
+                         proj_kernel_name(args.precision, M), args.precision, ts.name, B)),
+                     "kernel": proj_kernel_name(args.precision, M), "kernel_ms": proj_ms,
                      "flops_per_launch": flops_proj},
         "cpu_baseline": cpu,
         "grid_points_trials_per_s": value * G,
