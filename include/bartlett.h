@@ -120,9 +120,9 @@ ba_status ba_covariance(ba_plan p, int32_t n_trials, int32_t n_snap, const void*
                         void* stream);
 
 /*
- * Workspace bytes ba_spectrum needs for n_trials trials (0 for FP32 plans of
- * up to 64 elements; otherwise the real-equivalent covariance of every trial,
- * (2 Mp)^2 * 4 bytes per trial with Mp the padded element count).
+ * Workspace bytes ba_spectrum needs for n_trials trials (0 for plans of up to
+ * 64 elements; otherwise the real-equivalent covariance of every trial,
+ * (2 Mp)^2 * 4 bytes per trial with Mp the padded element count, 128 or 256).
  */
 ba_status ba_spectrum_workspace_size(ba_plan p, int32_t n_trials, size_t* bytes);
 

@@ -47,18 +47,17 @@ static void grid_direction(int kind, const double* grid, int64_t g, double u[3])
   }
 }
 
-// Which projection kernel a plan uses. FP32 up to 64 elements: Q in registers
-// (k_proj_q). Otherwise the streaming kernel, which first writes Q to the
-// workspace in fragment order.
-static bool uses_stream(const Plan& p) {
-  return p.precision != BA_PREC_F32_VALU && !(p.precision == BA_PREC_F32 && p.Mp <= 64);
-}
+// Which projection kernel a plan uses. Up to 64 elements Q stays in registers
+// (k_proj_q in FP32, k_proj_qb for the BF16 passes); larger arrays use the
+// streaming kernel, which first writes Q to the workspace in fragment order.
+static bool uses_stream(const Plan& p) { return p.precision != BA_PREC_F32_VALU && p.Mp > 64; }
 
 size_t spectrum_ws_bytes(const Plan& p, int B) { return uses_stream(p) ? qprep_bytes(p, B) : 0; }
 
 hipError_t launch_spectrum(const Plan& p, int B, const float2* R, float* P, void* ws, hipStream_t s) {
   if (p.precision == BA_PREC_F32_VALU) return launch_spectrum_valu(p, B, R, P, s);
-  if (!uses_stream(p)) return launch_spectrum_mfma(p, B, R, P, s);
+  if (!uses_stream(p))
+    return p.precision == BA_PREC_F32 ? launch_spectrum_mfma(p, B, R, P, s) : launch_spectrum_qb(p, B, R, P, s);
   return launch_spectrum_stream(p, B, R, ws, P, s);
 }
 

@@ -49,6 +49,7 @@ hipError_t launch_spectrum_stream(const Plan& p, int B, const float2* R, void* Q
                                   hipStream_t s);
 hipError_t launch_spectrum_valu(const Plan& p, int B, const float2* R, float* P, hipStream_t s);
 hipError_t launch_spectrum_mfma(const Plan& p, int B, const float2* R, float* P, hipStream_t s);
+hipError_t launch_spectrum_qb(const Plan& p, int B, const float2* R, float* P, hipStream_t s);
 hipError_t launch_spectrum_snapshots(const Plan& p, int B, int T, const float2* Y, float* P,
                                      hipStream_t s);
 hipError_t launch_peaks(const Plan& p, int B, const float* P, int k, int* idx, float* val,

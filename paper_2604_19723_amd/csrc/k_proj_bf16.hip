@@ -1,0 +1,172 @@
+// Split-precision Bartlett projection for arrays of up to 64 elements with Q
+// resident in registers (the BF16 counterpart of k_proj_q).
+//
+// Q X ~= Qh Xh + Qh Xl + Ql Xh on v_mfma_f32_16x16x32_bf16, FP32 accumulate
+// (hi = bf16(q), lo = bf16(q - hi), round to nearest even; the lo*lo term is
+// dropped). Q's hi/lo fragments are built from R once per workgroup; the BF16
+// steering chunks (hi and lo interleaved per k-step) arrive by LDS DMA one
+// chunk ahead. The quadratic-form epilogue takes x = xh + xl from the same
+// LDS chunk (16 significant bits, below the error of the dropped term).
+//
+// A workgroup serves two trials, so every steering chunk brought on chip is
+// used twice: 4 waves = 2 trials x 2 halves of Q's 128 rows (4 row blocks
+// each). Per 16-column block a wave issues 4 x 4 x 3 = 48 MFMAs against 8
+// conflict-free 16-byte LDS reads and 8 8-byte epilogue reads.
+#include "proj_common.h"
+
+namespace ba {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int MPB = 64;             // padded element count
+constexpr int KB = 2 * MPB;         // 128 rows of Q
+constexpr int NKC = KB / 32;        // 4 k-steps of 32
+constexpr int WRB = 2, RBB = 4;     // row waves per trial, row blocks per wave
+constexpr int NTW = 2;              // trials per workgroup
+constexpr int BLKW = NKC * 2 * 64;  // 16-byte words per 16-column block (8 KB)
+constexpr int NBB = 4;              // blocks per 32 KB chunk
+constexpr int CHW = NBB * BLKW;     // 16-byte words per chunk
+static_assert(WRB * RBB * 16 == KB, "row waves must cover Q");
+
+__device__ __forceinline__ unsigned short bf16_bits(float x) {
+  unsigned u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+__device__ __forceinline__ float lo_half(unsigned w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float hi_half(unsigned w) { return __uint_as_float(w & 0xffff0000u); }
+
+template <int PREC>
+__global__ __launch_bounds__(256, 1) void k_proj_qb(const float2* __restrict__ R, const uint4* __restrict__ Xb,
+                                                    float* __restrict__ P, int B, int M, int64_t G, int nchunk,
+                                                    int chunks_per_wg, int nsplit) {
+  extern __shared__ __attribute__((aligned(16))) uint4 sXb[];  // [2][CHW], LDS DMA
+  __shared__ float red[2][NTW][WRB][NBB * 16];
+
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wr = wave % WRB, wt = wave / WRB;
+  const int64_t pair = blockIdx.x / nsplit;
+  const int c0 = (blockIdx.x % nsplit) * chunks_per_wg;
+  const int c1 = min(c0 + chunks_per_wg, nchunk);
+  if (c0 >= c1) return;
+  // an odd batch leaves the last pair with one trial: its second half repeats
+  // the first and stores nothing
+  const int64_t b = pair * NTW + wt;
+  const int64_t bq = b < B ? b : pair * NTW;
+
+  // A operand hi/lo: rows i = 16 (4 wr + rb) + lane%16, k = 32 kc + 8 (lane/16) + e
+  uint4 ah[RBB][NKC], al[RBB][NKC];
+  const float2* Rb = R + bq * int64_t(M) * M;
+#pragma unroll
+  for (int rb = 0; rb < RBB; ++rb)
+#pragma unroll
+    for (int kc = 0; kc < NKC; ++kc) {
+      unsigned short h[8], l[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float q = qval(Rb, M, MPB, 16 * (RBB * wr + rb) + (lane & 15), 32 * kc + 8 * (lane >> 4) + e);
+        h[e] = bf16_bits(q);
+        l[e] = bf16_bits(q - __uint_as_float(unsigned(h[e]) << 16));
+      }
+      ah[rb][kc] = make_uint4(h[0] | (unsigned(h[1]) << 16), h[2] | (unsigned(h[3]) << 16),
+                              h[4] | (unsigned(h[5]) << 16), h[6] | (unsigned(h[7]) << 16));
+      al[rb][kc] = make_uint4(l[0] | (unsigned(l[1]) << 16), l[2] | (unsigned(l[3]) << 16),
+                              l[4] | (unsigned(l[5]) << 16), l[6] | (unsigned(l[7]) << 16));
+    }
+
+#define BA_FETCH(c, buf)                                                                  \
+  do {                                                                                    \
+    _Pragma("unroll") for (int f_ = 0; f_ < CHW / 4 / 64; ++f_) {                         \
+      const int o_ = wave * (CHW / 4) + f_ * 64;                                          \
+      lds_dma16(Xb + int64_t(c) * CHW + o_ + lane, sXb + (buf) * CHW + o_);               \
+    }                                                                                     \
+  } while (0)
+
+  BA_FETCH(c0, 0);
+  lds_dma_wait();
+  __syncthreads();
+  const float invM2 = 1.0f / float(M * M);
+  // epilogue: lane holds D rows 16 rbg + 4 (lane/16) + e, column lane%16; in the
+  // B layout those are 4 consecutive values of one 16-byte word
+  const int ew = (lane >> 5) * 16 + (lane & 15), eh = (lane >> 4) & 1;
+  for (int c = c0; c < c1; ++c) {
+    const int buf = (c - c0) & 1;
+    if (c + 1 < c1) BA_FETCH(c + 1, buf ^ 1);
+    for (int jb = 0; jb < NBB; ++jb) {
+      floatx4 acc[RBB];
+#pragma unroll
+      for (int rb = 0; rb < RBB; ++rb) acc[rb] = floatx4{0.f, 0.f, 0.f, 0.f};
+      const uint4* bx = sXb + buf * CHW + jb * BLKW;
+#pragma unroll
+      for (int kc = 0; kc < NKC; ++kc) {
+        const bf16x8 bh = __builtin_bit_cast(bf16x8, bx[(kc * 2) * 64 + lane]);
+        const bf16x8 bl = __builtin_bit_cast(bf16x8, bx[(kc * 2 + 1) * 64 + lane]);
+#pragma unroll
+        for (int rb = 0; rb < RBB; ++rb) {
+          const bf16x8 vah = __builtin_bit_cast(bf16x8, ah[rb][kc]);
+          acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vah, bh, acc[rb], 0, 0, 0);
+          if (PREC == BA_PREC_BF16X3) {
+            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vah, bl, acc[rb], 0, 0, 0);
+            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, al[rb][kc]), bh,
+                                                              acc[rb], 0, 0, 0);
+          }
+        }
+      }
+      float part = 0.f;
+#pragma unroll
+      for (int rb = 0; rb < RBB; ++rb) {
+        const int rbg = RBB * wr + rb, kc = rbg >> 1;
+        const int w = (rbg & 1) * 32 + ew;
+        const uint2 xh = reinterpret_cast<const uint2*>(bx + (kc * 2) * 64 + w)[eh];
+        const uint2 xl = reinterpret_cast<const uint2*>(bx + (kc * 2 + 1) * 64 + w)[eh];
+        part += (lo_half(xh.x) + lo_half(xl.x)) * acc[rb][0];
+        part += (hi_half(xh.x) + hi_half(xl.x)) * acc[rb][1];
+        part += (lo_half(xh.y) + lo_half(xl.y)) * acc[rb][2];
+        part += (hi_half(xh.y) + hi_half(xl.y)) * acc[rb][3];
+      }
+      part += __shfl_xor(part, 16, 64);
+      part += __shfl_xor(part, 32, 64);
+      if (lane < 16) red[buf][wt][wr][jb * 16 + lane] = part;
+    }
+    lds_dma_wait();
+    __syncthreads();
+    if (threadIdx.x < NTW * NBB * 16) {
+      const int t = threadIdx.x % (NBB * 16), tw = threadIdx.x / (NBB * 16);
+      const int64_t bo = pair * NTW + tw;
+      const int64_t g = int64_t(c) * NBB * 16 + t;
+      if (bo < B && g < G) P[bo * G + g] = (red[buf][tw][0][t] + red[buf][tw][1][t]) * invM2;
+    }
+  }
+#undef BA_FETCH
+}
+
+}  // namespace
+
+hipError_t launch_spectrum_qb(const Plan& p, int B, const float2* R, float* P, hipStream_t s) {
+  if (p.Mp != MPB || !p.d_Xb) return hipErrorInvalidValue;
+  if (B == 0) return hipSuccess;
+  // chunks stay inside the table: it holds a whole number of 32-block groups
+  const int nchunk = int((p.Gb + NBB - 1) / NBB);
+  if (int64_t(nchunk) * NBB > p.Xblocks) return hipErrorInvalidValue;
+  const int64_t pairs = (int64_t(B) + NTW - 1) / NTW;
+  int nsplit = 1;
+  while (pairs * nsplit < 2048 && nsplit < nchunk) nsplit *= 2;
+  const int per = (nchunk + nsplit - 1) / nsplit;
+  nsplit = (nchunk + per - 1) / per;
+  const int64_t nblk = pairs * nsplit;
+  if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+  const size_t lds = 2 * CHW * sizeof(uint4);
+  const uint4* Xb = reinterpret_cast<const uint4*>(p.d_Xb);
+  if (p.precision == BA_PREC_BF16X3)
+    hipLaunchKernelGGL(k_proj_qb<BA_PREC_BF16X3>, dim3(unsigned(nblk)), dim3(256), lds, s, R, Xb, P, B, p.M, p.G,
+                       nchunk, per, nsplit);
+  else
+    hipLaunchKernelGGL(k_proj_qb<BA_PREC_BF16>, dim3(unsigned(nblk)), dim3(256), lds, s, R, Xb, P, B, p.M, p.G,
+                       nchunk, per, nsplit);
+  return hipGetLastError();
+}
+
+}  // namespace ba
