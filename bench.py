@@ -101,6 +101,81 @@ def cpu_baseline(ts, K, seconds):
                       "zgemm, peaks, refinement), %.1f s" % (n, dt)}
 
 
+def bench_sequential(args, workers):
+    """Project-out-and-rescan detection on the ULA 64 workload: one step is the
+    covariance plus K passes of (residual covariance, spectrum, top-1 peak)."""
+    from paper_2604_19723_amd import workload as wl
+    t = time.perf_counter()
+    ts = wl.config2(args.trials, dtype=np.complex64, workers=workers)
+    log("generated %d trials in %.1f s" % (ts.n_trials, time.perf_counter() - t))
+    import torch
+    from paper_2604_19723_amd import bartlett as bb
+    prec = {"f32": bb.BA_PREC_F32, "bf16x3": bb.BA_PREC_BF16X3}[args.precision]
+    B, T, M, K = ts.n_trials, ts.n_snap, ts.n_elem, ts.K
+    dev = torch.device("cuda:0")
+    Y = torch.from_numpy(ts.Y).to(dev)
+    plan = bb.plan_for(ts, prec)
+    G = plan.G
+    R = torch.empty((B, M, M), dtype=torch.complex64, device=dev)
+    idx = torch.empty((B, K), dtype=torch.int32, device=dev)
+    val = torch.empty((B, K), dtype=torch.float32, device=dev)
+    ref = torch.empty((B, K, 1), dtype=torch.float64, device=dev)
+    ws = bb.sequential_workspace_for(plan, B, dev)
+
+    def step(ev=None):
+        bb.ba_covariance(plan, B, T, Y, R)
+        if ev is not None:
+            ev[0].record()
+        bb.ba_sequential_peaks(plan, B, R, K, idx, val, ref, ws)
+        if ev is not None:
+            ev[1].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    seq_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    log("timed %d steps: %.3f ms/step, %d passes %.3f ms" % (args.steps, dt / args.steps * 1e3, K, seq_ms))
+    from paper_2604_19723_amd import metrics
+    est = metrics.fractional_index_to_deg(ts.grid_kind, ts.grid, ts.grid_shape, ref.cpu().numpy())
+    rmse, fails = rmse_by_snr(ts, est, idx.cpu().numpy())
+    # the plain top-K search on the same trials, for the accuracy comparison
+    out = bb.run_grid_search(plan, Y, K)
+    torch.cuda.synchronize()
+    est_p = metrics.fractional_index_to_deg(ts.grid_kind, ts.grid, ts.grid_shape, out["refined"].cpu().numpy())
+    rmse_plain, fails_plain = rmse_by_snr(ts, est_p, out["idx"].cpu().numpy())
+    flops = float(B) * K * (8.0 * M * M * G + 8.0 * M * G)
+    bound, peak = PEAK[args.precision]
+    achieved = flops / (seq_ms * 1e-3) / 1e12
+    value = B * args.steps / dt
+    line = {
+        "metric": "MC trials/sec and grid-points*trials/sec at fixed RMSE; % MFMA/HBM peak",
+        "value": value, "unit": "trials/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.precision,
+        "data": "synthetic (seeded signal model: CN sources + CN noise on a half-wavelength ULA)",
+        "config": {"workload": ts.name + "_sequential", "trials": B, "passes": K, "n_elem": M, "n_snap": T,
+                   "n_grid": G, "precision": args.precision},
+        "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "%s x %d passes (residual and peak kernels inside the timed span)" % (
+                         proj_kernel_name(args.precision, M), K),
+                     "kernel_ms": seq_ms, "flops_per_launch": flops},
+        "cpu_baseline": None,
+        "grid_points_trials_per_s": value * G * K,
+        "rmse_deg_by_snr": rmse, "failed_trials": fails,
+        "plain_rmse_deg_by_snr": rmse_plain, "plain_failed_trials": fails_plain,
+    }
+    print(json.dumps(line), flush=True)
+    plan.close()
+    return 0
+
+
 def bench_ragged(args, workers):
     """Uneven batch: one graph replay = one step over all trials."""
     from paper_2604_19723_amd import workload as wl
@@ -238,7 +313,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--trials", type=int, default=10000)
     ap.add_argument("--precision", default="f32", choices=sorted(PEAK))
-    ap.add_argument("--workload", default="ula64", choices=["ula64", "ura256", "ragged", "learned"],
+    ap.add_argument("--workload", default="ula64",
+                    choices=["ula64", "ura256", "ragged", "learned", "sequential"],
                     help="ula64: 64-element ULA, 7201-point grid (default); ura256: 16x16 URA, "
                          "361x181 az/el grid; ragged: 50 000 uneven trials (M 8..128, T 16..2048) "
                          "in one persistent launch under a HIP graph")
@@ -264,6 +340,8 @@ def main():
         return bench_ragged(args, workers)
     if args.workload == "learned":
         return bench_learned(args, workers)
+    if args.workload == "sequential":
+        return bench_sequential(args, workers)
     t = time.perf_counter()
     if args.workload == "ula64":
         ts = wl.config2(args.trials, dtype=np.complex64, workers=workers)   # before the GPU is touched

@@ -332,6 +332,51 @@ ba_status ba_propose_refine(ba_plan plan, ba_mlp net, int32_t n_trials, const vo
                             uint8_t* fell_back, int32_t* n_fallback, void* workspace, size_t workspace_bytes,
                             void* stream);
 
+/* ---------------------------------------------------------------- residual projector
+ *
+ * Sec. IV-D.2: before the Bartlett cost is evaluated, each observation is
+ * replaced by its residual z~ = Pi z, Pi = I - Psi Psi^+, the component
+ * orthogonal to the span of the steering vectors Psi of the features already
+ * known. For T snapshots the residuals' covariance is R~ = Pi R Pi.
+ */
+
+/*
+ * Residual covariance R~ = Pi R Pi for every trial.
+ *   R      dev c64 [B][M][M], Hermitian (as ba_covariance writes it; the kernel
+ *          reads both triangles as one Hermitian matrix).
+ *   S      columns of Psi per trial, 0..16 (0 copies R).
+ *   Psi    dev c64 [B][S][M]: column s of trial b is the contiguous M-vector at
+ *          Psi + (b S + s) M. Columns whose part orthogonal to the earlier
+ *          columns has squared norm <= 1e-10 of their own (duplicates, zero
+ *          columns) add nothing to the span.
+ *   R_out  dev c64 [B][M][M], exactly Hermitian; may be R itself (in place).
+ * The projector algebra runs in FP64; R~ is rounded to FP32 once.
+ * Errors: BA_ERR_ARG for S outside [0, 16] or NULL buffers, synchronously.
+ */
+ba_status ba_residual_covariance(ba_plan p, int32_t n_trials, const void* R, int32_t S, const void* Psi,
+                                 void* R_out, void* stream);
+
+/* Workspace bytes of ba_sequential_peaks (256-byte aligned base required). */
+ba_status ba_sequential_workspace_size(ba_plan p, int32_t n_trials, size_t* bytes);
+
+/*
+ * Project-out-and-rescan detection: pass 0 takes the largest local maximum
+ * of the plain spectrum; pass j > 0 projects the steering vectors of the
+ * j grid points found so far out of R (ba_residual_covariance with Psi the
+ * plan's steering columns), evaluates the spectrum of the residual
+ * covariance at the plan's precision, and takes its largest local maximum.
+ *   R        dev c64 [B][M][M] (not modified).
+ *   k        passes, 1..16.
+ *   idx      dev int32 [B][k] in detection order (-1 if a pass finds no
+ *            local maximum; such a pass adds no column).
+ *   val      dev f32 [B][k]: the residual spectrum at the point, in its pass.
+ *   refined  dev f64 [B][k][ndim] (may be NULL): parabolic vertex on that
+ *            pass's spectrum, grid units.
+ * Cost: k spectrum evaluations per trial. Asynchronous on stream.
+ */
+ba_status ba_sequential_peaks(ba_plan p, int32_t n_trials, const void* R, int32_t k, int32_t* idx, float* val,
+                              double* refined, void* workspace, size_t workspace_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

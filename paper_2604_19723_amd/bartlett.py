@@ -84,6 +84,9 @@ _SIGS = {
     "ba_propose_workspace_size": (_i32, [_vp, _i32, _i32, _i32, C.POINTER(_sz)]),
     "ba_propose_refine": (_i32, [_vp, _vp, _i32, _vp, _i32, _i32, C.c_float, _vp, _vp, _vp, _vp,
                                  C.POINTER(_i32), _vp, _sz, _vp]),
+    "ba_residual_covariance": (_i32, [_vp, _i32, _vp, _i32, _vp, _vp, _vp]),
+    "ba_sequential_workspace_size": (_i32, [_vp, _i32, C.POINTER(_sz)]),
+    "ba_sequential_peaks": (_i32, [_vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
 }
 
 BA_ROUTE_AUTO = -1
@@ -543,3 +546,34 @@ def ba_propose_refine(plan: Plan, net: Mlp, n_trials, R, k, half_window, tau, id
         C.byref(nf), ws, nbytes, _stream(stream)))
     return nf.value
 
+
+# --------------------------------------------------------------------------- residual projector
+
+def ba_residual_covariance(plan: Plan, n_trials, R, S, Psi, R_out, stream=None):
+    """R~ = Pi R Pi, Pi = I - Psi Psi^+; Psi is c64 [B][S][M] (None when S = 0)."""
+    M = plan.M
+    _check("ba_residual_covariance", lib().ba_residual_covariance(
+        plan.handle, n_trials, _dev(R, "c64", n_trials * M * M, "R"), S,
+        _dev(Psi, "c64", n_trials * S * M, "Psi", optional=S == 0),
+        _dev(R_out, "c64", n_trials * M * M, "R_out"), _stream(stream)))
+
+
+def ba_sequential_workspace_size(plan: Plan, n_trials) -> int:
+    b = _sz()
+    _check("ba_sequential_workspace_size", lib().ba_sequential_workspace_size(plan.handle, n_trials, C.byref(b)))
+    return b.value
+
+
+def ba_sequential_peaks(plan: Plan, n_trials, R, k, idx, val, refined=None, workspace=None, stream=None):
+    """Project-out-and-rescan detection: k passes, outputs in detection order."""
+    M, nd = plan.M, plan.ndim
+    ws, nbytes = _workspace(workspace, ba_sequential_workspace_size(plan, n_trials))
+    _check("ba_sequential_peaks", lib().ba_sequential_peaks(
+        plan.handle, n_trials, _dev(R, "c64", n_trials * M * M, "R"), k,
+        _dev(idx, "i32", n_trials * k, "idx"), _dev(val, "f32", n_trials * k, "val"),
+        _dev(refined, "f64", n_trials * k * nd, "refined", optional=True), ws, nbytes, _stream(stream)))
+
+
+def sequential_workspace_for(plan: Plan, n_trials, device):
+    import torch
+    return torch.empty(max(ba_sequential_workspace_size(plan, n_trials), 1), dtype=torch.uint8, device=device)

@@ -56,6 +56,14 @@ hipError_t launch_peaks(const Plan& p, int B, const float* P, int k, int* idx, f
                         double* refined, hipStream_t s);
 hipError_t launch_moments(const Plan& p, int B, const float* P, double* mu_cov, hipStream_t s);
 
+// residual covariance R~ = Pi R Pi (Psi given as vectors [B][S][M], or as grid
+// indices gidx[b * ld + s] into the plan's steering table, -1 = no column)
+hipError_t launch_residual(const Plan& p, int B, const float2* R, int S, const float2* Psi, const int* gidx,
+                           int ld, float2* Rout, hipStream_t s);
+size_t residual_lds_bytes(int M, int S);
+hipError_t launch_put_column(int B, int c, int K, int ndim, const int* i1, const float* v1, const double* r1,
+                             int* idx, float* val, double* ref, hipStream_t s);
+
 void set_error(const std::string& msg);
 std::vector<float> plan_x_table(const Plan& p, int Mrows, int Mp, int64_t nblocks);
 

@@ -169,15 +169,112 @@ __device__ __forceinline__ void covariance_lds(const float2* __restrict__ Yb, in
 }
 
 // ---------------------------------------------------------------- one trial
+//
+// The projection of each size class is inlined into the kernel body, where
+// the compiler sees every LDS access against the kernel's own LDS block and
+// can tell the chunk being read from the chunk in flight; the covariance and
+// the peak pick stay out of line (their registers do not add to the
+// projection's, and the peak pick is one routine for every class).
 
-template <int MP, int WR>
-__device__ void trial_impl(const RArgs& A, const RItem& it, const float4* __restrict__ Xg, int nchunk,
-                           unsigned char* smem) {
+template <int BN>
+__device__ __attribute__((noinline)) void stage_covariance(const float2* __restrict__ Yb, int M, int T,
+                                                           unsigned char* smem) {
+  covariance_lds<BN>(Yb, M, T, smem);
+}
+
+// the chunk loop for NACT active row blocks per wave (a prefix of its RB)
+template <int MP, int WR, int NACT, int RB>
+__device__ __forceinline__ void project_chunks(const RArgs& A, const float4* __restrict__ Xg, int nchunk,
+                                               const float (&a)[RB][RC<MP>::KS], bool cov, float scale,
+                                               float* __restrict__ Pout, unsigned char* smem) {
   using C = RC<MP>;
-  constexpr int RB = (C::NRB + WR - 1) / WR;  // row blocks per wave (round-robin)
   constexpr int WC = (kThreads / 64) / WR;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wr = wave % WR, wc = wave / WR;
+  float4* sX = reinterpret_cast<float4*>(smem);
+  float* sP = reinterpret_cast<float*>(smem + kOffP);
+  float* red = reinterpret_cast<float*>(smem + kOffRed);  // [2][WR][NB*16]
+
+  // table chunks (32 KB) arrive by LDS DMA, one chunk ahead: 8 waves x 4 x 64 lanes x 16 bytes
+#define BA_FETCH_X(c, buf)                                                                    \
+  do {                                                                                        \
+    _Pragma("unroll") for (int f_ = 0; f_ < C::CH4 / kThreads; ++f_) {                        \
+      const int o_ = wave * (C::CH4 / 8) + f_ * 64;                                           \
+      lds_dma16(Xg + int64_t(c) * C::CH4 + o_ + lane, sX + (buf) * C::CH4 + o_);              \
+    }                                                                                         \
+  } while (0)
+  BA_FETCH_X(0, 0);
+  lds_dma_wait();
+  __syncthreads();
+  for (int c = 0; c < nchunk; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nchunk) BA_FETCH_X(c + 1, buf ^ 1);
+    const float4* xb4 = sX + buf * C::CH4;
+    const float* xbf = reinterpret_cast<const float*>(xb4);
+    for (int jb = wc; jb < C::NB; jb += WC) {
+      floatx4 acc[NACT > 0 ? NACT : 1];
+#pragma unroll
+      for (int rb = 0; rb < NACT; ++rb) acc[rb] = floatx4{0.f, 0.f, 0.f, 0.f};
+      const float4* bx = xb4 + jb * (C::BLK / 4);
+#pragma unroll
+      for (int s4 = 0; s4 < C::KS / 4; ++s4) {
+        if (NACT == 0) break;
+        const float4 bv = bx[s4 * 64 + lane];
+#pragma unroll
+        for (int rb = 0; rb < NACT; ++rb) {
+          acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 0], bv.x, acc[rb], 0, 0, 0);
+          acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 1], bv.y, acc[rb], 0, 0, 0);
+          acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 2], bv.z, acc[rb], 0, 0, 0);
+          acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 3], bv.w, acc[rb], 0, 0, 0);
+        }
+      }
+      float part = 0.f;
+#pragma unroll
+      for (int rb = 0; rb < NACT; ++rb) {
+        const int rbg = rb * WR + wr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (cov) {
+            const int i = 16 * rbg + 4 * (lane >> 4) + r;
+            const int s = i >> 2;
+            const float xv = xbf[jb * C::BLK + ((s >> 2) * 64 + r * 16 + (lane & 15)) * 4 + (s & 3)];
+            part += xv * acc[rb][r];
+          } else {
+            part += acc[rb][r] * acc[rb][r];
+          }
+        }
+      }
+      part += __shfl_xor(part, 16, 64);
+      part += __shfl_xor(part, 32, 64);
+      if (lane < 16) red[(buf * WR + wr) * (C::NB * 16) + jb * 16 + lane] = part;
+    }
+    lds_dma_wait();
+    __syncthreads();
+    for (int t = threadIdx.x; t < C::NB * 16; t += kThreads) {
+      float sum = 0.f;
+#pragma unroll
+      for (int w = 0; w < WR; ++w) sum += red[(buf * WR + w) * (C::NB * 16) + t];
+      const int64_t g = int64_t(c) * C::NB * 16 + t;
+      if (g < A.G) {
+        const float p = sum * scale;
+        sP[g] = p;
+        if (Pout) Pout[g] = p;
+      }
+    }
+  }
+#undef BA_FETCH_X
+  __syncthreads();  // spectrum row complete
+}
+
+template <int MP, int WR>
+__device__ __forceinline__ void trial_project(const RArgs& A, const RItem& it, const float4* __restrict__ Xg,
+                                              int nchunk, unsigned char* smem) {
+  using C = RC<MP>;
+  constexpr int RB = (C::NRB + WR - 1) / WR;  // row blocks per wave (round-robin)
+  const int lane = threadIdx.x & 63;
+  // the wave index is uniform: taking it through a scalar register keeps the
+  // active-block count below in scalar registers too
+  const int wr = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) % WR;
   const int M = it.M, T = it.T;
   const float2* Yb = A.Y + it.y_off;
   const bool cov = it.route == kRouteCov;
@@ -187,7 +284,7 @@ __device__ void trial_impl(const RArgs& A, const RItem& it, const float4* __rest
   // 1. A operand
   float a[RB][C::KS];
   if (cov) {
-    covariance_lds<(MP >= 128 ? 8 : 4)>(Yb, M, T, smem);
+    stage_covariance<(MP >= 128 ? 8 : 4)>(Yb, M, T, smem);
     const float2* sR = reinterpret_cast<const float2*>(smem);
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
@@ -226,89 +323,25 @@ __device__ void trial_impl(const RArgs& A, const RItem& it, const float4* __rest
   }
   __syncthreads();  // LDS covariance consumed
 
-  // 2. projection
-  float4* sX = reinterpret_cast<float4*>(smem);
-  float* sP = reinterpret_cast<float*>(smem + kOffP);
-  float* red = reinterpret_cast<float*>(smem + kOffRed);  // [2][WR][NB*16]
+  // 2. projection over the active row blocks of this wave (rb * WR + wr < nrb_act)
   const float scale = cov ? 1.0f / float(M * M) : 1.0f / (float(T) * float(M * M));
   float* Pout = A.P ? A.P + int64_t(it.trial) * A.G : nullptr;
+  int nact = 0;
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) nact += (rb * WR + wr < nrb_act) ? 1 : 0;
+  static_assert(RB <= 2, "row blocks per wave");
+  if (nact == RB)
+    project_chunks<MP, WR, RB, RB>(A, Xg, nchunk, a, cov, scale, Pout, smem);
+  else if (RB == 2 && nact == 1)
+    project_chunks<MP, WR, (RB == 2 ? 1 : 0), RB>(A, Xg, nchunk, a, cov, scale, Pout, smem);
+  else
+    project_chunks<MP, WR, 0, RB>(A, Xg, nchunk, a, cov, scale, Pout, smem);
+}
 
-  // table chunks (32 KB) arrive by LDS DMA, one chunk ahead: 8 waves x 4 x 64 lanes x 16 bytes
-  const int wave_dma = threadIdx.x >> 6, lane_dma = threadIdx.x & 63;
-#define BA_FETCH_X(c, buf)                                                                    \
-  do {                                                                                        \
-    _Pragma("unroll") for (int f_ = 0; f_ < C::CH4 / kThreads; ++f_) {                        \
-      const int o_ = wave_dma * (C::CH4 / 8) + f_ * 64;                                       \
-      lds_dma16(Xg + int64_t(c) * C::CH4 + o_ + lane_dma, sX + (buf) * C::CH4 + o_);          \
-    }                                                                                         \
-  } while (0)
-  BA_FETCH_X(0, 0);
-  lds_dma_wait();
-  __syncthreads();
-  for (int c = 0; c < nchunk; ++c) {
-    const int buf = c & 1;
-    const bool more = c + 1 < nchunk;
-    if (more) BA_FETCH_X(c + 1, buf ^ 1);
-    const float4* xb4 = sX + buf * C::CH4;
-    const float* xbf = reinterpret_cast<const float*>(xb4);
-    for (int jb = wc; jb < C::NB; jb += WC) {
-      floatx4 acc[RB];
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb) acc[rb] = floatx4{0.f, 0.f, 0.f, 0.f};
-      const float4* bx = xb4 + jb * (C::BLK / 4);
-#pragma unroll
-      for (int s4 = 0; s4 < C::KS / 4; ++s4) {
-        const float4 bv = bx[s4 * 64 + lane];
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-          if (rb * WR + wr < nrb_act) {
-            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 0], bv.x, acc[rb], 0, 0, 0);
-            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 1], bv.y, acc[rb], 0, 0, 0);
-            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 2], bv.z, acc[rb], 0, 0, 0);
-            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 3], bv.w, acc[rb], 0, 0, 0);
-          }
-        }
-      }
-      float part = 0.f;
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb) {
-        const int rbg = rb * WR + wr;
-        if (rbg < nrb_act) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            if (cov) {
-              const int i = 16 * rbg + 4 * (lane >> 4) + r;
-              const int s = i >> 2;
-              const float xv = xbf[jb * C::BLK + ((s >> 2) * 64 + r * 16 + (lane & 15)) * 4 + (s & 3)];
-              part += xv * acc[rb][r];
-            } else {
-              part += acc[rb][r] * acc[rb][r];
-            }
-          }
-        }
-      }
-      part += __shfl_xor(part, 16, 64);
-      part += __shfl_xor(part, 32, 64);
-      if (lane < 16) red[(buf * WR + wr) * (C::NB * 16) + jb * 16 + lane] = part;
-    }
-    lds_dma_wait();
-    __syncthreads();
-    for (int t = threadIdx.x; t < C::NB * 16; t += kThreads) {
-      float s = 0.f;
-#pragma unroll
-      for (int w = 0; w < WR; ++w) s += red[(buf * WR + w) * (C::NB * 16) + t];
-      const int64_t g = int64_t(c) * C::NB * 16 + t;
-      if (g < A.G) {
-        const float p = s * scale;
-        sP[g] = p;
-        if (Pout) Pout[g] = p;
-      }
-    }
-  }
-#undef BA_FETCH_X
-  __syncthreads();  // spectrum row complete
-
-  // 3. peaks from the LDS row (same rule as the standalone peak kernel)
+// 3. peaks from the LDS row (same rule as the standalone peak kernel)
+__device__ __attribute__((noinline)) void trial_peaks(const RArgs& A, const RItem& it, unsigned char* smem) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const float* sP = reinterpret_cast<const float*>(smem + kOffP);
   constexpr int KC = kRaggedMaxPeaks;
   float lv[KC];
   int li[KC];
@@ -447,21 +480,22 @@ __global__ __launch_bounds__(kThreads, 1) void k_ragged(const RArgs* __restrict_
     const RItem it = A.items[t];
     // class parameters picked with constant indices (no local copy of the arguments)
     switch (it.cls) {
-      case 0: trial_impl<8, 1>(A, it, A.X[0], A.nchunk[0], smem); break;
+      case 0: trial_project<8, 1>(A, it, A.X[0], A.nchunk[0], smem); break;
       case 1:
-        if (A.wr[1] == 1) trial_impl<16, 1>(A, it, A.X[1], A.nchunk[1], smem);
-        else trial_impl<16, 2>(A, it, A.X[1], A.nchunk[1], smem);
+        if (A.wr[1] == 1) trial_project<16, 1>(A, it, A.X[1], A.nchunk[1], smem);
+        else trial_project<16, 2>(A, it, A.X[1], A.nchunk[1], smem);
         break;
       case 2:
-        if (A.wr[2] == 2) trial_impl<32, 2>(A, it, A.X[2], A.nchunk[2], smem);
-        else trial_impl<32, 4>(A, it, A.X[2], A.nchunk[2], smem);
+        if (A.wr[2] == 2) trial_project<32, 2>(A, it, A.X[2], A.nchunk[2], smem);
+        else trial_project<32, 4>(A, it, A.X[2], A.nchunk[2], smem);
         break;
       case 3:
-        if (A.wr[3] == 4) trial_impl<64, 4>(A, it, A.X[3], A.nchunk[3], smem);
-        else trial_impl<64, 8>(A, it, A.X[3], A.nchunk[3], smem);
+        if (A.wr[3] == 4) trial_project<64, 4>(A, it, A.X[3], A.nchunk[3], smem);
+        else trial_project<64, 8>(A, it, A.X[3], A.nchunk[3], smem);
         break;
-      default: trial_impl<128, 8>(A, it, A.X[4], A.nchunk[4], smem); break;
+      default: trial_project<128, 8>(A, it, A.X[4], A.nchunk[4], smem); break;
     }
+    trial_peaks(A, it, smem);
   }
 }
 
