@@ -25,6 +25,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 # dense peaks of the arithmetic each projection kernel runs on
+SEED_PROPOSAL = 0xBA570007
 PEAK = {"f32": ("mfma", 157.3), "bf16x3": ("mfma", 2500.0), "bf16": ("mfma", 2500.0),
         "f32_valu": ("alu", 157.3)}
 
@@ -176,6 +177,93 @@ def bench_sequential(args, workers):
     return 0
 
 
+def bench_proposal(args, workers):
+    """The birth-proposal step on the ULA 64 workload: one step is covariance,
+    spectrum, proposal moments and N = 1024 Gaussian particles with importance
+    weights per trial (one new feature per trial, as in the paper's proposal)."""
+    from paper_2604_19723_amd import workload as wl
+    t = time.perf_counter()
+    ts = wl.config2(args.trials, dtype=np.complex64, workers=workers)
+    log("generated %d trials in %.1f s" % (ts.n_trials, time.perf_counter() - t))
+    import torch
+    from paper_2604_19723_amd import bartlett as bb
+    B, T, M, N = ts.n_trials, ts.n_snap, ts.n_elem, 1024
+    dev = torch.device("cuda:0")
+    Y = torch.from_numpy(ts.Y).to(dev)
+    plan = bb.plan_for(ts, bb.BA_PREC_F32)
+    G, d = plan.G, plan.coord_dim
+    R = torch.empty((B, M, M), dtype=torch.complex64, device=dev)
+    P = torch.empty((B, G), dtype=torch.float32, device=dev)
+    mc = torch.empty((B, d + d * d), dtype=torch.float64, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(SEED_PROPOSAL)
+    z = torch.randn((B, N, d), dtype=torch.float64, device=dev, generator=gen)
+    part = torch.empty((B, N, d), dtype=torch.float64, device=dev)
+    w = torch.empty((B, N), dtype=torch.float64, device=dev)
+    ws = bb.spectrum_workspace_for(plan, B, dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+
+    def step(timed=False):
+        bb.ba_covariance(plan, B, T, Y, R)
+        if timed:
+            ev[0].record()
+        bb.ba_spectrum(plan, B, R, P, ws)
+        if timed:
+            ev[1].record()
+        bb.ba_proposal_moments(plan, B, P, mc)
+        if timed:
+            ev[2].record()
+        bb.ba_proposal_sample(plan, B, mc, N, z, part, w)
+        if timed:
+            ev[3].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    proj, mom, samp = [], [], []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(True)
+        torch.cuda.synchronize()
+        proj.append(ev[0].elapsed_time(ev[1]))
+        mom.append(ev[1].elapsed_time(ev[2]))
+        samp.append(ev[2].elapsed_time(ev[3]))
+    dt = time.perf_counter() - t0
+    proj_ms, mom_ms, samp_ms = (float(np.mean(x)) for x in (proj, mom, samp))
+    log("timed %d steps: %.3f ms/step; projection %.3f, moments %.3f, sampling %.3f ms" % (
+        args.steps, dt / args.steps * 1e3, proj_ms, mom_ms, samp_ms))
+    flops = float(B) * (8.0 * M * M * G + 8.0 * M * G)
+    samp_bytes = float(B) * N * (2 * d + 1) * 8 + B * (d + d * d) * 8     # z in, particles + weights out
+    mom_bytes = float(B) * G * 4 + B * (d + d * d) * 8
+    wh = w.cpu().numpy()
+    ph = part.cpu().numpy()
+    ess = 1.0 / np.sum(wh * wh, axis=1)
+    value = B * args.steps / dt
+    line = {
+        "metric": "MC trials/sec and grid-points*trials/sec at fixed RMSE; % MFMA/HBM peak",
+        "value": value, "unit": "trials/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 spectrum, f64 proposal",
+        "data": "synthetic (seeded signal model: CN sources + CN noise on a half-wavelength ULA; "
+                "standard normal draws from torch's seeded device generator)",
+        "config": {"workload": ts.name + "_proposal_n1024", "trials": B, "particles": N, "n_grid": G},
+        "roofline": {"bound": "mfma", "achieved": flops / (proj_ms * 1e-3) / 1e12, "peak": 157.3,
+                     "unit": "TFLOP/s", "frac": flops / (proj_ms * 1e-3) / 1e12 / 157.3, "traffic": None,
+                     "kernel": "k_proj_q", "kernel_ms": proj_ms, "flops_per_launch": flops},
+        "proposal_kernels": {
+            "k_moments": {"ms": mom_ms, "bound": "hbm", "bytes": mom_bytes,
+                          "achieved_gb_s": mom_bytes / (mom_ms * 1e-3) / 1e9, "peak_gb_s": 8000.0},
+            "k_proposal_sample": {"ms": samp_ms, "bound": "hbm", "bytes": samp_bytes,
+                                  "achieved_gb_s": samp_bytes / (samp_ms * 1e-3) / 1e9, "peak_gb_s": 8000.0}},
+        "cpu_baseline": None,
+        "effective_sample_size_median": float(np.median(ess)),
+        "particles_finite": bool(np.all(np.isfinite(ph))),
+    }
+    print(json.dumps(line), flush=True)
+    plan.close()
+    return 0
+
+
 def bench_ragged(args, workers):
     """Uneven batch: one graph replay = one step over all trials."""
     from paper_2604_19723_amd import workload as wl
@@ -314,7 +402,7 @@ def main():
     ap.add_argument("--trials", type=int, default=10000)
     ap.add_argument("--precision", default="f32", choices=sorted(PEAK))
     ap.add_argument("--workload", default="ula64",
-                    choices=["ula64", "ura256", "ragged", "learned", "sequential"],
+                    choices=["ula64", "ura256", "ragged", "learned", "sequential", "proposal"],
                     help="ula64: 64-element ULA, 7201-point grid (default); ura256: 16x16 URA, "
                          "361x181 az/el grid; ragged: 50 000 uneven trials (M 8..128, T 16..2048) "
                          "in one persistent launch under a HIP graph")
@@ -342,6 +430,8 @@ def main():
         return bench_learned(args, workers)
     if args.workload == "sequential":
         return bench_sequential(args, workers)
+    if args.workload == "proposal":
+        return bench_proposal(args, workers)
     t = time.perf_counter()
     if args.workload == "ula64":
         ts = wl.config2(args.trials, dtype=np.complex64, workers=workers)   # before the GPU is touched

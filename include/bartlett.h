@@ -176,6 +176,24 @@ ba_status ba_proposal_moments(ba_plan p, int32_t n_trials, const float* P, doubl
                               void* stream);
 
 /*
+ * Gaussian birth proposal of Sec. IV-D.2 from the moments above: particle n
+ * of trial b is mu + L z[b][n] with C = L L^T, and its importance weight is
+ * proportional to the indicator of the search region over the proposal
+ * density (the target being uniform on the region), normalised to sum to one
+ * per trial. The region is the span of the grid's coordinates; on an az/el
+ * grid whose azimuth axis wraps, azimuth is periodic (always inside; the
+ * particle is reported wrapped, its density taken at the unwrapped draw).
+ *   mu_cov     dev double [B][d + d*d] (ba_proposal_moments).
+ *   z          dev double [B][N][d]: standard normal draws, supplied by the caller.
+ *   particles  dev double [B][N][d]; weights dev double [B][N].
+ * A covariance that is not positive definite gives particles = mu and equal
+ * weights; a trial with no particle inside the region gets NaN weights.
+ * Angle grids only: BA_ERR_UNSUPPORTED for BA_GRID_DIRS.
+ */
+ba_status ba_proposal_sample(ba_plan p, int32_t n_trials, const double* mu_cov, int32_t n_particles,
+                             const double* z, double* particles, double* weights, void* stream);
+
+/*
  * The whole path for B trials: covariance -> spectrum -> peaks (+refinement).
  *   Y          dev c64 [B][T][M].
  *   P          dev float [B][G] or NULL (then staged in the workspace).

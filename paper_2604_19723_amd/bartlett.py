@@ -84,6 +84,7 @@ _SIGS = {
     "ba_propose_workspace_size": (_i32, [_vp, _i32, _i32, _i32, C.POINTER(_sz)]),
     "ba_propose_refine": (_i32, [_vp, _vp, _i32, _vp, _i32, _i32, C.c_float, _vp, _vp, _vp, _vp,
                                  C.POINTER(_i32), _vp, _sz, _vp]),
+    "ba_proposal_sample": (_i32, [_vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp]),
     "ba_residual_covariance": (_i32, [_vp, _i32, _vp, _i32, _vp, _vp, _vp]),
     "ba_sequential_workspace_size": (_i32, [_vp, _i32, C.POINTER(_sz)]),
     "ba_sequential_peaks": (_i32, [_vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
@@ -282,6 +283,16 @@ def ba_proposal_moments(plan: Plan, n_trials, P, mu_cov, stream=None):
     _check("ba_proposal_moments", lib().ba_proposal_moments(
         plan.handle, n_trials, _dev(P, "f32", n_trials * plan.G, "P"),
         _dev(mu_cov, "f64", n_trials * (d + d * d), "mu_cov"), _stream(stream)))
+
+
+def ba_proposal_sample(plan: Plan, n_trials, mu_cov, n_particles, z, particles, weights, stream=None):
+    """Particles mu + L z and normalised importance weights per trial."""
+    d = plan.coord_dim
+    _check("ba_proposal_sample", lib().ba_proposal_sample(
+        plan.handle, n_trials, _dev(mu_cov, "f64", n_trials * (d + d * d), "mu_cov"), n_particles,
+        _dev(z, "f64", n_trials * n_particles * d, "z"),
+        _dev(particles, "f64", n_trials * n_particles * d, "particles"),
+        _dev(weights, "f64", n_trials * n_particles, "weights"), _stream(stream)))
 
 
 def _workspace(workspace, need):

@@ -2,6 +2,8 @@
 // tables, and dispatch to the kernel launchers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -383,6 +385,45 @@ ba_status ba_proposal_moments(ba_plan p, int32_t n_trials, const float* P, doubl
   if (n_trials == 0) return BA_OK;
   if (!P || !mu_cov) return arg_error(fn, "null buffer");
   hipError_t e = launch_moments(q, n_trials, P, mu_cov, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? BA_OK : dev_error(fn, e);
+}
+
+ba_status ba_proposal_sample(ba_plan p, int32_t n_trials, const double* mu_cov, int32_t n_particles,
+                             const double* z, double* particles, double* weights, void* stream) {
+  static const char* fn = "ba_proposal_sample";
+  CHECK_PLAN(fn);
+  if (n_trials < 0 || n_particles < 0) return arg_error(fn, "n_trials >= 0 and n_particles >= 0 required");
+  if (q.kind == BA_GRID_DIRS) {
+    set_error(std::string(fn) + ": direction-vector grids have no angle region");
+    return BA_ERR_UNSUPPORTED;
+  }
+  if (n_trials == 0 || n_particles == 0) return BA_OK;
+  if (!mu_cov || !z || !particles || !weights) return arg_error(fn, "null buffer");
+  // the region spanned by the grid's coordinates (degrees)
+  ProposalRegion reg{};
+  const int d = q.coord_dim;
+  const int64_t G = q.G;
+  for (int a = 0; a < d; ++a) {
+    double lo = q.coords[a], hi = q.coords[a];
+    for (int64_t g = 0; g < G; ++g) {
+      lo = std::min(lo, q.coords[g * d + a]);
+      hi = std::max(hi, q.coords[g * d + a]);
+    }
+    reg.lo[a] = lo;
+    reg.hi[a] = hi;
+    reg.period[a] = 0.0;
+  }
+  if (q.kind == BA_GRID_AZEL_DEG && q.wrap0) {
+    // azimuth runs along the first grid axis (rows of shape1 points)
+    const int s1 = q.shape1;
+    reg.lo[0] = q.coords[0];
+    reg.period[0] = q.wrap0 == 2 ? q.coords[int64_t(q.shape0 - 1) * s1 * d] - q.coords[0]
+                                 : double(q.shape0) * (q.coords[int64_t(s1) * d] - q.coords[0]);
+    reg.hi[0] = reg.lo[0] + reg.period[0];
+    if (!(reg.period[0] > 0.0)) return arg_error(fn, "azimuth grid without a positive period");
+  }
+  hipError_t e = launch_proposal_sample(n_trials, mu_cov, d, n_particles, z, reg, particles, weights,
+                                        static_cast<hipStream_t>(stream));
   return e == hipSuccess ? BA_OK : dev_error(fn, e);
 }
 

@@ -64,6 +64,14 @@ size_t residual_lds_bytes(int M, int S);
 hipError_t launch_put_column(int B, int c, int K, int ndim, const int* i1, const float* v1, const double* r1,
                              int* idx, float* val, double* ref, hipStream_t s);
 
+// search region of the Gaussian proposal, per coordinate: [lo, hi], or
+// periodic with the given period (> 0) starting at lo
+struct ProposalRegion {
+  double lo[3], hi[3], period[3];
+};
+hipError_t launch_proposal_sample(int B, const double* mu_cov, int d, int N, const double* z,
+                                  const ProposalRegion& reg, double* particles, double* weights, hipStream_t s);
+
 void set_error(const std::string& msg);
 std::vector<float> plan_x_table(const Plan& p, int Mrows, int Mp, int64_t nblocks);
 
