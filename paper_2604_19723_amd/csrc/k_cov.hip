@@ -74,10 +74,113 @@ __global__ __launch_bounds__(256) void k_cov_tiles(const float2* __restrict__ Y,
   }
 }
 
+// Arrays of up to 64 elements: the covariance as a real Gram matrix on the
+// matrix cores. With z_t the 2M floats of snapshot t (re, im interleaved),
+// G = sum_t z_t z_t^T and
+//   Re R[m][n] = G[2m][2n] + G[2m+1][2n+1],  Im R[m][n] = G[2m+1][2n] - G[2m][2n+1].
+// One workgroup per trial; 64-snapshot chunks staged row-major in LDS; the
+// 16x16 tiles of G on or above the diagonal (each holds 8x8 elements of R)
+// are split over the waves by pairs of tile rows (w, MT-1-w), so every wave
+// carries MT+1 tiles. A k-step of v_mfma_f32_16x16x4f32 reads each 16-column
+// fragment once (lane (i, k) holds z_{t+k}[16c + i]) and uses it as the B
+// operand of both rows' tiles.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+constexpr int kGramChunk = 64;
+
+template <int MT>
+__global__ __launch_bounds__(256) void k_cov_mfma(const float2* __restrict__ Y, float2* __restrict__ R, int M,
+                                                  int T) {
+  constexpr int W = 16 * MT;   // Gram columns, 2M padded
+  constexpr int LD = W + 16;   // LDS row stride: rows k and k+1 fall on different bank halves
+  __shared__ __attribute__((aligned(16))) float sZ[kGramChunk * LD];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int64_t b = blockIdx.x;
+  const float2* Yb = Y + b * int64_t(T) * M;
+  const int ra = wave, rb = MT - 1 - wave;
+  const bool act = wave < (MT + 1) / 2;
+  const bool two = act && rb != ra;
+  floatx4 accA[MT], accB[MT];
+#pragma unroll
+  for (int c = 0; c < MT; ++c) {
+    accA[c] = floatx4{0.f, 0.f, 0.f, 0.f};
+    accB[c] = floatx4{0.f, 0.f, 0.f, 0.f};
+  }
+  const int fi = lane & 15, fk = lane >> 4;
+  for (int t0 = 0; t0 < T; t0 += kGramChunk) {
+    for (int v = threadIdx.x; v < kGramChunk * (W / 2); v += 256) {
+      const int tt = v / (W / 2), m = v - tt * (W / 2);
+      const int t = t0 + tt;
+      const float2 y = (t < T && m < M) ? Yb[int64_t(t) * M + m] : make_float2(0.f, 0.f);
+      *reinterpret_cast<float2*>(&sZ[tt * LD + 2 * m]) = y;
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll 2
+      for (int s = 0; s < kGramChunk / 4; ++s) {
+        const float* row = sZ + (4 * s + fk) * LD + fi;
+        const float fa = row[16 * ra], fb = row[16 * rb];
+        float f[MT];
+#pragma unroll
+        for (int c = 0; c < MT; ++c) f[c] = row[16 * c];
+#pragma unroll
+        for (int c = 0; c < MT; ++c) {
+          if (c >= ra) accA[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa, f[c], accA[c], 0, 0, 0);
+          if (two && c >= rb) accB[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(fb, f[c], accB[c], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (!act) return;
+  // D[i][j] of a tile sits in lane j + 16 (i / 4), register i % 4; the odd
+  // column 2n+1 is in the neighbouring lane
+  const float invT = 1.0f / float(T);
+  float2* Rb = R + b * int64_t(M) * M;
+  const bool even = (lane & 1) == 0;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (h == 1 && !two) break;
+    const int r = h == 0 ? ra : rb;
+#pragma unroll
+    for (int c = 0; c < MT; ++c) {
+      if (c < r) continue;
+      const floatx4 a = h == 0 ? accA[c] : accB[c];
+      floatx4 x;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) x[e] = __shfl_xor(a[e], 1, 64);
+      if (!even) continue;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int m = 8 * r + 2 * (lane >> 4) + q;
+        const int n = 8 * c + (fi >> 1);
+        if (m >= M || n >= M || m > n) continue;
+        const float re = (a[2 * q] + x[2 * q + 1]) * invT;
+        const float im = m == n ? 0.f : (a[2 * q + 1] - x[2 * q]) * invT;
+        Rb[int64_t(m) * M + n] = make_float2(re, im);
+        if (m != n) Rb[int64_t(n) * M + m] = make_float2(re, -im);
+      }
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_covariance(const Plan& p, int B, int T, const float2* Y, float2* R,
                              hipStream_t s) {
+  if (p.M <= 64) {
+    const dim3 grid{static_cast<uint32_t>(B)}, block{256u};
+    switch ((p.M + 7) / 8) {
+      case 1: hipLaunchKernelGGL(k_cov_mfma<1>, grid, block, 0, s, Y, R, p.M, T); break;
+      case 2: hipLaunchKernelGGL(k_cov_mfma<2>, grid, block, 0, s, Y, R, p.M, T); break;
+      case 3: hipLaunchKernelGGL(k_cov_mfma<3>, grid, block, 0, s, Y, R, p.M, T); break;
+      case 4: hipLaunchKernelGGL(k_cov_mfma<4>, grid, block, 0, s, Y, R, p.M, T); break;
+      case 5: hipLaunchKernelGGL(k_cov_mfma<5>, grid, block, 0, s, Y, R, p.M, T); break;
+      case 6: hipLaunchKernelGGL(k_cov_mfma<6>, grid, block, 0, s, Y, R, p.M, T); break;
+      case 7: hipLaunchKernelGGL(k_cov_mfma<7>, grid, block, 0, s, Y, R, p.M, T); break;
+      default: hipLaunchKernelGGL(k_cov_mfma<8>, grid, block, 0, s, Y, R, p.M, T); break;
+    }
+    return hipGetLastError();
+  }
   const int ntile = (p.M + kTile - 1) / kTile;
   const int npairs = ntile * (ntile + 1) / 2;
   const int64_t nblk = int64_t(B) * npairs;
