@@ -395,6 +395,58 @@ ba_status ba_sequential_workspace_size(ba_plan p, int32_t n_trials, size_t* byte
 ba_status ba_sequential_peaks(ba_plan p, int32_t n_trials, const void* R, int32_t k, int32_t* idx, float* val,
                               double* refined, void* workspace, size_t workspace_bytes, void* stream);
 
+/* ---------------------------------------------------------------- coherent multi-array cost
+ *
+ * The paper's own birth-proposal workload (Sec. IV-D.2): the coherent
+ * Bartlett spectrum P(s) = |sum_j (1/N_z) z_j^H psi_j(s)|^2 over J arrays for
+ * candidate SFV positions s, where psi_j(s) is the path-loss compensated
+ * wideband URA response (Sec. II-C) of the path that the surface with SFV s
+ * creates between the terminal and array j: virtual anchor, Householder mirror
+ * and array rotation of Sec. II-B. Element order of psi_j: frequency slowest,
+ * then the horizontal element, then the vertical one (b (x) a_y (x) a_z); the
+ * pilot spectrum is flat; baseband frequencies are equally spaced over the
+ * bandwidth and centred on zero; elements sit at half a wavelength, centred.
+ */
+typedef struct ba_coherent_s* ba_coherent;
+
+/*
+ * Plan of one geometry: builds the steering table of every candidate at every
+ * array on the device (FP64 geometry and phases, stored FP32).
+ *   pa_pos      host double [J][3]: array positions (m).
+ *   pa_rot      host double [J][3][3] row-major: array rotations (local -> global).
+ *   n_y, n_z    URA elements per axis (1..16); n_f baseband frequencies (1..64);
+ *               J * n_f * n_y * n_z <= 2048.
+ *   fc          carrier (Hz); bandwidth (Hz, >= 0).
+ *   p_mt        host double [3]: terminal position (m).
+ *   candidates  host double [n_cand][3]: SFV positions (m), nonzero, n_cand <= 2^26.
+ * Table memory: 8 * J * N_z * ceil(n_cand / 128) * 128 bytes.
+ */
+ba_status ba_coherent_create(ba_coherent* out, int32_t n_arrays, const double* pa_pos, const double* pa_rot,
+                             int32_t n_y, int32_t n_z, int32_t n_f, double fc, double bandwidth,
+                             const double* p_mt, int64_t n_cand, const double* candidates);
+ba_status ba_coherent_destroy(ba_coherent h);
+/* n_obs = J * N_z (complex values per trial), n_cand = candidates. */
+ba_status ba_coherent_info(ba_coherent h, int32_t* n_obs, int64_t* n_cand);
+/* Workspace bytes of ba_coherent_spectrum (256-byte aligned base required). */
+ba_status ba_coherent_workspace_size(ba_coherent h, int32_t n_trials, size_t* bytes);
+
+/*
+ * The cost for every (trial, candidate).
+ *   Z  dev c64 [B][J][N_z]: each trial's (residual) observations, array by array.
+ *   P  dev float [B][n_cand].
+ * FP32 MFMA with FP32 accumulation. Asynchronous on stream.
+ */
+ba_status ba_coherent_spectrum(ba_coherent h, int32_t n_trials, const void* Z, float* P, void* workspace,
+                               size_t workspace_bytes, void* stream);
+
+/*
+ * Proposal moments over the candidates (Sec. IV-D.2): weights P / sum P, mean
+ * = the candidate of maximum cost (lowest index among equal maxima),
+ * covariance = weighted second central moment, in metres.
+ *   mu_cov  dev double [B][3 + 9].
+ */
+ba_status ba_coherent_moments(ba_coherent h, int32_t n_trials, const float* P, double* mu_cov, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -85,6 +85,13 @@ _SIGS = {
     "ba_propose_refine": (_i32, [_vp, _vp, _i32, _vp, _i32, _i32, C.c_float, _vp, _vp, _vp, _vp,
                                  C.POINTER(_i32), _vp, _sz, _vp]),
     "ba_proposal_sample": (_i32, [_vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp]),
+    "ba_coherent_create": (_i32, [C.POINTER(_vp), _i32, _vp, _vp, _i32, _i32, _i32, C.c_double, C.c_double,
+                                  _vp, C.c_int64, _vp]),
+    "ba_coherent_destroy": (_i32, [_vp]),
+    "ba_coherent_info": (_i32, [_vp, C.POINTER(_i32), C.POINTER(C.c_int64)]),
+    "ba_coherent_workspace_size": (_i32, [_vp, _i32, C.POINTER(_sz)]),
+    "ba_coherent_spectrum": (_i32, [_vp, _i32, _vp, _vp, _vp, _sz, _vp]),
+    "ba_coherent_moments": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "ba_residual_covariance": (_i32, [_vp, _i32, _vp, _i32, _vp, _vp, _vp]),
     "ba_sequential_workspace_size": (_i32, [_vp, _i32, C.POINTER(_sz)]),
     "ba_sequential_peaks": (_i32, [_vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
@@ -588,3 +595,72 @@ def ba_sequential_peaks(plan: Plan, n_trials, R, k, idx, val, refined=None, work
 def sequential_workspace_for(plan: Plan, n_trials, device):
     import torch
     return torch.empty(max(ba_sequential_workspace_size(plan, n_trials), 1), dtype=torch.uint8, device=device)
+
+
+# --------------------------------------------------------------------------- coherent multi-array cost
+
+class Coherent:
+    """Owns a ba_coherent handle (geometry + device steering table)."""
+
+    def __init__(self, handle, n_obs, n_cand):
+        self.handle, self.n_obs, self.n_cand = handle, n_obs, n_cand
+
+    def close(self):
+        if self.handle:
+            ba_coherent_destroy(self)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ba_coherent_create(pa_pos, pa_rot, n_y, n_z, n_f, fc, bandwidth, p_mt, candidates) -> Coherent:
+    pa = np.ascontiguousarray(np.asarray(pa_pos, np.float64).reshape(-1, 3))
+    J = pa.shape[0]
+    rot = _host_f64(pa_rot, 9 * J, "pa_rot")
+    mt = _host_f64(p_mt, 3, "p_mt")
+    cand = np.ascontiguousarray(np.asarray(candidates, np.float64).reshape(-1, 3))
+    h = C.c_void_p()
+    _check("ba_coherent_create", lib().ba_coherent_create(
+        C.byref(h), J, pa.ctypes.data_as(_vp), rot.ctypes.data_as(_vp), n_y, n_z, n_f, float(fc),
+        float(bandwidth), mt.ctypes.data_as(_vp), cand.shape[0], cand.ctypes.data_as(_vp)))
+    n_obs, n_cand = _i32(), C.c_int64()
+    _check("ba_coherent_info", lib().ba_coherent_info(h, C.byref(n_obs), C.byref(n_cand)))
+    return Coherent(h, n_obs.value, n_cand.value)
+
+
+def ba_coherent_destroy(h: Coherent):
+    _check("ba_coherent_destroy", lib().ba_coherent_destroy(h.handle))
+
+
+def ba_coherent_workspace_size(h: Coherent, n_trials) -> int:
+    b = _sz()
+    _check("ba_coherent_workspace_size", lib().ba_coherent_workspace_size(h.handle, n_trials, C.byref(b)))
+    return b.value
+
+
+def ba_coherent_spectrum(h: Coherent, n_trials, Z, P, workspace, stream=None):
+    ws, nbytes = _workspace(workspace, ba_coherent_workspace_size(h, n_trials))
+    _check("ba_coherent_spectrum", lib().ba_coherent_spectrum(
+        h.handle, n_trials, _dev(Z, "c64", n_trials * h.n_obs, "Z"), _dev(P, "f32", n_trials * h.n_cand, "P"),
+        ws, nbytes, _stream(stream)))
+
+
+def ba_coherent_moments(h: Coherent, n_trials, P, mu_cov, stream=None):
+    _check("ba_coherent_moments", lib().ba_coherent_moments(
+        h.handle, n_trials, _dev(P, "f32", n_trials * h.n_cand, "P"), _dev(mu_cov, "f64", n_trials * 12, "mu_cov"),
+        _stream(stream)))
+
+
+def coherent_workspace_for(h: Coherent, n_trials, device="cuda"):
+    import torch
+    return torch.empty(max(ba_coherent_workspace_size(h, n_trials), 256), dtype=torch.uint8, device=device)

@@ -14,6 +14,7 @@
 #include <climits>
 
 #include "ba_internal.h"
+#include "coherent.h"
 
 namespace ba {
 namespace {
@@ -281,6 +282,13 @@ hipError_t launch_peaks(const Plan& p, int B, const float* P, int k, int* idx, f
     hipLaunchKernelGGL(k_peaks<8>, grid, block, 0, s, P, p.G, p.shape1, p.rows, p.wrap0, k, idx, val, refined, p.ndim);
   else
     hipLaunchKernelGGL(k_peaks<16>, grid, block, 0, s, P, p.G, p.shape1, p.rows, p.wrap0, k, idx, val, refined, p.ndim);
+  return hipGetLastError();
+}
+
+// the same moments over an arbitrary point set X [G][d] (no wrap)
+hipError_t launch_point_moments(int B, const float* P, int64_t G, const double* X, int d, double* mu_cov,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_moments, dim3(unsigned(B)), dim3(256), 0, s, P, G, G, X, d, 0, mu_cov);
   return hipGetLastError();
 }
 

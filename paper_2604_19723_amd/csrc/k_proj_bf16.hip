@@ -102,8 +102,8 @@ __global__ __launch_bounds__(256, 1) void k_proj_qb(const float2* __restrict__ R
       const uint4* bx = sXb + buf * CHW + jb * BLKW;
 #pragma unroll
       for (int kc = 0; kc < NKC; ++kc) {
-        const bf16x8 bh = __builtin_bit_cast(bf16x8, bx[(kc * 2) * 64 + lane]);
-        const bf16x8 bl = __builtin_bit_cast(bf16x8, bx[(kc * 2 + 1) * 64 + lane]);
+        const bf16x8 bh = __builtin_bit_cast(bf16x8, lds_frag(bx, (kc * 2) * 64 + lane));
+        const bf16x8 bl = __builtin_bit_cast(bf16x8, lds_frag(bx, (kc * 2 + 1) * 64 + lane));
 #pragma unroll
         for (int rb = 0; rb < RBB; ++rb) {
           const bf16x8 vah = __builtin_bit_cast(bf16x8, ah[rb][kc]);
@@ -120,8 +120,8 @@ __global__ __launch_bounds__(256, 1) void k_proj_qb(const float2* __restrict__ R
       for (int rb = 0; rb < RBB; ++rb) {
         const int rbg = RBB * wr + rb, kc = rbg >> 1;
         const int w = (rbg & 1) * 32 + ew;
-        const uint2 xh = reinterpret_cast<const uint2*>(bx + (kc * 2) * 64 + w)[eh];
-        const uint2 xl = reinterpret_cast<const uint2*>(bx + (kc * 2 + 1) * 64 + w)[eh];
+        const uint2 xh = lds_frag(reinterpret_cast<const uint2*>(bx + (kc * 2) * 64 + w), eh);
+        const uint2 xl = lds_frag(reinterpret_cast<const uint2*>(bx + (kc * 2 + 1) * 64 + w), eh);
         part += (lo_half(xh.x) + lo_half(xl.x)) * acc[rb][0];
         part += (hi_half(xh.x) + hi_half(xl.x)) * acc[rb][1];
         part += (lo_half(xh.y) + lo_half(xl.y)) * acc[rb][2];

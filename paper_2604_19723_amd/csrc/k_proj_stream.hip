@@ -160,7 +160,7 @@ __global__ __launch_bounds__(64 * waves_for<PREC>(), 1) void k_proj_s(const void
       for (int h = 0; h < 2; ++h) {
 #pragma unroll
         for (int c = 0; c < kCB; ++c) {
-          const float4 bv = sb[c * 128 + h * 64 + lane];
+          const float4 bv = lds_frag(sb, c * 128 + h * 64 + lane);
 #pragma unroll
           for (int r = 0; r < RBW; ++r) {
             acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r][h].x, bv.x, acc[r][c], 0, 0, 0);
@@ -200,8 +200,8 @@ __global__ __launch_bounds__(64 * waves_for<PREC>(), 1) void k_proj_s(const void
       }
 #pragma unroll
       for (int c = 0; c < kCB; ++c) {
-        const uint4 bh = sBd[buf * CHUNK16 + c * 128 + lane];
-        const uint4 bl = sBd[buf * CHUNK16 + c * 128 + 64 + lane];
+        const uint4 bh = lds_frag(sBd + buf * CHUNK16, c * 128 + lane);
+        const uint4 bl = lds_frag(sBd + buf * CHUNK16, c * 128 + 64 + lane);
         const bf16x8 vbh = __builtin_bit_cast(bf16x8, bh);
         const bf16x8 vbl = __builtin_bit_cast(bf16x8, bl);
 #pragma unroll

@@ -34,6 +34,16 @@ __device__ __forceinline__ void lds_dma16(const void* gsrc_lane, void* lds_wave)
 
 __device__ __forceinline__ void lds_dma_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); /* vmcnt(0) */ }
 
+// Read of a fragment from an LDS chunk that an earlier lds_dma_wait() and
+// barrier have published. The restrict-qualified base gives the load alias
+// scope information; without it the compiler cannot tell the chunk being
+// read from the chunk still in flight and waits for every outstanding LDS
+// DMA before the read, which serialises the prefetch with the MFMAs.
+template <typename T>
+__device__ __forceinline__ T lds_frag(const T* __restrict__ base, int i) {
+  return base[i];
+}
+
 // Q = [[Rr, -Ri], [Ri, Rr]] element (i, k) for an element count padded to MP
 __device__ __forceinline__ float qval(const float2* __restrict__ Rb, int M, int MP, int i, int k) {
   const bool iim = i >= MP, kim = k >= MP;

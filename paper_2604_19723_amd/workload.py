@@ -419,3 +419,91 @@ def config5(n_trials: int, first_trial: int = 0, seed_offset: int = 0, K: int = 
     return TrialSet(Y=cat(0), pos_wl=ula_positions(64), grid_kind=GRID_ULA_DEG, grid=ula_grid(7201),
                     grid_shape=(7201, 1), wrap0=0, K=K, truth=cat(1), snr_db=cat(2), sigma2=cat(3),
                     name="learned_ula64_k4_t256_g7201")
+
+
+# ------------------------------------------------------------------ coherent multi-array (SFV candidates)
+#
+# The paper's own birth-proposal workload: J URAs around a room receive a
+# wideband pilot from one terminal; the observation of array j is the sum of
+# its paths' path-loss compensated responses plus noise (Sec. II-C,
+# eq. (observation-generative)). The residual after the known paths is taken
+# as exact, so a trial's observation holds the one new path (the reflection
+# at the wall whose SFV is to be found) plus white noise.
+
+C_LIGHT = 299792458.0
+
+
+@dataclasses.dataclass
+class CoherentSet:
+    Z: np.ndarray                 # complex [B][J][N_z]
+    pa_pos: np.ndarray            # [J][3] m
+    pa_rot: np.ndarray            # [J][3][3] local -> global
+    p_mt: np.ndarray              # [3] m
+    n_y: int
+    n_z: int
+    n_f: int
+    fc: float
+    bandwidth: float
+    sfv_true: np.ndarray          # [3] m
+    candidates: np.ndarray        # [G][3] m
+    name: str = ""
+
+    @property
+    def n_trials(self):
+        return self.Z.shape[0]
+
+
+def _rot_z(a):
+    c, s = math.cos(a), math.sin(a)
+    return np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+
+
+def _path_response(p_mt, s, p_pa, rot, f_base, p_y, p_z, fc):
+    """Response of the reflected path at one array (signal model of Sec. II-B/C)."""
+    lam = C_LIGHT / fc
+    d_mt = p_mt - (p_pa - (2.0 * (p_pa @ s) / (s @ s) - 1.0) * s)   # from the virtual anchor
+    w = d_mt - 2.0 * (d_mt @ s) / (s @ s) * s                        # mirrored across the surface
+    r = rot.T @ w
+    d = math.sqrt(r @ r)
+    ph = (-2.0 * math.pi * (fc + f_base)[:, None, None] * d / C_LIGHT
+          + 2.0 * math.pi / lam * (p_y[None, :, None] * r[1] / d + p_z[None, None, :] * r[2] / d))
+    return (lam / (4.0 * math.pi * d)) * np.exp(1j * ph).reshape(-1)
+
+
+def coherent_config(n_trials: int = 1024, n_cand: int = 131072, snr_db: float = 20.0, n_f: int = 10,
+                    bandwidth: float = 100e6, seed: int = SEED_BASE + 6) -> CoherentSet:
+    """J = 4 URAs of 4 x 4 elements at half a wavelength, N_f = 10 bins over
+    100 MHz at 3.5 GHz (N_z = 160); arrays near the ceiling corners of a
+    6 m x 5 m x 2.5 m room, each turned towards the room's centre; the new
+    feature is the wall x = 7 m (SFV (14, 0, 0) m); candidates are uniform in
+    the 1 m cube around it. Noise is CN(0, eta) with eta set by the sum-channel
+    SNR of Sec. V (mean power of the noise-free observation over the N_z J
+    entries, divided by the SNR). The amplitude is common to the arrays (unit
+    modulus, uniform phase per trial): the phase-coherent case the coherent
+    cost is built for."""
+    fc = 3.5e9
+    lam = C_LIGHT / fc
+    centre = np.array([4.0, 3.5])
+    pa = np.array([[1.5, 1.5, 2.5], [6.5, 1.5, 2.5], [6.5, 5.5, 2.5], [1.5, 5.5, 2.5]])
+    rots = np.stack([_rot_z(math.atan2(centre[1] - p[1], centre[0] - p[0])) for p in pa])
+    p_mt = np.array([3.2, 2.8, 1.2])
+    s_true = np.array([14.0, 0.0, 0.0])
+    n_y = n_z = 4
+    f_base = (np.arange(n_f) - (n_f - 1) / 2.0) * (bandwidth / (n_f - 1)) if n_f > 1 else np.zeros(1)
+    p_y = (np.arange(n_y) - (n_y - 1) / 2.0) * lam / 2
+    p_z = (np.arange(n_z) - (n_z - 1) / 2.0) * lam / 2
+    Psi = np.stack([_path_response(p_mt, s_true, pa[j], rots[j], f_base, p_y, p_z, fc) for j in range(4)])
+    J, N = Psi.shape
+    crng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed, spawn_key=(0xC0,))))
+    cand = s_true + crng.uniform(-0.5, 0.5, size=(n_cand, 3))
+    Z = np.empty((n_trials, J, N), np.complex64)
+    for b in range(n_trials):
+        rng = trial_rng(seed, b)
+        rho = np.exp(2j * math.pi * rng.uniform())      # one amplitude, phase-coherent across the arrays
+        clean = rho * Psi
+        eta = np.mean(np.abs(clean) ** 2) / 10 ** (snr_db / 10)
+        noise = rng.standard_normal((J, N, 2)) @ np.array([1.0, 1j]) * math.sqrt(eta / 2)
+        Z[b] = clean + noise
+    return CoherentSet(Z=Z, pa_pos=pa, pa_rot=rots, p_mt=p_mt, n_y=n_y, n_z=n_z, n_f=n_f, fc=fc,
+                       bandwidth=bandwidth, sfv_true=s_true, candidates=cand,
+                       name="coherent_j4_ura4x4_nf%d_g%d" % (n_f, n_cand))
