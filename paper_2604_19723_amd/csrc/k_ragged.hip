@@ -182,6 +182,87 @@ __device__ __attribute__((noinline)) void stage_covariance(const float2* __restr
   covariance_lds<BN>(Yb, M, T, smem);
 }
 
+// Covariance of the larger classes on the matrix cores: the real Gram matrix
+// G = sum_t z_t z_t^T of the snapshots' float views (re, im interleaved), with
+//   Re R[m][n] = G[2m][2n] + G[2m+1][2n+1],  Im R[m][n] = G[2m+1][2n] - G[2m][2n+1],
+// written to the LDS matrix R (exactly Hermitian). The 16x16 Gram tiles on or
+// above the diagonal go to the waves as tile-row pairs (w, MT-1-w); snapshot
+// chunks are staged row-major (row stride 2 MP + 16 floats).
+template <int MT>
+__device__ __attribute__((noinline)) void stage_covariance_gram(const float2* __restrict__ Yb, int M, int T,
+                                                                unsigned char* smem) {
+  constexpr int W = 16 * MT;                       // Gram columns = 2 MP
+  constexpr int LD = W + 16;
+  constexpr int TC = (kStageBytes / (LD * 4)) & ~3;  // snapshots per stage, a multiple of 4
+  static_assert(TC >= 4, "stage");
+  float2* sR = reinterpret_cast<float2*>(smem);
+  float* sZ = reinterpret_cast<float*>(smem + kOffY);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int ra = wave, rb = MT - 1 - wave;
+  const bool act = wave < (MT + 1) / 2;
+  const bool two = act && rb != ra;
+  floatx4 accA[MT], accB[MT];
+#pragma unroll
+  for (int c = 0; c < MT; ++c) {
+    accA[c] = floatx4{0.f, 0.f, 0.f, 0.f};
+    accB[c] = floatx4{0.f, 0.f, 0.f, 0.f};
+  }
+  const int fi = lane & 15, fk = lane >> 4;
+  for (int t0 = 0; t0 < T; t0 += TC) {
+    for (int v = threadIdx.x; v < TC * (W / 2); v += kThreads) {
+      const int tt = v / (W / 2), m = v - tt * (W / 2);
+      const int t = t0 + tt;
+      const float2 y = (t < T && m < M) ? Yb[int64_t(t) * M + m] : make_float2(0.f, 0.f);
+      *reinterpret_cast<float2*>(&sZ[tt * LD + 2 * m]) = y;
+    }
+    __syncthreads();
+    if (act) {
+      for (int s = 0; s < TC / 4; ++s) {
+        const float* row = sZ + (4 * s + fk) * LD + fi;
+        const float fa = row[16 * ra], fb = row[16 * rb];
+        float f[MT];
+#pragma unroll
+        for (int c = 0; c < MT; ++c) f[c] = row[16 * c];
+#pragma unroll
+        for (int c = 0; c < MT; ++c) {
+          if (c >= ra) accA[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa, f[c], accA[c], 0, 0, 0);
+          if (two && c >= rb) accB[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(fb, f[c], accB[c], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (act) {
+    const float invT = 1.0f / float(T);
+    const bool even = (lane & 1) == 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (h == 1 && !two) break;
+      const int r = h == 0 ? ra : rb;
+#pragma unroll
+      for (int c = 0; c < MT; ++c) {
+        if (c < r) continue;
+        const floatx4 a = h == 0 ? accA[c] : accB[c];
+        floatx4 x;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) x[e] = __shfl_xor(a[e], 1, 64);
+        if (!even) continue;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int m = 8 * r + 2 * fk + q;
+          const int n = 8 * c + (fi >> 1);
+          if (m >= M || n >= M || m > n) continue;
+          const float re = (a[2 * q] + x[2 * q + 1]) * invT;
+          const float im = m == n ? 0.f : (a[2 * q + 1] - x[2 * q]) * invT;
+          sR[m * M + n] = make_float2(re, im);
+          if (m != n) sR[n * M + m] = make_float2(re, -im);
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // the chunk loop for NACT active row blocks per wave (a prefix of its RB)
 template <int MP, int WR, int NACT, int RB>
 __device__ __forceinline__ void project_chunks(const RArgs& A, const float4* __restrict__ Xg, int nchunk,
@@ -284,7 +365,10 @@ __device__ __forceinline__ void trial_project(const RArgs& A, const RItem& it, c
   // 1. A operand
   float a[RB][C::KS];
   if (cov) {
-    stage_covariance<(MP >= 128 ? 8 : 4)>(Yb, M, T, smem);
+    if (MP >= 64)
+      stage_covariance_gram<MP / 8>(Yb, M, T, smem);
+    else
+      stage_covariance<4>(Yb, M, T, smem);
     const float2* sR = reinterpret_cast<const float2*>(smem);
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
