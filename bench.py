@@ -293,7 +293,7 @@ def bench_coherent(args, workers):
         bb.ba_coherent_spectrum(h, B, Z, P, ws)
         if ev is not None:
             ev[1].record()
-        bb.ba_coherent_moments(h, B, P, mc)
+        bb.ba_coherent_moments(h, B, P, mc, ws)
 
     for _ in range(args.warmup):
         step()

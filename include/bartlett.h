@@ -427,7 +427,8 @@ ba_status ba_coherent_create(ba_coherent* out, int32_t n_arrays, const double* p
 ba_status ba_coherent_destroy(ba_coherent h);
 /* n_obs = J * N_z (complex values per trial), n_cand = candidates. */
 ba_status ba_coherent_info(ba_coherent h, int32_t* n_obs, int64_t* n_cand);
-/* Workspace bytes of ba_coherent_spectrum (256-byte aligned base required). */
+/* Workspace bytes of ba_coherent_spectrum and ba_coherent_moments (one buffer
+ * serves both; 256-byte aligned base required). */
 ba_status ba_coherent_workspace_size(ba_coherent h, int32_t n_trials, size_t* bytes);
 
 /*
@@ -442,10 +443,12 @@ ba_status ba_coherent_spectrum(ba_coherent h, int32_t n_trials, const void* Z, f
 /*
  * Proposal moments over the candidates (Sec. IV-D.2): weights P / sum P, mean
  * = the candidate of maximum cost (lowest index among equal maxima),
- * covariance = weighted second central moment, in metres.
+ * covariance = weighted second central moment, in metres, evaluated in one
+ * FP64 pass as S2/S0 - mu m^T - m mu^T + mu mu^T (m the weighted mean).
  *   mu_cov  dev double [B][3 + 9].
  */
-ba_status ba_coherent_moments(ba_coherent h, int32_t n_trials, const float* P, double* mu_cov, void* stream);
+ba_status ba_coherent_moments(ba_coherent h, int32_t n_trials, const float* P, double* mu_cov, void* workspace,
+                              size_t workspace_bytes, void* stream);
 
 #ifdef __cplusplus
 }

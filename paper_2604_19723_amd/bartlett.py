@@ -91,7 +91,7 @@ _SIGS = {
     "ba_coherent_info": (_i32, [_vp, C.POINTER(_i32), C.POINTER(C.c_int64)]),
     "ba_coherent_workspace_size": (_i32, [_vp, _i32, C.POINTER(_sz)]),
     "ba_coherent_spectrum": (_i32, [_vp, _i32, _vp, _vp, _vp, _sz, _vp]),
-    "ba_coherent_moments": (_i32, [_vp, _i32, _vp, _vp, _vp]),
+    "ba_coherent_moments": (_i32, [_vp, _i32, _vp, _vp, _vp, _sz, _vp]),
     "ba_residual_covariance": (_i32, [_vp, _i32, _vp, _i32, _vp, _vp, _vp]),
     "ba_sequential_workspace_size": (_i32, [_vp, _i32, C.POINTER(_sz)]),
     "ba_sequential_peaks": (_i32, [_vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
@@ -655,10 +655,11 @@ def ba_coherent_spectrum(h: Coherent, n_trials, Z, P, workspace, stream=None):
         ws, nbytes, _stream(stream)))
 
 
-def ba_coherent_moments(h: Coherent, n_trials, P, mu_cov, stream=None):
+def ba_coherent_moments(h: Coherent, n_trials, P, mu_cov, workspace, stream=None):
+    ws, nbytes = _workspace(workspace, ba_coherent_workspace_size(h, n_trials))
     _check("ba_coherent_moments", lib().ba_coherent_moments(
         h.handle, n_trials, _dev(P, "f32", n_trials * h.n_cand, "P"), _dev(mu_cov, "f64", n_trials * 12, "mu_cov"),
-        _stream(stream)))
+        ws, nbytes, _stream(stream)))
 
 
 def coherent_workspace_for(h: Coherent, n_trials, device="cuda"):

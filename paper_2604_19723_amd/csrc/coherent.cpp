@@ -141,7 +141,10 @@ ba_status ba_coherent_info(ba_coherent h, int32_t* n_obs, int64_t* n_cand) {
 
 ba_status ba_coherent_workspace_size(ba_coherent h, int32_t n_trials, size_t* bytes) {
   if (!h || !bytes || n_trials < 0) return c_arg("ba_coherent_workspace_size", "bad argument");
-  *bytes = al(size_t(coh_row_blocks(n_trials)) * (h->Kp / 16) * 256 * sizeof(float));
+  // the trial rows of the spectrum, or the slice partials of the moments (used one after the other)
+  const size_t rows = al(size_t(coh_row_blocks(n_trials)) * (h->Kp / 16) * 256 * sizeof(float));
+  const size_t mom = al(point_moments_ws_bytes(n_trials, h->G));
+  *bytes = rows > mom ? rows : mom;
   return BA_OK;
 }
 
@@ -164,13 +167,19 @@ ba_status ba_coherent_spectrum(ba_coherent h, int32_t n_trials, const void* Z, f
   return e == hipSuccess ? BA_OK : c_dev(fn, e);
 }
 
-ba_status ba_coherent_moments(ba_coherent h, int32_t n_trials, const float* P, double* mu_cov, void* stream) {
+ba_status ba_coherent_moments(ba_coherent h, int32_t n_trials, const float* P, double* mu_cov, void* workspace,
+                              size_t workspace_bytes, void* stream) {
   static const char* fn = "ba_coherent_moments";
   if (!h) return c_arg(fn, "handle is NULL");
   if (n_trials < 0) return c_arg(fn, "n_trials >= 0 required");
   if (n_trials == 0) return BA_OK;
   if (!P || !mu_cov) return c_arg(fn, "null buffer");
-  const hipError_t e = launch_point_moments(n_trials, P, h->G, h->d_cand, 3, mu_cov, static_cast<hipStream_t>(stream));
+  size_t need = 0;
+  (void)ba_coherent_workspace_size(h, n_trials, &need);
+  if (!workspace || workspace_bytes < need) return c_arg(fn, "workspace missing or smaller than ba_coherent_workspace_size");
+  if (reinterpret_cast<uintptr_t>(workspace) & 255) return c_arg(fn, "workspace must be 256-byte aligned");
+  const hipError_t e = launch_point_moments(n_trials, P, h->G, h->d_cand, mu_cov, workspace,
+                                            static_cast<hipStream_t>(stream));
   return e == hipSuccess ? BA_OK : c_dev(fn, e);
 }
 

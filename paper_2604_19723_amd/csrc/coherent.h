@@ -24,7 +24,8 @@ int64_t coh_row_blocks(int B);
 hipError_t launch_coh_rows(const float2* Z, int B, int JNz, int Kp, float* A, hipStream_t s);
 hipError_t launch_coh_gemm(const float* A, const float* X, float* P, int B, int64_t G, int64_t ctiles, int Kp,
                            float scale, hipStream_t s);
-hipError_t launch_point_moments(int B, const float* P, int64_t G, const double* X, int d, double* mu_cov,
+size_t point_moments_ws_bytes(int B, int64_t G);
+hipError_t launch_point_moments(int B, const float* P, int64_t G, const double* X, double* mu_cov, void* ws,
                                 hipStream_t s);
 
 }  // namespace ba

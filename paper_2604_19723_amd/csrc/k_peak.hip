@@ -78,10 +78,17 @@ template <int KC>
 __global__ __launch_bounds__(256) void k_peaks(const float* __restrict__ P, int64_t G, int s1,
                                                int rows, int wrap0, int k, int* __restrict__ idx,
                                                float* __restrict__ val,
-                                               double* __restrict__ refined, int ndim) {
+                                               double* __restrict__ refined, int ndim, int staged) {
+  extern __shared__ float sRow[];  // the trial's spectrum row, when it fits
   const int64_t b = blockIdx.x;
-  const float* Pb = P + b * G;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const float* Pb = P + b * G;
+  if (staged) {
+    // one coalesced pass over the row; the neighbour tests then read LDS
+    for (int64_t g = tid; g < G; g += 256) sRow[g] = Pb[g];
+    __syncthreads();
+    Pb = sRow;
+  }
 
   float lv[KC];
   int li[KC];
@@ -272,23 +279,144 @@ __global__ __launch_bounds__(256) void k_moments(const float* __restrict__ P, in
 hipError_t launch_peaks(const Plan& p, int B, const float* P, int k, int* idx, float* val,
                         double* refined, hipStream_t s) {
   const dim3 grid{static_cast<uint32_t>(B)}, block{256u};
-  if (k <= 1)
-    hipLaunchKernelGGL(k_peaks<1>, grid, block, 0, s, P, p.G, p.shape1, p.rows, p.wrap0, k, idx, val, refined, p.ndim);
-  else if (k <= 2)
-    hipLaunchKernelGGL(k_peaks<2>, grid, block, 0, s, P, p.G, p.shape1, p.rows, p.wrap0, k, idx, val, refined, p.ndim);
-  else if (k <= 4)
-    hipLaunchKernelGGL(k_peaks<4>, grid, block, 0, s, P, p.G, p.shape1, p.rows, p.wrap0, k, idx, val, refined, p.ndim);
-  else if (k <= 8)
-    hipLaunchKernelGGL(k_peaks<8>, grid, block, 0, s, P, p.G, p.shape1, p.rows, p.wrap0, k, idx, val, refined, p.ndim);
-  else
-    hipLaunchKernelGGL(k_peaks<16>, grid, block, 0, s, P, p.G, p.shape1, p.rows, p.wrap0, k, idx, val, refined, p.ndim);
+  // stage the row in LDS when it fits beside the per-lane lists (64 KB in all)
+  const int kc = k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : k <= 8 ? 8 : 16;
+  const size_t lists = size_t(256) * kc * 8 + 1024;
+  const size_t row = size_t(p.G) * sizeof(float);
+  const int staged = lists + row <= 64 * 1024 ? 1 : 0;
+  const size_t lds = staged ? row : 0;
+#define BA_PK(KCV) \
+  hipLaunchKernelGGL(k_peaks<KCV>, grid, block, lds, s, P, p.G, p.shape1, p.rows, p.wrap0, k, idx, val, refined, \
+                     p.ndim, staged)
+  switch (kc) {
+    case 1: BA_PK(1); break;
+    case 2: BA_PK(2); break;
+    case 4: BA_PK(4); break;
+    case 8: BA_PK(8); break;
+    default: BA_PK(16); break;
+  }
+#undef BA_PK
   return hipGetLastError();
 }
 
-// the same moments over an arbitrary point set X [G][d] (no wrap)
-hipError_t launch_point_moments(int B, const float* P, int64_t G, const double* X, int d, double* mu_cov,
+// The same moments over a large point set X [G][3] (no wrap), in one pass:
+// with S0 = sum P, m = sum P x / S0 and S2 = sum P x x^T / S0,
+//   C = S2 - mu m^T - m mu^T + mu mu^T,
+// which equals sum w (x - mu)(x - mu)^T. Slices of the points go to separate
+// workgroups (FP64 partial sums and the slice's maximum), and one workgroup
+// per trial combines the slices in index order.
+constexpr int kPtSlice = 8192;
+constexpr int kPtParts = 11;  // S0, S1[3], S2[6], max value; the index goes separately
+
+__global__ __launch_bounds__(256) void k_point_partial(const float* __restrict__ P, int64_t G,
+                                                       const double* __restrict__ X, int nslice,
+                                                       double* __restrict__ part, int* __restrict__ part_idx) {
+  const int64_t b = blockIdx.x / nslice;
+  const int sl = int(blockIdx.x % nslice);
+  const float* Pb = P + b * G;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ double red[4];
+  __shared__ float wv[4];
+  __shared__ int wi[4];
+  double acc[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  float bv = -INFINITY;
+  int bi = INT_MAX;
+  const int64_t g1 = min(G, int64_t(sl + 1) * kPtSlice);
+  for (int64_t g = int64_t(sl) * kPtSlice + tid; g < g1; g += 256) {
+    const float pf = Pb[g];
+    if (better(pf, int(g), bv, bi)) {
+      bv = pf;
+      bi = int(g);
+    }
+    const double p = double(pf);
+    const double x0 = X[3 * g], x1 = X[3 * g + 1], x2 = X[3 * g + 2];
+    acc[0] += p;
+    acc[1] += p * x0;
+    acc[2] += p * x1;
+    acc[3] += p * x2;
+    acc[4] += p * x0 * x0;
+    acc[5] += p * x0 * x1;
+    acc[6] += p * x0 * x2;
+    acc[7] += p * x1 * x1;
+    acc[8] += p * x1 * x2;
+    acc[9] += p * x2 * x2;
+  }
+  double* o = part + (b * nslice + sl) * kPtParts;
+  for (int c = 0; c < 10; ++c) {
+    const double v = block_sum(acc[c], red);
+    if (tid == 0) o[c] = v;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const float ov = __shfl_xor(bv, off, 64);
+    const int oi = __shfl_xor(bi, off, 64);
+    if (better(ov, oi, bv, bi)) {
+      bv = ov;
+      bi = oi;
+    }
+  }
+  if (lane == 0) {
+    wv[wave] = bv;
+    wi[wave] = bi;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < 4; ++w)
+      if (better(wv[w], wi[w], bv, bi)) {
+        bv = wv[w];
+        bi = wi[w];
+      }
+    o[10] = double(bv);
+    part_idx[b * nslice + sl] = bi;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_point_combine(const double* __restrict__ part,
+                                                      const int* __restrict__ part_idx, int nslice,
+                                                      const double* __restrict__ X, double* __restrict__ out) {
+  const int64_t b = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  double S[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  float bv = -INFINITY;
+  int bi = INT_MAX;
+  for (int sl = 0; sl < nslice; ++sl) {
+    const double* o = part + (b * nslice + sl) * kPtParts;
+    for (int c = 0; c < 10; ++c) S[c] += o[c];
+    const float v = float(o[10]);
+    const int i = part_idx[b * nslice + sl];
+    if (i != INT_MAX && better(v, i, bv, bi)) {
+      bv = v;
+      bi = i;
+    }
+  }
+  const double nan = __longlong_as_double(0x7ff8000000000000LL);
+  double mu[3], m[3];
+  for (int a = 0; a < 3; ++a) {
+    mu[a] = bi != INT_MAX ? X[int64_t(bi) * 3 + a] : nan;
+    m[a] = S[1 + a] / S[0];
+  }
+  const int q[3][3] = {{4, 5, 6}, {5, 7, 8}, {6, 8, 9}};
+  double* o = out + b * 12;
+  for (int a = 0; a < 3; ++a) o[a] = mu[a];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      o[3 + i * 3 + j] = S[q[i][j]] / S[0] - mu[i] * m[j] - m[i] * mu[j] + mu[i] * mu[j];
+}
+
+size_t point_moments_ws_bytes(int B, int64_t G) {
+  const int64_t nslice = (G + kPtSlice - 1) / kPtSlice;
+  return size_t(B) * nslice * (kPtParts * sizeof(double) + sizeof(int)) + 256;
+}
+
+hipError_t launch_point_moments(int B, const float* P, int64_t G, const double* X, double* mu_cov, void* ws,
                                 hipStream_t s) {
-  hipLaunchKernelGGL(k_moments, dim3(unsigned(B)), dim3(256), 0, s, P, G, G, X, d, 0, mu_cov);
+  const int nslice = int((G + kPtSlice - 1) / kPtSlice);
+  double* part = static_cast<double*>(ws);
+  int* part_idx = reinterpret_cast<int*>(part + size_t(B) * nslice * kPtParts);
+  const int64_t nblk = int64_t(nslice) * B;
+  if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_point_partial, dim3(unsigned(nblk)), dim3(256), 0, s, P, G, X, nslice, part, part_idx);
+  hipLaunchKernelGGL(k_point_combine, dim3(unsigned(B)), dim3(64), 0, s, part, part_idx, nslice, X, mu_cov);
   return hipGetLastError();
 }
 

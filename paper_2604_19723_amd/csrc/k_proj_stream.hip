@@ -198,10 +198,16 @@ __global__ __launch_bounds__(64 * waves_for<PREC>(), 1) void k_proj_s(const void
           anl[r] = Qw[(int64_t(kc + 1) * NRB + rb0 + r) * 128 + 64 + lane];
         }
       }
+      // fragments of column block c + 1 are read while block c is multiplied
+      uint4 bh = lds_frag(sBd + buf * CHUNK16, lane);
+      uint4 bl = lds_frag(sBd + buf * CHUNK16, 64 + lane);
 #pragma unroll
       for (int c = 0; c < kCB; ++c) {
-        const uint4 bh = lds_frag(sBd + buf * CHUNK16, c * 128 + lane);
-        const uint4 bl = lds_frag(sBd + buf * CHUNK16, c * 128 + 64 + lane);
+        uint4 nh = bh, nl = bl;
+        if (c + 1 < kCB) {
+          nh = lds_frag(sBd + buf * CHUNK16, (c + 1) * 128 + lane);
+          nl = lds_frag(sBd + buf * CHUNK16, (c + 1) * 128 + 64 + lane);
+        }
         const bf16x8 vbh = __builtin_bit_cast(bf16x8, bh);
         const bf16x8 vbl = __builtin_bit_cast(bf16x8, bl);
 #pragma unroll
@@ -214,6 +220,8 @@ __global__ __launch_bounds__(64 * waves_for<PREC>(), 1) void k_proj_s(const void
             acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(val, vbh, acc[r][c], 0, 0, 0);
           }
         }
+        bh = nh;
+        bl = nl;
       }
       if (more) {
 #pragma unroll

@@ -76,3 +76,35 @@ def test_null_plan_and_null_out():
     assert L.ba_run(None, 1, 1, None, 1, None, None, None, None, None, 0, None) == bb.BA_ERR_ARG
     assert L.ba_peaks(None, 1, None, 1, None, None, None, None) == bb.BA_ERR_ARG
     assert L.ba_plan_destroy(None) == bb.BA_OK
+
+
+def test_new_entry_points_reject_bad_arguments_before_device_work():
+    L = bb.lib()
+    sz = C.c_size_t()
+    assert L.ba_residual_covariance(None, 1, None, 1, None, None, None) == bb.BA_ERR_ARG
+    assert L.ba_sequential_workspace_size(None, 1, C.byref(sz)) == bb.BA_ERR_ARG
+    assert L.ba_sequential_peaks(None, 1, None, 2, None, None, None, None, 0, None) == bb.BA_ERR_ARG
+    assert L.ba_proposal_sample(None, 1, None, 4, None, None, None, None) == bb.BA_ERR_ARG
+    h = C.c_void_p()
+    pos = np.zeros((4, 3))
+    rot = np.tile(np.eye(3), (4, 1, 1))
+    mt = np.array([1.0, 2.0, 1.0])
+    cand = np.array([[14.0, 0.0, 0.0]])
+    vp = lambda a: a.ctypes.data_as(C.c_void_p)
+    cases = [
+        (0, 4, 4, 10, 3.5e9, 1e8, "n_arrays"),       # no arrays
+        (4, 0, 4, 10, 3.5e9, 1e8, "n_y"),            # no elements
+        (4, 4, 4, 0, 3.5e9, 1e8, "n_f"),             # no frequencies
+        (4, 4, 4, 10, -1.0, 1e8, "fc"),              # negative carrier
+        (16, 16, 16, 10, 3.5e9, 1e8, "<= 2048"),     # observation too long
+    ]
+    for J, ny, nz, nf, fc, bw, msg in cases:
+        st = L.ba_coherent_create(C.byref(h), J, vp(pos), vp(rot), ny, nz, nf, C.c_double(fc), C.c_double(bw),
+                                  vp(mt), 1, vp(cand))
+        assert st == bb.BA_ERR_ARG and not h.value, (J, ny, nz, nf)
+        assert msg in L.ba_last_error().decode()
+    zero = np.zeros((1, 3))
+    st = L.ba_coherent_create(C.byref(h), 4, vp(pos), vp(rot), 4, 4, 10, C.c_double(3.5e9), C.c_double(1e8),
+                              vp(mt), 1, vp(zero))
+    assert st == bb.BA_ERR_ARG and "nonzero" in L.ba_last_error().decode()
+    assert L.ba_coherent_destroy(None) == bb.BA_ERR_ARG
