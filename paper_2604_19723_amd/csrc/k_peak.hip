@@ -78,17 +78,10 @@ template <int KC>
 __global__ __launch_bounds__(256) void k_peaks(const float* __restrict__ P, int64_t G, int s1,
                                                int rows, int wrap0, int k, int* __restrict__ idx,
                                                float* __restrict__ val,
-                                               double* __restrict__ refined, int ndim, int staged) {
-  extern __shared__ float sRow[];  // the trial's spectrum row, when it fits
+                                               double* __restrict__ refined, int ndim) {
   const int64_t b = blockIdx.x;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const float* Pb = P + b * G;
-  if (staged) {
-    // one coalesced pass over the row; the neighbour tests then read LDS
-    for (int64_t g = tid; g < G; g += 256) sRow[g] = Pb[g];
-    __syncthreads();
-    Pb = sRow;
-  }
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
   float lv[KC];
   int li[KC];
@@ -279,22 +272,18 @@ __global__ __launch_bounds__(256) void k_moments(const float* __restrict__ P, in
 hipError_t launch_peaks(const Plan& p, int B, const float* P, int k, int* idx, float* val,
                         double* refined, hipStream_t s) {
   const dim3 grid{static_cast<uint32_t>(B)}, block{256u};
-  // stage the row in LDS when it fits beside the per-lane lists (64 KB in all)
-  const int kc = k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : k <= 8 ? 8 : 16;
-  const size_t lists = size_t(256) * kc * 8 + 1024;
-  const size_t row = size_t(p.G) * sizeof(float);
-  const int staged = lists + row <= 64 * 1024 ? 1 : 0;
-  const size_t lds = staged ? row : 0;
 #define BA_PK(KCV) \
-  hipLaunchKernelGGL(k_peaks<KCV>, grid, block, lds, s, P, p.G, p.shape1, p.rows, p.wrap0, k, idx, val, refined, \
-                     p.ndim, staged)
-  switch (kc) {
-    case 1: BA_PK(1); break;
-    case 2: BA_PK(2); break;
-    case 4: BA_PK(4); break;
-    case 8: BA_PK(8); break;
-    default: BA_PK(16); break;
-  }
+  hipLaunchKernelGGL(k_peaks<KCV>, grid, block, 0, s, P, p.G, p.shape1, p.rows, p.wrap0, k, idx, val, refined, p.ndim)
+  if (k <= 1)
+    BA_PK(1);
+  else if (k <= 2)
+    BA_PK(2);
+  else if (k <= 4)
+    BA_PK(4);
+  else if (k <= 8)
+    BA_PK(8);
+  else
+    BA_PK(16);
 #undef BA_PK
   return hipGetLastError();
 }
