@@ -106,14 +106,29 @@ __global__ __launch_bounds__(256) void k_cov_mfma(const float2* __restrict__ Y, 
     accB[c] = floatx4{0.f, 0.f, 0.f, 0.f};
   }
   const int fi = lane & 15, fk = lane >> 4;
-  for (int t0 = 0; t0 < T; t0 += kGramChunk) {
-    for (int v = threadIdx.x; v < kGramChunk * (W / 2); v += 256) {
+  // the next chunk is loaded into registers while the current one is multiplied
+  constexpr int kPer = kGramChunk * (W / 2) / 256;  // float2 per thread and chunk
+  static_assert(kGramChunk * (W / 2) % 256 == 0, "staging split");
+  float2 yv[kPer];
+  auto load_chunk = [&](int t0) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int v = threadIdx.x + q * 256;
       const int tt = v / (W / 2), m = v - tt * (W / 2);
       const int t = t0 + tt;
-      const float2 y = (t < T && m < M) ? Yb[int64_t(t) * M + m] : make_float2(0.f, 0.f);
-      *reinterpret_cast<float2*>(&sZ[tt * LD + 2 * m]) = y;
+      yv[q] = (t < T && m < M) ? Yb[int64_t(t) * M + m] : make_float2(0.f, 0.f);
+    }
+  };
+  load_chunk(0);
+  for (int t0 = 0; t0 < T; t0 += kGramChunk) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int v = threadIdx.x + q * 256;
+      const int tt = v / (W / 2), m = v - tt * (W / 2);
+      *reinterpret_cast<float2*>(&sZ[tt * LD + 2 * m]) = yv[q];
     }
     __syncthreads();
+    if (t0 + kGramChunk < T) load_chunk(t0 + kGramChunk);
     if (act) {
 #pragma unroll 2
       for (int s = 0; s < kGramChunk / 4; ++s) {
