@@ -259,13 +259,27 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
       }
 }
 
-// db[n] = sum_m dZ[m][n], fixed summation order
-__global__ __launch_bounds__(256) void k_colsum(const float* __restrict__ dZ, float* __restrict__ db, int M, int N) {
-  const int n = blockIdx.x * 256 + threadIdx.x;
-  if (n >= N) return;
+// db[n] = sum_m dZ[m][n] in a fixed summation order: a workgroup takes 64
+// columns; its 16 waves sum interleaved rows (many loads in flight per lane),
+// and the 16 partial sums are added in wave order
+__global__ __launch_bounds__(1024) void k_colsum(const float* __restrict__ dZ, float* __restrict__ db, int M,
+                                                 int N) {
+  __shared__ float part[16][64];
+  const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int n = blockIdx.x * 64 + c;
   float s = 0.f;
-  for (int m = 0; m < M; ++m) s += dZ[int64_t(m) * N + n];
-  db[n] = s;
+  if (n < N) {
+#pragma unroll 8
+    for (int m = g; m < M; m += 16) s += dZ[int64_t(m) * N + n];
+  }
+  part[g][c] = s;
+  __syncthreads();
+  if (g == 0 && n < N) {
+    float t = 0.f;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) t += part[q][c];
+    db[n] = t;
+  }
 }
 
 // masked MSE: loss = sum m (y - t)^2 / sum m, dY = 2 m (y - t) / sum m (one workgroup)
@@ -371,7 +385,7 @@ hipError_t launch_gemm(const GemmArgs& g, int prec, hipStream_t s) {
 }
 
 hipError_t launch_colsum(const float* dZ, float* db, int M, int N, hipStream_t s) {
-  hipLaunchKernelGGL(k_colsum, dim3(unsigned((N + 255) / 256)), dim3(256), 0, s, dZ, db, M, N);
+  hipLaunchKernelGGL(k_colsum, dim3(unsigned((N + 63) / 64)), dim3(1024), 0, s, dZ, db, M, N);
   return hipGetLastError();
 }
 

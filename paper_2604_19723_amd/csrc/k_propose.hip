@@ -37,8 +37,11 @@ template <int MP>
 __global__ __launch_bounds__(256) void k_window(WindowArgs A) {
   using C = QCfg<MP>;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  float4* sX = reinterpret_cast<float4*>(smem);                                   // [kMaxWinBlocks][BLK]
-  float* sP = reinterpret_cast<float*>(smem + kMaxWinBlocks * C::BLK * 4);        // [kMaxProp][kMaxWinBlocks*16]
+  // LDS sized for the windows of this launch: nbmax blocks of one window, then
+  // the spectrum rows of the K windows
+  const int nbmax = window_blocks(A.hw);
+  float4* sX = reinterpret_cast<float4*>(smem);                                   // [nbmax][BLK]
+  float* sP = reinterpret_cast<float*>(smem + size_t(nbmax) * C::BLK * 4);        // [kMaxProp][nbmax*16]
   __shared__ float red[C::WR][16 * kMaxWinBlocks];
   __shared__ int s_lo[kMaxProp], s_hi[kMaxProp], s_jb0[kMaxProp];
   __shared__ float s_tr;
@@ -101,7 +104,7 @@ __global__ __launch_bounds__(256) void k_window(WindowArgs A) {
       float s = 0.f;
 #pragma unroll
       for (int w = 0; w < C::WR; ++w) s += red[w][t];
-      sP[k * (16 * kMaxWinBlocks) + t] = s * invM2;
+      sP[k * (16 * nbmax) + t] = s * invM2;
     }
     __syncthreads();
   }
@@ -112,7 +115,7 @@ __global__ __launch_bounds__(256) void k_window(WindowArgs A) {
     float bv = -INFINITY;
     int bi = INT_MAX;
     for (int g = lo + int(threadIdx.x); g <= hi; g += 256) {
-      const float p = sP[k * (16 * kMaxWinBlocks) + (g - base)];
+      const float p = sP[k * (16 * nbmax) + (g - base)];
       if (p == p && better(p, g, bv, bi)) {
         bv = p;
         bi = g;
@@ -173,7 +176,7 @@ __global__ __launch_bounds__(256) void k_window(WindowArgs A) {
         }
       for (int r = 0; r < K; ++r) {
         const int k = ord[r], g = s_pi[k], base = s_jb0[k] * 16;
-        const float* row = sP + k * (16 * kMaxWinBlocks) - base;
+        const float* row = sP + k * (16 * nbmax) - base;
         A.idx[b * K + r] = g;
         A.val[b * K + r] = s_pv[k];
         double d = 0.0;
@@ -212,10 +215,13 @@ __global__ void k_zero_count(int* count) {
 
 }  // namespace
 
-size_t window_lds_bytes(int Mp) { return size_t(kMaxWinBlocks) * (2 * Mp * 16) * 4 + size_t(kMaxProp) * 16 * kMaxWinBlocks * 4; }
+size_t window_lds_bytes(int Mp, int hw) {
+  const size_t nb = size_t(window_blocks(hw));
+  return nb * (2 * Mp * 16) * 4 + size_t(kMaxProp) * 16 * nb * 4;
+}
 
 hipError_t launch_window(const WindowArgs& a, int Mp, int B, hipStream_t s) {
-  const size_t lds = window_lds_bytes(Mp);
+  const size_t lds = window_lds_bytes(Mp, a.hw);
   hipError_t e = hipSuccess;
 #define BA_W(MPV)                                                                                    \
   case MPV:                                                                                          \

@@ -26,7 +26,9 @@ struct WindowArgs {
   int* fb_count;
 };
 
-size_t window_lds_bytes(int Mp);
+// 16-column blocks one window of half width hw can touch
+__host__ __device__ inline int window_blocks(int hw) { return (2 * hw) / 16 + 2; }
+size_t window_lds_bytes(int Mp, int hw);
 hipError_t launch_window(const WindowArgs& a, int Mp, int B, hipStream_t s);
 hipError_t launch_zero_count(int* count, hipStream_t s);
 hipError_t launch_gather_r(const int* list, int n, const float2* R, float2* Rc, int M, hipStream_t s);
