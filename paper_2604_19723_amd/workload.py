@@ -507,3 +507,126 @@ def coherent_config(n_trials: int = 1024, n_cand: int = 131072, snr_db: float = 
     return CoherentSet(Z=Z, pa_pos=pa, pa_rot=rots, p_mt=p_mt, n_y=n_y, n_z=n_z, n_f=n_f, fc=fc,
                        bandwidth=bandwidth, sfv_true=s_true, candidates=cand,
                        name="coherent_j4_ura4x4_nf%d_g%d" % (n_f, n_cand))
+
+
+# --------------------------------------------------------------------------- particle update messages
+
+@dataclasses.dataclass
+class MessageSet:
+    """One time step of the particle-based update messages (Sec. IV-F and
+    Supplementary Sec. S-V): the observation of every array and the particle
+    representations the messages are evaluated on. Feature s = 0 is the
+    line-of-sight path; features s >= 1 are surfaces given by their SFVs."""
+    z: np.ndarray           # complex128 [J][N_z] observation of each array
+    mt_pos: np.ndarray      # [P][3] m, MT state particles (positions)
+    w_beta: np.ndarray      # [P] MT particle weights (sum 1)
+    sfv: np.ndarray         # [S][P][3] m, SFV particles (row 0 unused: LOS)
+    gamma: np.ndarray       # [S][P] amplitude prior variance particles
+    mu: np.ndarray          # complex128 [S][P] amplitude prior mean particles
+    w_alpha: np.ndarray     # [S][P] PF particle weights (sum = existence probability)
+    zeta: np.ndarray        # [S][J] PR existence probabilities zeta(r = 1)
+    eta: np.ndarray         # [J][P] noise variance particles
+    w_xi: np.ndarray        # [J][P] noise particle weights (sum 1 per array)
+    pa_pos: np.ndarray      # [J][3] m
+    pa_rot: np.ndarray      # [J][3][3] local -> global
+    n_y: int
+    n_z: int
+    n_f: int
+    fc: float
+    bandwidth: float
+    name: str = ""
+
+    @property
+    def n_feat(self):
+        return self.gamma.shape[0]
+
+    @property
+    def n_part(self):
+        return self.mt_pos.shape[0]
+
+
+def _los_response(p_mt, p_pa, rot, f_base, p_y, p_z, fc):
+    """Response of the direct path at one array (signal model of Sec. II-B/C)."""
+    lam = C_LIGHT / fc
+    r = rot.T @ (p_mt - p_pa)
+    d = math.sqrt(r @ r)
+    ph = (-2.0 * math.pi * (fc + f_base)[:, None, None] * d / C_LIGHT
+          + 2.0 * math.pi / lam * (p_y[None, :, None] * r[1] / d + p_z[None, None, :] * r[2] / d))
+    return (lam / (4.0 * math.pi * d)) * np.exp(1j * ph).reshape(-1)
+
+
+# walls x = 1, x = 7, y = 1, y = 6 and the ceiling z = 2.5 of the room: SFV = the
+# origin mirrored across each surface
+MSG_SFVS = np.array([[2.0, 0.0, 0.0], [14.0, 0.0, 0.0], [0.0, 2.0, 0.0], [0.0, 12.0, 0.0], [0.0, 0.0, 5.0]])
+
+
+def message_config(n_part: int = 30000, n_feat: int = 6, snr_db: float = 20.0, n_f: int = 10,
+                   bandwidth: float = 100e6, spread: float = 0.05, seed: int = SEED_BASE + 7) -> MessageSet:
+    """Experiment-1 sized message workload: J = 4 URAs of 4 x 4 elements at half
+    a wavelength, N_f = 10 bins over 100 MHz at 3.5 GHz (N_z = 160), P = 30 000
+    particles, S = 6 features (LOS plus the four walls and the ceiling of a
+    6 m x 5 m x 2.5 m room). Arrays hang 0.3 m below the ceiling near its
+    corners, turned towards the room's centre.
+
+    Observation: per array, the sum over features of the path response times
+    an amplitude drawn from CN(mu_s, gamma_s) (mu_s common to the arrays:
+    |mu| = 1 for LOS, 0.6 for surfaces, uniform phase; gamma_s = 0.01 |mu_s|^2),
+    plus CN(0, eta) noise, eta set by the SNR over the mean power of the
+    noise-free observation. Particles: MT positions N(p_mt, spread^2 I); SFV
+    positions N(s_true, spread^2 I); gamma particles gamma_s U(0.5, 1.5); mu
+    particles mu_s + CN(0, (0.05 |mu_s|)^2); MT weights (1 + 0.2 U(-1, 1))
+    normalised; PF weights (existence e_s = 0.99, 0.9, 0.8, 0.7, 0.6, 0.5, ...)
+    e_s (1 + 0.2 U(-1, 1)) / sum; zeta U(0.5, 1); noise particles
+    eta U(0.5, 2), weights 1/P. With n_feat above 6, the extra features reuse
+    the surfaces in order with SFVs moved by 0.25 m."""
+    if not 1 <= n_feat <= 16:
+        raise ValueError("n_feat must be in [1, 16]")
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed, spawn_key=(0x3E55,))))
+    fc = 3.5e9
+    lam = C_LIGHT / fc
+    centre = np.array([4.0, 3.5])
+    pa = np.array([[1.5, 1.5, 2.2], [6.5, 1.5, 2.2], [6.5, 5.5, 2.2], [1.5, 5.5, 2.2]])
+    rots = np.stack([_rot_z(math.atan2(centre[1] - p[1], centre[0] - p[0])) for p in pa])
+    p_mt = np.array([3.2, 2.8, 1.2])
+    n_y = n_z = 4
+    J = len(pa)
+    f_base = (np.arange(n_f) - (n_f - 1) / 2.0) * (bandwidth / (n_f - 1)) if n_f > 1 else np.zeros(1)
+    p_y = (np.arange(n_y) - (n_y - 1) / 2.0) * lam / 2
+    p_z = (np.arange(n_z) - (n_z - 1) / 2.0) * lam / 2
+    S, P = n_feat, n_part
+    sfv_true = np.zeros((S, 3))
+    for s in range(1, S):
+        base = MSG_SFVS[(s - 1) % len(MSG_SFVS)]
+        sfv_true[s] = base + 0.25 * ((s - 1) // len(MSG_SFVS)) * base / np.linalg.norm(base)
+    mu_true = np.exp(2j * math.pi * rng.uniform(size=S)) * np.where(np.arange(S) == 0, 1.0, 0.6)
+    gamma_true = 0.01 * np.abs(mu_true) ** 2
+    N = n_f * n_y * n_z
+    clean = np.zeros((J, N), np.complex128)
+    for j in range(J):
+        for s in range(S):
+            amp = mu_true[s] + math.sqrt(gamma_true[s] / 2) * (rng.standard_normal() + 1j * rng.standard_normal())
+            if s == 0:
+                psi = _los_response(p_mt, pa[j], rots[j], f_base, p_y, p_z, fc)
+            else:
+                psi = _path_response(p_mt, sfv_true[s], pa[j], rots[j], f_base, p_y, p_z, fc)
+            clean[j] += amp * psi
+    eta_true = np.mean(np.abs(clean) ** 2) / 10 ** (snr_db / 10)
+    z = clean + math.sqrt(eta_true / 2) * (rng.standard_normal((J, N)) + 1j * rng.standard_normal((J, N)))
+    mt_pos = p_mt + spread * rng.standard_normal((P, 3))
+    w_beta = 1.0 + 0.2 * rng.uniform(-1, 1, size=P)
+    w_beta /= w_beta.sum()
+    sfv = np.zeros((S, P, 3))
+    sfv[1:] = sfv_true[1:, None, :] + spread * rng.standard_normal((S - 1, P, 3))
+    gamma = gamma_true[:, None] * rng.uniform(0.5, 1.5, size=(S, P))
+    mu = mu_true[:, None] + 0.05 * np.abs(mu_true)[:, None] * (
+        rng.standard_normal((S, P)) + 1j * rng.standard_normal((S, P))) / math.sqrt(2)
+    exist = np.array([0.99, 0.9, 0.8, 0.7, 0.6, 0.5] + [0.5] * 10)[:S]
+    w_alpha = 1.0 + 0.2 * rng.uniform(-1, 1, size=(S, P))
+    w_alpha *= (exist / w_alpha.sum(axis=1))[:, None]
+    zeta = rng.uniform(0.5, 1.0, size=(S, J))
+    eta = eta_true * rng.uniform(0.5, 2.0, size=(J, P))
+    w_xi = np.full((J, P), 1.0 / P)
+    return MessageSet(z=z, mt_pos=mt_pos, w_beta=w_beta, sfv=sfv, gamma=gamma, mu=mu, w_alpha=w_alpha,
+                      zeta=zeta, eta=eta, w_xi=w_xi, pa_pos=pa, pa_rot=rots, n_y=n_y, n_z=n_z, n_f=n_f,
+                      fc=fc, bandwidth=bandwidth,
+                      name="messages_j4_ura4x4_nf%d_s%d_p%d" % (n_f, S, P))
