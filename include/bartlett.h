@@ -450,6 +450,89 @@ ba_status ba_coherent_spectrum(ba_coherent h, int32_t n_trials, const void* Z, f
 ba_status ba_coherent_moments(ba_coherent h, int32_t n_trials, const float* P, double* mu_cov, void* workspace,
                               size_t workspace_bytes, void* stream);
 
+
+/* ---------------------------------------------------------------- particle update messages
+ *
+ * The likelihood-to-variable update messages of the particle-based BP step
+ * (Sec. IV-F; Supplementary Sec. S-V, efficient implementation), each a
+ * complex Gaussian log-density log CN(z_j; mu, C) of the observation z_j of
+ * array j with covariance eta I plus a low-rank part:
+ *   iota  MT state message at every (MT particle p, array j);
+ *   nu    noise variance message at every (noise particle eta^(j,p), array j);
+ *   kappa PF state message at every (feature s, PF particle p, array j), PF
+ *         existence r = 1, and per (s, j) at r = 0;
+ *   omega PR existence message per (s, j) at r = 0 and r = 1.
+ * Feature s = 0 is the line-of-sight path, s >= 1 surfaces given by SFVs. PF
+ * particle p of every feature is paired with MT particle p, so a_s^(j,p) is
+ * the response at array j of feature s's path for MT position x^p and SFV
+ * v_s^p (geometry of Sec. II-B, response of Sec. II-C, as for the coherent
+ * cost above: path loss included, element order b (x) a_y (x) a_z, centred
+ * half-wavelength supports and frequency bins).
+ * Moments (rho_s = sum_p w_alpha,s^p, zeta_s = zeta_s^(j)(1), eta~_j =
+ * sum_p w_xi^(j,p) eta^(j,p)):
+ *   iota: mu = sum_s zeta_s rho_s mu_s^p a_s, C = eta~ I + sum_s c_s a_s a_s^H,
+ *         c_s = zeta_s rho_s (gamma_s^p + |mu_s^p|^2 (1 - zeta_s rho_s));
+ *   kappa: mu = r zeta_s mu_s^p a_s + sum_{t != s} m3_t,
+ *          C = r q a_s a_s^H + eta~ I + sum_{t != s} m_t m_t^H,
+ *          q = zeta_s (gamma_s^p + |mu_s^p|^2 (1 - zeta_s));
+ *   omega: mu = r m4_s + sum_{t != s} m3_t, C = r w_s w_s^H + eta~ I + sum_{t != s} m_t m_t^H;
+ *   nu:   mu = sum_t m3_t, C = eta^(j,p) I + sum_t m_t m_t^H;
+ * with the particle averages (weights w_beta^p of the MT particles)
+ *   m_s = rho_s zeta_s sum_p w_beta^p sqrt(gamma_s^p + |mu_s^p|^2 (1 - zeta_s rho_s)) a_s^(j,p),
+ *   w_s = rho_s sum_p w_beta^p sqrt(gamma_s^p + |mu_s^p|^2 (1 - rho_s)) a_s^(j,p),
+ *   m4_s = rho_s sum_p w_beta^p mu_s^p a_s^(j,p), m3_s = zeta_s m4_s.
+ * Values are full log-densities (normalisation included). FP64 throughout.
+ */
+typedef struct ba_msgs_s* ba_msgs;
+
+/*
+ * Geometry of the arrays (copied to the device).
+ *   pa_pos  host double [J][3] (m); pa_rot host double [J][3][3] row-major
+ *           (local -> global); J in [1, 16].
+ *   n_y, n_z in [1, 16]; n_f in [1, 64]; N_z = n_f n_y n_z <= 1024.
+ *   fc (Hz) > 0; bandwidth (Hz) >= 0 (bins spaced bandwidth / (n_f - 1)).
+ */
+ba_status ba_msgs_create(ba_msgs* out, int32_t n_arrays, const double* pa_pos, const double* pa_rot, int32_t n_y,
+                         int32_t n_z, int32_t n_f, double fc, double bandwidth);
+ba_status ba_msgs_destroy(ba_msgs h);
+/* Workspace bytes for n_feat features and n_part particles (256-byte aligned base required). */
+ba_status ba_msgs_workspace_size(ba_msgs h, int32_t n_feat, int32_t n_part, size_t* bytes);
+
+/* One time step's inputs; every pointer is device memory, complex values are
+ * interleaved (re, im) doubles. */
+typedef struct {
+  int32_t n_feat;        /* S in [1, 16], LOS included; S (N_z + 1) <= 6144 */
+  int32_t n_part;        /* P in [1, 2^26] */
+  const void* z;         /* complex [J][N_z] observations */
+  const double* mt_pos;  /* [P][3] MT position particles (m) */
+  const double* w_beta;  /* [P] MT particle weights */
+  const double* sfv;     /* [S][P][3] SFV particles (m), nonzero for s >= 1; row 0 unused */
+  const double* gamma;   /* [S][P] amplitude prior variance particles (>= 0) */
+  const void* mu;        /* complex [S][P] amplitude prior mean particles */
+  const double* w_alpha; /* [S][P] PF particle weights (sum = existence probability) */
+  const double* zeta;    /* [S][J] PR existence probabilities zeta(r = 1) */
+  const double* eta;     /* [J][P] noise variance particles (> 0) */
+  const double* w_xi;    /* [J][P] noise particle weights */
+} ba_msg_inputs;
+
+/* Outputs (device memory, double); any may be NULL to skip it. */
+typedef struct {
+  double* log_iota;   /* [J][P] */
+  double* log_nu;     /* [J][P] */
+  double* log_kappa;  /* [S][J][P], r = 1 */
+  double* log_kappa0; /* [S][J], r = 0 */
+  double* log_omega;  /* [S][J][2], r = 0 then r = 1 */
+} ba_msg_outputs;
+
+/*
+ * Evaluate the messages of one time step. Argument errors (sizes, NULL
+ * inputs, workspace smaller than ba_msgs_workspace_size) return BA_ERR_ARG
+ * before anything is enqueued; values are not checked on the host (a
+ * non-positive eta or a zero SFV gives NaN or Inf). Asynchronous on stream.
+ */
+ba_status ba_update_messages(ba_msgs h, const ba_msg_inputs* in, const ba_msg_outputs* out, void* workspace,
+                             size_t workspace_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -49,6 +49,19 @@ _i64 = C.c_int64
 _sz = C.c_size_t
 _dp = C.POINTER(C.c_double)
 
+
+
+class MsgInputs(C.Structure):
+    """Host layout of ba_msg_inputs (device pointers)."""
+    _fields_ = [("n_feat", _i32), ("n_part", _i32), ("z", _vp), ("mt_pos", _vp), ("w_beta", _vp), ("sfv", _vp),
+                ("gamma", _vp), ("mu", _vp), ("w_alpha", _vp), ("zeta", _vp), ("eta", _vp), ("w_xi", _vp)]
+
+
+class MsgOutputs(C.Structure):
+    """Host layout of ba_msg_outputs (device pointers, NULL to skip)."""
+    _fields_ = [("log_iota", _vp), ("log_nu", _vp), ("log_kappa", _vp), ("log_kappa0", _vp), ("log_omega", _vp)]
+
+
 # name -> (restype, argtypes)
 _SIGS = {
     "ba_status_string": (C.c_char_p, [_i32]),
@@ -95,6 +108,10 @@ _SIGS = {
     "ba_residual_covariance": (_i32, [_vp, _i32, _vp, _i32, _vp, _vp, _vp]),
     "ba_sequential_workspace_size": (_i32, [_vp, _i32, C.POINTER(_sz)]),
     "ba_sequential_peaks": (_i32, [_vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "ba_msgs_create": (_i32, [C.POINTER(_vp), _i32, _vp, _vp, _i32, _i32, _i32, C.c_double, C.c_double]),
+    "ba_msgs_destroy": (_i32, [_vp]),
+    "ba_msgs_workspace_size": (_i32, [_vp, _i32, _i32, C.POINTER(_sz)]),
+    "ba_update_messages": (_i32, [_vp, C.POINTER(MsgInputs), C.POINTER(MsgOutputs), _vp, _sz, _vp]),
 }
 
 BA_ROUTE_AUTO = -1
@@ -147,7 +164,7 @@ def _stream(stream):
     return C.c_void_p(stream.cuda_stream)
 
 
-_TORCH_DT = {"c64": ("complex64", 8), "f32": ("float32", 4), "f64": ("float64", 8),
+_TORCH_DT = {"c64": ("complex64", 8), "c128": ("complex128", 16), "f32": ("float32", 4), "f64": ("float64", 8),
              "i32": ("int32", 4), "u8": ("uint8", 1), "bf16": ("bfloat16", 2)}
 
 
@@ -665,3 +682,86 @@ def ba_coherent_moments(h: Coherent, n_trials, P, mu_cov, workspace, stream=None
 def coherent_workspace_for(h: Coherent, n_trials, device="cuda"):
     import torch
     return torch.empty(max(ba_coherent_workspace_size(h, n_trials), 256), dtype=torch.uint8, device=device)
+
+
+# --------------------------------------------------------------------------- particle update messages
+
+class Messages:
+    """Owns a ba_msgs handle (array geometry on the device)."""
+
+    def __init__(self, handle, n_arrays, n_obs):
+        self.handle, self.J, self.n_obs = handle, n_arrays, n_obs
+
+    def close(self):
+        if self.handle:
+            ba_msgs_destroy(self)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ba_msgs_create(pa_pos, pa_rot, n_y, n_z, n_f, fc, bandwidth) -> Messages:
+    pa = np.ascontiguousarray(np.asarray(pa_pos, np.float64).reshape(-1, 3))
+    J = pa.shape[0]
+    rot = _host_f64(pa_rot, 9 * J, "pa_rot")
+    h = C.c_void_p()
+    _check("ba_msgs_create", lib().ba_msgs_create(C.byref(h), J, pa.ctypes.data_as(_vp), rot.ctypes.data_as(_vp),
+                                                  n_y, n_z, n_f, float(fc), float(bandwidth)))
+    return Messages(h, J, n_f * n_y * n_z)
+
+
+def ba_msgs_destroy(h: Messages):
+    _check("ba_msgs_destroy", lib().ba_msgs_destroy(h.handle))
+
+
+def ba_msgs_workspace_size(h: Messages, n_feat, n_part) -> int:
+    b = _sz()
+    _check("ba_msgs_workspace_size", lib().ba_msgs_workspace_size(h.handle, n_feat, n_part, C.byref(b)))
+    return b.value
+
+
+def messages_workspace_for(h: Messages, n_feat, n_part, device="cuda"):
+    import torch
+    return torch.empty(max(ba_msgs_workspace_size(h, n_feat, n_part), 256), dtype=torch.uint8, device=device)
+
+
+def ba_update_messages(h: Messages, n_feat, n_part, z, mt_pos, w_beta, sfv, gamma, mu, w_alpha, zeta, eta, w_xi,
+                       workspace, log_iota=None, log_nu=None, log_kappa=None, log_kappa0=None, log_omega=None,
+                       stream=None):
+    """All tensors on the device: z complex128 [J][N_z], mt_pos [P][3], w_beta [P],
+    sfv [S][P][3], gamma [S][P], mu complex128 [S][P], w_alpha [S][P], zeta [S][J],
+    eta [J][P], w_xi [J][P] (float64); outputs float64 log_iota/log_nu [J][P],
+    log_kappa [S][J][P], log_kappa0 [S][J], log_omega [S][J][2] (None skips)."""
+    S, P, J = int(n_feat), int(n_part), h.J
+    ws, nbytes = _workspace(workspace, ba_msgs_workspace_size(h, S, P))
+    mi = MsgInputs(S, P, _dev(z, "c128", J * h.n_obs, "z"), _dev(mt_pos, "f64", 3 * P, "mt_pos"),
+                   _dev(w_beta, "f64", P, "w_beta"), _dev(sfv, "f64", 3 * S * P, "sfv"),
+                   _dev(gamma, "f64", S * P, "gamma"), _dev(mu, "c128", S * P, "mu"),
+                   _dev(w_alpha, "f64", S * P, "w_alpha"), _dev(zeta, "f64", S * J, "zeta"),
+                   _dev(eta, "f64", J * P, "eta"), _dev(w_xi, "f64", J * P, "w_xi"))
+    mo = MsgOutputs(_dev(log_iota, "f64", J * P, "log_iota", True), _dev(log_nu, "f64", J * P, "log_nu", True),
+                    _dev(log_kappa, "f64", S * J * P, "log_kappa", True),
+                    _dev(log_kappa0, "f64", S * J, "log_kappa0", True),
+                    _dev(log_omega, "f64", 2 * S * J, "log_omega", True))
+    _check("ba_update_messages", lib().ba_update_messages(h.handle, C.byref(mi), C.byref(mo), ws, nbytes,
+                                                          _stream(stream)))
+
+
+def message_tensors(ms, device="cuda"):
+    """The arrays of a workload.MessageSet as contiguous device tensors, keyed
+    by the argument names of ba_update_messages."""
+    import torch
+    f64 = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float64)).to(device)
+    c128 = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.complex128)).to(device)
+    return dict(z=c128(ms.z), mt_pos=f64(ms.mt_pos), w_beta=f64(ms.w_beta), sfv=f64(ms.sfv), gamma=f64(ms.gamma),
+                mu=c128(ms.mu), w_alpha=f64(ms.w_alpha), zeta=f64(ms.zeta), eta=f64(ms.eta), w_xi=f64(ms.w_xi))

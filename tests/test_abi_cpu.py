@@ -108,3 +108,32 @@ def test_new_entry_points_reject_bad_arguments_before_device_work():
                               vp(mt), 1, vp(zero))
     assert st == bb.BA_ERR_ARG and "nonzero" in L.ba_last_error().decode()
     assert L.ba_coherent_destroy(None) == bb.BA_ERR_ARG
+
+
+def test_message_entry_points_reject_bad_arguments_before_device_work():
+    L = bb.lib()
+    sz = C.c_size_t()
+    h = C.c_void_p()
+    pos = np.zeros((4, 3))
+    rot = np.tile(np.eye(3), (4, 1, 1))
+    vp = lambda a: a.ctypes.data_as(C.c_void_p)
+    cases = [
+        (0, 4, 4, 10, 3.5e9, 1e8, "n_arrays"),
+        (17, 4, 4, 10, 3.5e9, 1e8, "n_arrays"),
+        (4, 4, 0, 10, 3.5e9, 1e8, "n_y"),
+        (4, 4, 4, 65, 3.5e9, 1e8, "n_f"),
+        (4, 16, 16, 8, 3.5e9, 1e8, "<= 1024"),
+        (4, 4, 4, 10, 0.0, 1e8, "fc"),
+        (4, 4, 4, 10, 3.5e9, -1.0, "bandwidth"),
+    ]
+    for J, ny, nz, nf, fc, bw, msg in cases:
+        st = L.ba_msgs_create(C.byref(h), J, vp(pos), vp(rot), ny, nz, nf, C.c_double(fc), C.c_double(bw))
+        assert st == bb.BA_ERR_ARG and not h.value, (J, ny, nz, nf, fc, bw)
+        assert msg in L.ba_last_error().decode()
+    assert L.ba_msgs_create(C.byref(h), 4, None, vp(rot), 4, 4, 10, C.c_double(3.5e9), C.c_double(1e8)) == \
+        bb.BA_ERR_ARG
+    assert L.ba_msgs_destroy(None) == bb.BA_ERR_ARG
+    assert L.ba_msgs_workspace_size(None, 6, 100, C.byref(sz)) == bb.BA_ERR_ARG
+    mi = bb.MsgInputs(6, 100)
+    mo = bb.MsgOutputs()
+    assert L.ba_update_messages(None, C.byref(mi), C.byref(mo), None, 0, None) == bb.BA_ERR_ARG

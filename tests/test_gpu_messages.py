@@ -1,0 +1,136 @@
+"""Particle update messages through the C-ABI against the FP64 oracle on the
+same seeded inputs. The oracle forms every covariance densely and takes the
+log-density with an LU solve and log-determinant; the kernels use the
+inversion and determinant lemmas with Kronecker-structured steering vectors,
+so agreement checks both the algebra and the geometry.
+
+Tolerance: every value is FP64 on both sides; the dense LU and the S x S
+Cholesky of I + G/eta differ in rounding by about eps times the condition
+number of C (below 1e5 here) times the magnitude of the terms that cancel in
+the quadratic form (|z|^2 / eta, about N_z * SNR). Hence
+|gpu - oracle| <= 1e-9 * (|oracle| + |z|^2 / eta~).
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import messages as om
+from paper_2604_19723_amd import bartlett as bb
+from paper_2604_19723_amd import workload as wl
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def run(ms, which=("iota", "nu", "kappa", "kappa0", "omega")):
+    S, P, J = ms.n_feat, ms.n_part, len(ms.pa_pos)
+    shapes = {"iota": (J, P), "nu": (J, P), "kappa": (S, J, P), "kappa0": (S, J), "omega": (S, J, 2)}
+    outs = {k: torch.full(shapes[k], float("nan"), dtype=torch.float64, device=DEV) for k in which}
+    with bb.ba_msgs_create(ms.pa_pos, ms.pa_rot, ms.n_y, ms.n_z, ms.n_f, ms.fc, ms.bandwidth) as h:
+        ws = bb.messages_workspace_for(h, S, P, DEV)
+        bb.ba_update_messages(h, S, P, workspace=ws, **bb.message_tensors(ms, DEV),
+                              **{"log_" + k: v for k, v in outs.items()})
+        torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in outs.items()}
+
+
+def scale(ms):
+    eta = om.noise_mean(ms)
+    return np.sum(np.abs(ms.z) ** 2, axis=1) / eta  # per array
+
+
+def close(got, ref, sc, what):
+    err = np.abs(got - ref)
+    bound = 1e-9 * (np.abs(ref) + sc)
+    assert np.all(np.isfinite(got)), what
+    assert np.all(err <= bound), "%s: max err %.3e (bound %.3e)" % (what, err.max(), bound[err > bound].min())
+
+
+@pytest.mark.parametrize("S,P,n_f", [(6, 37, 10), (1, 5, 10), (3, 64, 4), (9, 20, 2), (6, 1, 10)])
+def test_messages_match_oracle(S, P, n_f):
+    ms = wl.message_config(n_part=P, n_feat=S, n_f=n_f, seed=wl.SEED_BASE + 100 + S + P)
+    got = run(ms)
+    sc = scale(ms)
+    avg = om.particle_averages(ms)
+    close(got["iota"], om.mt_message(ms), sc[:, None], "iota")
+    close(got["nu"], om.noise_message(ms, avg=avg), sc[:, None], "nu")
+    k1, k0 = om.pf_message(ms, avg=avg)
+    close(got["kappa"], k1, sc[None, :, None], "kappa")
+    close(got["kappa0"], k0, sc[None, :], "kappa0")
+    close(got["omega"], om.pr_message(ms, avg=avg), sc[None, :, None], "omega")
+
+
+def test_two_reduction_chunks_and_a_ragged_tail():
+    # 1100 particles: two 1024-particle chunks of the particle sums, and the
+    # last workgroup of the per-particle kernels only partly filled
+    ms = wl.message_config(n_part=1100, n_feat=4, n_f=4, seed=wl.SEED_BASE + 211)
+    got = run(ms)
+    sc = scale(ms)
+    avg = om.particle_averages(ms)
+    parts = [0, 1, 511, 1023, 1024, 1031, 1099]
+    close(got["iota"][:, parts], om.mt_message(ms, parts=parts), sc[:, None], "iota")
+    close(got["nu"][:, parts], om.noise_message(ms, parts=parts, avg=avg), sc[:, None], "nu")
+    k1, k0 = om.pf_message(ms, parts=parts, avg=avg)
+    close(got["kappa"][:, :, parts], k1, sc[None, :, None], "kappa")
+    close(got["kappa0"], k0, sc[None, :], "kappa0")
+    close(got["omega"], om.pr_message(ms, avg=avg), sc[None, :, None], "omega")
+
+
+def test_experiment_size_sampled():
+    # the benchmark's workload (P = 30 000, S = 6, J = 4, N_z = 160) in its
+    # launch configuration; the oracle evaluates sampled particles
+    ms = wl.message_config()
+    got = run(ms)
+    sc = scale(ms)
+    avg = om.particle_averages(ms)
+    rng = np.random.default_rng(4)
+    parts = sorted(set([0, ms.n_part - 1] + list(rng.integers(0, ms.n_part, 10))))
+    close(got["iota"][:, parts], om.mt_message(ms, parts=parts), sc[:, None], "iota")
+    close(got["nu"][:, parts], om.noise_message(ms, parts=parts, avg=avg), sc[:, None], "nu")
+    k1, k0 = om.pf_message(ms, parts=parts, avg=avg)
+    close(got["kappa"][:, :, parts], k1, sc[None, :, None], "kappa")
+    close(got["kappa0"], k0, sc[None, :], "kappa0")
+    close(got["omega"], om.pr_message(ms, avg=avg), sc[None, :, None], "omega")
+    for k in ("iota", "nu", "kappa"):
+        assert np.all(np.isfinite(got[k])), k
+
+
+def test_outputs_are_optional_and_repeatable():
+    ms = wl.message_config(n_part=50, n_feat=5, n_f=4, seed=wl.SEED_BASE + 212)
+    a = run(ms)
+    b = run(ms, which=("kappa",))
+    c = run(ms, which=("iota", "omega"))
+    np.testing.assert_array_equal(a["kappa"], b["kappa"])
+    np.testing.assert_array_equal(a["iota"], c["iota"])
+    np.testing.assert_array_equal(a["omega"], c["omega"])
+
+
+def test_message_argument_errors():
+    ms = wl.message_config(n_part=8, n_feat=3, n_f=2)
+    with pytest.raises(bb.BartlettError):
+        bb.ba_msgs_create(ms.pa_pos, ms.pa_rot, 16, 16, 8, ms.fc, ms.bandwidth)   # N_z > 1024
+    with pytest.raises(bb.BartlettError):
+        bb.ba_msgs_create(ms.pa_pos, ms.pa_rot, 4, 4, 2, -1.0, ms.bandwidth)
+    with bb.ba_msgs_create(ms.pa_pos, ms.pa_rot, ms.n_y, ms.n_z, ms.n_f, ms.fc, ms.bandwidth) as h:
+        with pytest.raises(bb.BartlettError):
+            bb.ba_msgs_workspace_size(h, 17, 8)
+        with pytest.raises(bb.BartlettError):
+            bb.ba_msgs_workspace_size(h, 3, 0)
+        t = bb.message_tensors(ms, DEV)
+        ws = bb.messages_workspace_for(h, 3, 8, DEV)
+        out = torch.empty((4, 8), dtype=torch.float64, device=DEV)
+        order = ("z", "mt_pos", "w_beta", "sfv", "gamma", "mu", "w_alpha", "zeta", "eta", "w_xi")
+        ptrs = [C.c_void_p(t[k].data_ptr()) for k in order]
+        mo = bb.MsgOutputs(C.c_void_p(out.data_ptr()), None, None, None, None)
+        call = lambda mi, nbytes: bb.lib().ba_update_messages(h.handle, C.byref(mi), C.byref(mo),
+                                                              C.c_void_p(ws.data_ptr()), nbytes, None)
+        assert call(bb.MsgInputs(3, 8, *ptrs), 256) == bb.BA_ERR_ARG          # workspace too small
+        assert call(bb.MsgInputs(17, 8, *ptrs), ws.numel()) == bb.BA_ERR_ARG  # too many features
+        assert call(bb.MsgInputs(3, 0, *ptrs), ws.numel()) == bb.BA_ERR_ARG   # no particles
+        assert call(bb.MsgInputs(3, 8, *(ptrs[:3] + [None] + ptrs[4:])), ws.numel()) == bb.BA_ERR_ARG
+        assert call(bb.MsgInputs(3, 8, *ptrs), ws.numel()) == bb.BA_OK
+        torch.cuda.synchronize()
+        assert torch.isfinite(out).all()
