@@ -470,6 +470,140 @@ def bench_learned(args, workers):
     return 0
 
 
+def message_flops(S, P, J, nf, ny, nz):
+    """Algorithmic FP64 flops of one message step: (reduction, pair kernel, PF kernel).
+    A Kronecker contraction a^H X costs Kc = N_z + N_f N_y + N_f complex MACs (8 flops);
+    a Gram entry <a_s, a_t> Nt = N_f + N_y + N_z; an S x S Cholesky 8 S^3 / 6, a solve 4 S^2."""
+    Nz, Kc, Nt = nf * ny * nz, nf * ny * nz + nf * ny + nf, nf + ny + nz
+    chol = 8.0 * S ** 3 / 6 + 4.0 * S * S
+    red = 28.0 * Nz * S * J * P
+    pair = J * P * (8.0 * S * Kc + 8.0 * S * S * Nt + 2 * chol)
+    pf = S * J * P * (8.0 * S * Kc + 4.0 * S * S)
+    return red, pair, pf
+
+
+def bench_messages(args, workers):
+    """Particle update messages of one BP time step (Sec. IV-F, Supplement
+    S-V) at the Experiment-1 size: P = 30 000 particles, J = 4 URAs (4 x 4,
+    10 bins: N_z = 160), S = 6 features (LOS + 5 surfaces). One step = one
+    ba_update_messages call: particle sums, per-(feature, array) setup, MT and
+    noise messages at every (particle, array), PF messages at every (feature,
+    particle, array), PR messages."""
+    from paper_2604_19723_amd import workload as wl
+    P = args.trials if args.trials != 10000 else 30000
+    t = time.perf_counter()
+    ms = wl.message_config(n_part=P)
+    log("generated the message workload (P = %d) in %.1f s" % (P, time.perf_counter() - t))
+    import torch
+    from paper_2604_19723_amd import bartlett as bb
+    dev = torch.device("cuda:0")
+    S, J = ms.n_feat, len(ms.pa_pos)
+    h = bb.ba_msgs_create(ms.pa_pos, ms.pa_rot, ms.n_y, ms.n_z, ms.n_f, ms.fc, ms.bandwidth)
+    tens = bb.message_tensors(ms, dev)
+    out = dict(log_iota=torch.empty((J, P), dtype=torch.float64, device=dev),
+               log_nu=torch.empty((J, P), dtype=torch.float64, device=dev),
+               log_kappa=torch.empty((S, J, P), dtype=torch.float64, device=dev),
+               log_kappa0=torch.empty((S, J), dtype=torch.float64, device=dev),
+               log_omega=torch.empty((S, J, 2), dtype=torch.float64, device=dev))
+    ws = bb.messages_workspace_for(h, S, P, dev)
+    variants = {"all": out, "prep": {"log_kappa0": out["log_kappa0"]},
+                "pf": {"log_kappa": out["log_kappa"]}}
+
+    def call(which):
+        bb.ba_update_messages(h, S, P, workspace=ws, **tens, **variants[which])
+
+    def timed(which, n):
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+        for a, b in evs:
+            a.record()
+            call(which)
+            b.record()
+        torch.cuda.synchronize()
+        return float(np.mean([a.elapsed_time(b) for a, b in evs]))
+
+    for _ in range(args.warmup):
+        call("all")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        call("all")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_all = timed("all", args.steps)
+    ms_prep = timed("prep", args.steps)
+    ms_pf = timed("pf", args.steps)
+    pf_ms = ms_pf - ms_prep
+    log("timed %d steps: %.3f ms/step (events %.3f ms; prep %.3f ms; PF kernel %.3f ms)" % (
+        args.steps, dt / args.steps * 1e3, ms_all, ms_prep, pf_ms))
+    red, pair, pf = message_flops(S, P, J, ms.n_f, ms.n_y, ms.n_z)
+    achieved = pf / (pf_ms * 1e-3) / 1e12
+    step_tf = (red + pair + pf) / (ms_all * 1e-3) / 1e12
+    got = {k: v.cpu().numpy() for k, v in out.items()}
+    # spot parity: three particles against the dense FP64 oracle
+    from oracle import messages as om
+    parts = [0, P // 2, P - 1]
+    ref = om.mt_message(ms, parts=parts)
+    spot = float(np.max(np.abs(got["log_iota"][:, parts] - ref) / np.abs(ref)))
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = message_cpu_baseline(ms, args.cpu_seconds)
+    value = args.steps / dt
+    line = {
+        "metric": "MC trials/sec and grid-points*trials/sec at fixed RMSE; % MFMA/HBM peak",
+        "value": value, "unit": "time steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded: 4 URAs in a room, LOS + 5 surfaces, particle clouds around the truth, "
+                "SNR 20 dB)",
+        "config": {"workload": ms.name, "particles": P, "features": S, "arrays": J,
+                   "n_obs": ms.n_f * ms.n_y * ms.n_z},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": 78.6, "unit": "TFLOP/s",
+                     "frac": achieved / 78.6, "traffic": None, "kernel": "k_msg_kappa",
+                     "kernel_ms": pf_ms, "flops_per_launch": pf},
+        "cpu_baseline": cpu,
+        "pair_messages_per_s": value * J * P,
+        "step_tflops_f64": step_tf,
+        "step_flops": red + pair + pf,
+        "event_ms": {"all": ms_all, "prep": ms_prep, "prep_plus_pf": ms_pf},
+    }
+    line["spot_parity_rel_max"] = spot
+    print(json.dumps(line), flush=True)
+    h.close()
+    return 0
+
+
+def message_cpu_baseline(ms, seconds):
+    """The FP64 oracle on a sample of particles: particle sums over the sample,
+    then every message at the sample's particles; scaled to the full P (all
+    parts are linear in P)."""
+    import dataclasses
+    from oracle import messages as om
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        cores = max([i.get("num_threads", 1) for i in info if i.get("user_api") == "blas"] or [1])
+    except Exception:
+        cores = None
+    n, dt = 0, 0.0
+    for n in (2, 4, 8, 16, 32, 64, 128, 256):
+        sub = dataclasses.replace(ms, mt_pos=ms.mt_pos[:n], w_beta=ms.w_beta[:n], sfv=ms.sfv[:, :n],
+                                  gamma=ms.gamma[:, :n], mu=ms.mu[:, :n], w_alpha=ms.w_alpha[:, :n],
+                                  eta=ms.eta[:, :n], w_xi=ms.w_xi[:, :n])
+        t0 = time.perf_counter()
+        avg = om.particle_averages(sub)
+        om.mt_message(sub)
+        om.noise_message(sub, avg=avg)
+        om.pf_message(sub, avg=avg)
+        om.pr_message(sub, avg=avg)
+        dt = time.perf_counter() - t0
+        if dt > seconds / 3:
+            break
+    per_step = dt * ms.n_part / n
+    return {"value": 1.0 / per_step, "unit": "time steps/s", "cores": cores, "kind": "oracle",
+            "sample": "%d of %d particles (all messages + particle sums over the sample, dense FP64 "
+                      "numpy), %.1f s, scaled by P" % (n, ms.n_part, dt)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -478,7 +612,8 @@ def main():
     ap.add_argument("--trials", type=int, default=10000)
     ap.add_argument("--precision", default="f32", choices=sorted(PEAK))
     ap.add_argument("--workload", default="ula64",
-                    choices=["ula64", "ura256", "ragged", "learned", "sequential", "proposal", "coherent"],
+                    choices=["ula64", "ura256", "ragged", "learned", "sequential", "proposal", "coherent",
+                             "messages"],
                     help="ula64: 64-element ULA, 7201-point grid (default); ura256: 16x16 URA, "
                          "361x181 az/el grid; ragged: 50 000 uneven trials (M 8..128, T 16..2048) "
                          "in one persistent launch under a HIP graph")
@@ -510,6 +645,8 @@ def main():
         return bench_proposal(args, workers)
     if args.workload == "coherent":
         return bench_coherent(args, workers)
+    if args.workload == "messages":
+        return bench_messages(args, workers)
     t = time.perf_counter()
     if args.workload == "ula64":
         ts = wl.config2(args.trials, dtype=np.complex64, workers=workers)   # before the GPU is touched

@@ -501,7 +501,7 @@ ba_status ba_msgs_workspace_size(ba_msgs h, int32_t n_feat, int32_t n_part, size
 /* One time step's inputs; every pointer is device memory, complex values are
  * interleaved (re, im) doubles. */
 typedef struct {
-  int32_t n_feat;        /* S in [1, 16], LOS included; S (N_z + 1) <= 6144 */
+  int32_t n_feat;        /* S in [1, 16], LOS included */
   int32_t n_part;        /* P in [1, 2^26] */
   const void* z;         /* complex [J][N_z] observations */
   const double* mt_pos;  /* [P][3] MT position particles (m) */

@@ -11,7 +11,7 @@
 // (delay over the bins, horizontal and vertical phase over the elements;
 // Sec. II-C). Hence
 //   * a^H X for a dense X is a three-level contraction (N_z + N_f N_y + N_f
-//     complex MACs) with the sequences generated by recurrence;
+//     complex MACs);
 //   * <a_s, a_t> is a product of three sums of N_f, N_y, N_z terms.
 // With these, the MT message's per-pair cost is O(S (N_z + S (N_f + N_y +
 // N_z)) + S^3) instead of the O(N_z S^2) of the dense Gram.
@@ -28,7 +28,8 @@
 //                  GS lanes per pair, lane s owning feature s (row s of the
 //                  S x S system; Cholesky and solves across the group);
 //   k_msg_kappa    per (feature, particle, array): the PF message at r = 1,
-//                  lane t contracting the path with column t (or with z').
+//                  one thread per particle contracting its path with every
+//                  column (and with z'), columns read wave-uniformly.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -49,19 +50,46 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return {a.x + b.
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return {a.x - b.x, a.y - b.y}; }
 __device__ __forceinline__ double2 cscale(double a, double2 b) { return {a * b.x, a * b.y}; }
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+  return {fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x)};
 }
 // conj(a) * b
 __device__ __forceinline__ double2 cmulc(double2 a, double2 b) {
-  return {a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x};
+  return {fma(a.x, b.x, a.y * b.y), fma(a.x, b.y, -a.y * b.x)};
+}
+// acc + a * b and acc + conj(a) * b, four FMAs each
+__device__ __forceinline__ double2 cmac(double2 acc, double2 a, double2 b) {
+  return {fma(a.x, b.x, fma(-a.y, b.y, acc.x)), fma(a.x, b.y, fma(a.y, b.x, acc.y))};
+}
+__device__ __forceinline__ double2 cmacc(double2 acc, double2 a, double2 b) {
+  return {fma(a.x, b.x, fma(a.y, b.y, acc.x)), fma(a.x, b.y, fma(-a.y, b.x, acc.y))};
 }
 __device__ __forceinline__ double2 cconj(double2 a) { return {a.x, -a.y}; }
-__device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+__device__ __forceinline__ double cabs2(double2 a) { return fma(a.x, a.x, a.y * a.y); }
 __device__ __forceinline__ double2 cexpi(double t) {
   double s, c;
   sincos(t, &s, &c);
   return {c, s};
 }
+// x^n by squaring (n >= 0, uniform across the wave)
+__device__ __forceinline__ double2 cpowi(double2 x, int n) {
+  double2 r = {1.0, 0.0};
+  while (n) {
+    if (n & 1) r = cmul(r, x);
+    x = cmul(x, x);
+    n >>= 1;
+  }
+  return r;
+}
+
+// Read-only vectors that every lane of a wave reads at the same index go
+// through the constant address space, so the loads are wave-uniform (scalar
+// registers feed the FMAs) instead of one LDS or vector load per lane.
+struct cplx {
+  double x, y;
+};
+typedef const __attribute__((address_space(4))) cplx* cvec;
+__device__ __forceinline__ cvec uniform_vec(const double2* p) { return (cvec)(p); }
+__device__ __forceinline__ double2 ld(cvec p, int i) { return {p[i].x, p[i].y}; }
 
 template <int W>
 __device__ __forceinline__ double2 gshfl(double2 v, int src) {
@@ -113,37 +141,56 @@ __device__ Kron path_kron(const MsgGeom& G, int j, const double* __restrict__ x,
   const double lam = kC / G.fc;
   Kron k;
   k.g = cscale(lam / (4.0 * kPi * d), cexpi(-2.0 * kPi * G.fc * d / kC));
-  const double tf = -2.0 * kPi * G.df * d / kC;
-  const double ty = kPi * r1 / d, tz = kPi * r2 / d;
-  k.b0 = cexpi(-tf * 0.5 * (G.nf - 1));
-  k.bs = cexpi(tf);
-  k.y0 = cexpi(-ty * 0.5 * (G.ny - 1));
-  k.ys = cexpi(ty);
-  k.z0 = cexpi(-tz * 0.5 * (G.nz - 1));
-  k.zs = cexpi(tz);
+  // step e^{j theta} = h^2 and first term e^{-j theta (n-1)/2} = conj(h)^(n-1), h = e^{j theta / 2}
+  const double2 hf = cexpi(-kPi * G.df * d / kC);
+  const double2 hy = cexpi(0.5 * kPi * r1 / d), hz = cexpi(0.5 * kPi * r2 / d);
+  k.bs = cmul(hf, hf);
+  k.ys = cmul(hy, hy);
+  k.zs = cmul(hz, hz);
+  k.b0 = cpowi(cconj(hf), G.nf - 1);
+  k.y0 = cpowi(cconj(hy), G.ny - 1);
+  k.z0 = cpowi(cconj(hz), G.nz - 1);
   return k;
 }
 
-// a^H X = conj(g) sum_f conj(b_f) sum_i conj(y_i) sum_l conj(z_l) X[f][i][l]
-__device__ double2 contract(const Kron& k, const double2* X, int nf, int ny, int nz) {
+// a^H X = conj(g) sum_f conj(b_f) sum_i conj(y_i) sum_l conj(z_l) X[f][i][l],
+// X read wave-uniformly; NZ > 0 fixes N_z at compile time (the vertical
+// phasors then sit in registers instead of being generated by recurrence).
+template <int NZ>
+__device__ double2 contract(const Kron& k, cvec X, int nf, int ny, int nzr) {
+  const int nz = NZ > 0 ? NZ : nzr;
+  const double2 bsc = cconj(k.bs), ysc = cconj(k.ys), zsc = cconj(k.zs);
+  double2 zc[NZ > 0 ? NZ : 1];
+  if constexpr (NZ > 0) {
+    double2 v = cconj(k.z0);
+#pragma unroll
+    for (int l = 0; l < NZ; ++l) {
+      zc[l] = v;
+      v = cmul(v, zsc);
+    }
+  }
   double2 af = {0.0, 0.0};
   double2 bf = cconj(k.b0);
-  const double2 bsc = cconj(k.bs), ysc = cconj(k.ys), zsc = cconj(k.zs);
   for (int f = 0; f < nf; ++f) {
     double2 ai = {0.0, 0.0};
     double2 yi = cconj(k.y0);
     for (int i = 0; i < ny; ++i) {
-      const double2* row = X + (f * ny + i) * nz;
+      const int base = (f * ny + i) * nz;
       double2 al = {0.0, 0.0};
-      double2 zl = cconj(k.z0);
-      for (int l = 0; l < nz; ++l) {
-        al = cadd(al, cmul(zl, row[l]));
-        zl = cmul(zl, zsc);
+      if constexpr (NZ > 0) {
+#pragma unroll
+        for (int l = 0; l < NZ; ++l) al = cmac(al, zc[l], ld(X, base + l));
+      } else {
+        double2 zl = cconj(k.z0);
+        for (int l = 0; l < nz; ++l) {
+          al = cmac(al, zl, ld(X, base + l));
+          zl = cmul(zl, zsc);
+        }
       }
-      ai = cadd(ai, cmul(yi, al));
+      ai = cmac(ai, yi, al);
       yi = cmul(yi, ysc);
     }
-    af = cadd(af, cmul(bf, ai));
+    af = cmac(af, bf, ai);
     bf = cmul(bf, bsc);
   }
   return cmulc(k.g, af);
@@ -249,12 +296,13 @@ MsgWs carve(void* base, const MsgGeom& g, int S, int P, size_t* total) {
   return w;
 }
 
-// Fixed-order sum over a workgroup of 256 threads (result valid in thread 0).
+// Fixed-order sum over a workgroup of NT threads (result valid in thread 0).
+template <int NT>
 __device__ double block_sum(double v, double* red) {
   red[threadIdx.x] = v;
   __syncthreads();
 #pragma unroll
-  for (int w = 128; w >= 1; w >>= 1) {
+  for (int w = NT / 2; w >= 1; w >>= 1) {
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
@@ -263,23 +311,24 @@ __device__ double block_sum(double v, double* red) {
 
 // rho_s = sum_p w_alpha,s^p (workgroups 0..S-1); eta~_j = sum_p w_xi^(j,p)
 // eta^(j,p) (workgroups S..S+J-1)
-__global__ __launch_bounds__(256) void k_msg_scalars(MsgIn in, int J, double* __restrict__ rho,
-                                                     double* __restrict__ etam) {
-  __shared__ double red[256];
-  const int b = blockIdx.x;
-  double acc = 0.0;
-  if (b < in.S) {
-    const double* w = in.wa + int64_t(b) * in.P;
-    for (int p = threadIdx.x; p < in.P; p += 256) acc += w[p];
-  } else {
-    const int j = b - in.S;
-    const double* w = in.wxi + int64_t(j) * in.P;
-    const double* e = in.eta + int64_t(j) * in.P;
-    for (int p = threadIdx.x; p < in.P; p += 256) acc += w[p] * e[p];
+__global__ __launch_bounds__(1024) void k_msg_scalars(MsgIn in, int J, double* __restrict__ rho,
+                                                      double* __restrict__ etam) {
+  __shared__ double red[1024];
+  const int b = blockIdx.x, P = in.P;
+  const bool ex = b < in.S;
+  const double* w = ex ? in.wa + int64_t(b) * P : in.wxi + int64_t(b - in.S) * P;
+  const double* e = ex ? nullptr : in.eta + int64_t(b - in.S) * P;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int p0 = threadIdx.x; p0 < P; p0 += 4096) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int p = p0 + 1024 * q;
+      if (p < P) acc[q] += ex ? w[p] : w[p] * e[p];
+    }
   }
-  const double t = block_sum(acc, red);
+  const double t = block_sum<1024>((acc[0] + acc[1]) + (acc[2] + acc[3]), red);
   if (threadIdx.x == 0) {
-    if (b < in.S)
+    if (ex)
       rho[b] = t;
     else
       etam[b - in.S] = t;
@@ -375,6 +424,127 @@ __global__ __launch_bounds__(256) void k_msg_reduce(MsgGeom G, MsgIn in, const d
   }
 }
 
+// The same partial sums as a rank-P update: with U_k,p[f] = W_k,p g_p b_p[f]
+// (W_1, W_2 the real square-root weights, W_3 = w_beta mu) and V_p[il] =
+// y_p[i] z_p[l], out_k[f][il] = sum_p U_k,p[f] V_p[il]. Each round forms the
+// paths of 256 particles (one per thread) as compact phasors in LDS; in
+// sub-rounds of 32 particles their U rows and V are expanded into a stage,
+// and a thread owns the 3 x kRedCB tile (k = 0..2 at one f, kRedCB
+// consecutive il) while groups of nf * ceil(N_y N_z / kRedCB) threads split
+// the sub-round's particles. Groups are summed in fixed order.
+// Requires nf * ceil(N_y N_z / kRedCB) <= 256 and 3 nf + N_y N_z <= 256.
+constexpr int kRedR = 256;  // particles per round (paths formed)
+constexpr int kRedSub = 32; // particles per expanded sub-round
+constexpr int kRedCB = 4;   // il columns of a thread's tile
+
+__global__ __launch_bounds__(256) void k_msg_reduce_tile(MsgGeom G, MsgIn in, const double* __restrict__ rho,
+                                                         double2* __restrict__ part) {
+  extern __shared__ double2 sm[];
+  const int nf = G.nf, ny = G.ny, nz = G.nz, nyz = ny * nz, Nz = nf * nyz, J = G.J;
+  const int S = in.S, P = in.P;
+  const int ncb = (nyz + kRedCB - 1) / kRedCB;
+  const int T = nf * ncb, NG = 256 / T;
+  const int per = 3 * nf + nyz;        // staged complex values per particle
+  Kron* kp = reinterpret_cast<Kron*>(sm);                       // [kRedR]
+  double2* wts = reinterpret_cast<double2*>(kp + kRedR);         // [kRedR][2]: (w1, w2), w3
+  double2* stage = wts + 2 * kRedR;                              // [kRedSub][per]
+  double2* red = stage + kRedSub * per;                          // [3][nf][nyz]
+  const int chunk = blockIdx.x, s = blockIdx.y, j = blockIdx.z;
+  const double zeta = in.zeta[s * J + j], rh = rho[s];
+  const double pdd = 1.0 - zeta * rh, pd = 1.0 - rh;
+  const int grp = threadIdx.x / T, rr = threadIdx.x - grp * T;
+  const int f = rr / ncb, c0 = (rr - f * ncb) * kRedCB;
+  const bool act = grp < NG;
+  double2 acc[3][kRedCB];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int c = 0; c < kRedCB; ++c) acc[k][c] = {0.0, 0.0};
+  const int p_end = min(P, (chunk + 1) * kChunk);
+  for (int p0 = chunk * kChunk; p0 < p_end; p0 += kRedR) {
+    const int nr = min(kRedR, p_end - p0);
+    __syncthreads();
+    {
+      const int q = threadIdx.x, p = p0 + q;
+      if (q < nr) {
+        kp[q] = path_kron(G, j, in.mt + 3 * int64_t(p), s ? in.sfv + (int64_t(s) * P + p) * 3 : nullptr);
+        const double wb = in.wb[p];
+        const double gm = in.gamma[int64_t(s) * P + p];
+        const double2 mu = in.mu[int64_t(s) * P + p];
+        const double m2 = cabs2(mu);
+        wts[2 * q] = {wb * sqrt(gm + m2 * pdd), wb * sqrt(gm + m2 * pd)};
+        wts[2 * q + 1] = cscale(wb, mu);
+      }
+    }
+    for (int q0 = 0; q0 < nr; q0 += kRedSub) {
+      const int np = min(kRedSub, nr - q0);
+      __syncthreads();
+      {
+        // expand: threads [0, 3 kRedSub) write U rows, [3 kRedSub, 4 kRedSub) V
+        const int q = threadIdx.x % kRedSub, pt = threadIdx.x / kRedSub;
+        if (q < np && pt < 4) {
+          const Kron k = kp[q0 + q];
+          double2* row = stage + q * per;
+          if (pt < 3) {
+            const double2 wq = wts[2 * (q0 + q) + (pt == 2 ? 1 : 0)];
+            const double2 w = pt == 2 ? wq : double2{pt == 0 ? wq.x : wq.y, 0.0};
+            double2 v = cmul(w, cmul(k.g, k.b0));
+            for (int ff = 0; ff < nf; ++ff) {
+              row[pt * nf + ff] = v;
+              v = cmul(v, k.bs);
+            }
+          } else {
+            double2 y = k.y0;
+            for (int i = 0; i < ny; ++i) {
+              double2 zz = cmul(y, k.z0);
+              for (int l = 0; l < nz; ++l) {
+                row[3 * nf + i * nz + l] = zz;
+                zz = cmul(zz, k.zs);
+              }
+              y = cmul(y, k.ys);
+            }
+          }
+        }
+      }
+      __syncthreads();
+      if (act) {
+        for (int q = grp; q < np; q += NG) {
+          const double2* row = stage + q * per;
+          const double2 u0 = row[f], u1 = row[nf + f], u2 = row[2 * nf + f];
+          const double2* vr = row + 3 * nf + c0;
+#pragma unroll
+          for (int c = 0; c < kRedCB; ++c) {
+            if (c0 + c < nyz) {
+              const double2 v = vr[c];
+              acc[0][c] = cmac(acc[0][c], u0, v);
+              acc[1][c] = cmac(acc[1][c], u1, v);
+              acc[2][c] = cmac(acc[2][c], u2, v);
+            }
+          }
+        }
+      }
+    }
+  }
+  // groups in order into red, then out
+  for (int g = 0; g < NG; ++g) {
+    __syncthreads();
+    if (act && grp == g) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int c = 0; c < kRedCB; ++c) {
+          if (c0 + c < nyz) {
+            double2* d = red + (k * nf + f) * nyz + c0 + c;
+            *d = g == 0 ? acc[k][c] : cadd(*d, acc[k][c]);
+          }
+        }
+    }
+  }
+  __syncthreads();
+  double2* out = part + ((int64_t(chunk) * S + s) * J + j) * 3 * Nz;
+  for (int e = threadIdx.x; e < 3 * Nz; e += 256) out[e] = red[e];
+}
+
 // m = rho zeta sum1, w = rho sum2, m4 = rho sum3, m3 = zeta m4 (chunks summed in order)
 __global__ __launch_bounds__(256) void k_msg_combine(MsgGeom G, MsgIn in, int nchunk, const double* __restrict__ rho,
                                                      const double2* __restrict__ part, double2* __restrict__ avg) {
@@ -407,12 +577,6 @@ __device__ void pair_of(int d, int S, int* t, int* u) {
   }
   *t = r;
   *u = r + d;
-}
-
-__device__ double2 vdot(const double2* x, const double2* y, int n) {
-  double2 acc = {0.0, 0.0};
-  for (int e = 0; e < n; ++e) acc = cadd(acc, cmulc(x[e], y[e]));
-  return acc;
 }
 
 // in-place Cholesky of the n x n Hermitian matrix H (row-major, stride 16),
@@ -470,7 +634,8 @@ __global__ __launch_bounds__(256) void k_msg_setup(MsgGeom G, int S, int GS, con
   __syncthreads();
   const int nG = S * (S + 1) / 2;
   const int nd = nub ? nG + S + 2 : nG + 3 * S + 6;
-  for (int d = threadIdx.x; d < nd; d += 256) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int d = wave; d < nd; d += 4) {
     const double2 *x, *y;
     if (d < nG) {
       int t, u;
@@ -497,7 +662,10 @@ __global__ __launch_bounds__(256) void k_msg_setup(MsgGeom G, int S, int GS, con
       x = xs[q];
       y = ys[q];
     }
-    dots[d] = vdot(x, y, Nz);
+    double2 acc = {0.0, 0.0};
+    for (int e = lane; e < Nz; e += 64) acc = cmacc(acc, x[e], y[e]);
+    acc = gsum<64>(acc);
+    if (lane == 0) dots[d] = acc;
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
@@ -569,16 +737,13 @@ __global__ __launch_bounds__(256) void k_msg_setup(MsgGeom G, int S, int GS, con
 
 // MT message (and noise message) at (particle p, array j): group of GS lanes,
 // lane s owns feature s.
-template <int GS>
+template <int GS, int NZ>
 __global__ __launch_bounds__(256) void k_msg_pair(MsgGeom G, MsgIn in, MsgWs W, double* __restrict__ iota,
                                                   double* __restrict__ nu) {
-  extern __shared__ double2 sm[];
+  __shared__ double2 slot[256 * kSlot];
   const int nf = G.nf, ny = G.ny, nz = G.nz, Nz = nf * ny * nz, J = G.J;
   const int S = in.S, P = in.P;
   const int j = blockIdx.y;
-  double2* sz = sm;                // [N_z]
-  double2* slot = sm + Nz;         // [256][kSlot]
-  for (int e = threadIdx.x; e < Nz; e += 256) sz[e] = in.z[int64_t(j) * Nz + e];
   const int s = threadIdx.x % GS;
   const int gbase = threadIdx.x - s;
   const int64_t p = int64_t(blockIdx.x) * (256 / GS) + threadIdx.x / GS;
@@ -594,8 +759,8 @@ __global__ __launch_bounds__(256) void k_msg_pair(MsgGeom G, MsgIn in, MsgWs W, 
     c = pe * (in.gamma[int64_t(s) * P + pc] + cabs2(mu) * (1.0 - pe));
     pm = cscale(pe, mu);
   }
-  __syncthreads();
-  const double2 y = s < S ? contract(k, sz, nf, ny, nz) : double2{0.0, 0.0};  // a_s^H z
+  // a_s^H z (padded lanes have g = 0)
+  const double2 y = contract<NZ>(k, uniform_vec(in.z + int64_t(j) * Nz), nf, ny, nz);
   double2* my = slot + threadIdx.x * kSlot;
   my[0] = k.g;
   my[1] = k.b0;
@@ -620,7 +785,7 @@ __global__ __launch_bounds__(256) void k_msg_pair(MsgGeom G, MsgIn in, MsgWs W, 
                        seqdot(k.z0, k.zs, o[5], o[6], nz);
       g0 = cscale(d, cmulc(k.g, o[0]));
     }
-    sg = cadd(sg, cmul(o[7], g0));
+    sg = cmac(sg, o[7], g0);
     H[t] = cscale(sc * sqrt(o[8].x) / eta, g0);
     if (t == s) H[t].x += 1.0;
   }
@@ -650,36 +815,81 @@ __global__ __launch_bounds__(256) void k_msg_pair(MsgGeom G, MsgIn in, MsgWs W, 
   }
 }
 
-// PF message at r = 1 for (feature s, particle p, array j): lane t contracts
-// the path a_s^(j,p) with column m_t (t != s) or, at t = s, with z'.
-template <int GS>
-__global__ __launch_bounds__(256) void k_msg_kappa(MsgGeom G, MsgIn in, MsgWs W, double* __restrict__ kappa) {
-  extern __shared__ double2 sm[];
-  const int nf = G.nf, ny = G.ny, nz = G.nz, Nz = nf * ny * nz, J = G.J;
+// PF message at r = 1 for (feature s, particle p, array j), one thread per
+// particle. The S dense columns (m_t for t != s; z' at t = s) are read
+// wave-uniformly, and each element of the path is generated once for all of
+// them. SC columns are contracted: SC = S for S <= 8, else 16 (the extra
+// columns repeat column 0 and are discarded).
+template <int SC, int NZ>
+__global__ __launch_bounds__(256) void k_msg_kappa(MsgGeom G, MsgIn in, MsgWs W, int GS, double* __restrict__ kappa) {
+  const int nf = G.nf, ny = G.ny, nz = NZ > 0 ? NZ : G.nz, Nz = nf * ny * nz, J = G.J;
   const int S = in.S, P = in.P;
-  const int s = blockIdx.y / J, j = blockIdx.y % J, sj = blockIdx.y;
-  const int ld = Nz + 1;  // odd stride in complex doubles: lanes of a group hit different banks
-  const int64_t vec = int64_t(S) * J * Nz;
-  for (int idx = threadIdx.x; idx < S * Nz; idx += 256) {
-    const int t = idx / Nz, e = idx - t * Nz;
-    sm[t * ld + e] = t == s ? W.zp[int64_t(sj) * Nz + e] : W.avg[(int64_t(t) * J + j) * Nz + e];
-  }
-  const int t = threadIdx.x % GS;
-  const int64_t p = int64_t(blockIdx.x) * (256 / GS) + threadIdx.x / GS;
+  const int sj = blockIdx.y, s = sj / J, j = sj - s * J;
+  const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
   const int64_t pc = p < P ? p : P - 1;
   const double eta = W.etam[j];
   const Kron k = path_kron(G, j, in.mt + 3 * pc, s ? in.sfv + (int64_t(s) * P + pc) * 3 : nullptr);
-  double2 Lr[GS];
+  cvec X[SC];
 #pragma unroll
-  for (int u = 0; u < GS; ++u) Lr[u] = W.L[(int64_t(sj) * GS + t) * GS + u];
-  const double2 wt = W.wv[int64_t(sj) * GS + t];
-  __syncthreads();
-  const double2 cv = t < S ? contract(k, sm + t * ld, nf, ny, nz) : double2{0.0, 0.0};  // a^H X_t
-  const double2 rhs = (t < S && t != s) ? cconj(cv) : double2{0.0, 0.0};               // m_t^H a
-  const double2 aHz = gshfl<GS>(cv, s);                                                 // a^H z'
-  const double2 u = group_forward<GS>(Lr, rhs, t);
-  const double uu = gsum<GS>(cabs2(u));
-  const double2 uw = gsum<GS>(cmulc(u, wt));
+  for (int t = 0; t < SC; ++t) {
+    const int tt = t < S ? t : 0;
+    X[t] = uniform_vec(tt == s ? W.zp + int64_t(sj) * Nz : W.avg + (int64_t(tt) * J + j) * Nz);
+  }
+  double2 acc[SC];
+#pragma unroll
+  for (int t = 0; t < SC; ++t) acc[t] = {0.0, 0.0};
+  double2 zl[NZ > 0 ? NZ : 1];
+  if constexpr (NZ > 0) {
+    double2 v = k.z0;
+#pragma unroll
+    for (int l = 0; l < NZ; ++l) {
+      zl[l] = v;
+      v = cmul(v, k.zs);
+    }
+  }
+  double2 bf = cmul(k.g, k.b0);
+  for (int f = 0; f < nf; ++f) {
+    double2 yi = k.y0;
+    for (int i = 0; i < ny; ++i) {
+      const double2 w = cmul(bf, yi);
+      const int base = (f * ny + i) * nz;
+      if constexpr (NZ > 0) {
+#pragma unroll
+        for (int l = 0; l < NZ; ++l) {
+          const double2 a = cmul(w, zl[l]);
+#pragma unroll
+          for (int t = 0; t < SC; ++t) acc[t] = cmacc(acc[t], ld(X[t], base + l), a);
+        }
+      } else {
+        double2 zz = k.z0;
+        for (int l = 0; l < nz; ++l) {
+          const double2 a = cmul(w, zz);
+#pragma unroll
+          for (int t = 0; t < SC; ++t) acc[t] = cmacc(acc[t], ld(X[t], base + l), a);
+          zz = cmul(zz, k.zs);
+        }
+      }
+      yi = cmul(yi, k.ys);
+    }
+    bf = cmul(bf, k.bs);
+  }
+  // acc[t] = X_t^H a: (M_s^H a)_t for t != s, and a^H z' = conj(acc[s]);
+  // u = L^{-1} M_s^H a with L of I + G_s / eta~ (identity at s and past S)
+  const cvec Lm = uniform_vec(W.L + int64_t(sj) * GS * GS);
+  const cvec wv = uniform_vec(W.wv + int64_t(sj) * GS);
+  double2 u[SC];
+  double uu = 0.0;
+  double2 uw = {0.0, 0.0}, aHz = {0.0, 0.0};
+#pragma unroll
+  for (int t = 0; t < SC; ++t) {
+    if (t == s) aHz = cconj(acc[t]);
+    double2 r = (t < S && t != s) ? acc[t] : double2{0.0, 0.0};
+#pragma unroll
+    for (int m = 0; m < t; ++m) r = csub(r, cmul(ld(Lm, t * GS + m), u[m]));
+    u[t] = cscale(1.0 / ld(Lm, t * GS + t).x, r);
+    uu += cabs2(u[t]);
+    uw = cmacc(uw, u[t], ld(wv, t));
+  }
   const double aAa = double(Nz) * cabs2(k.g) / eta - uu / (eta * eta);
   const double2 aAz = csub(cscale(1.0 / eta, aHz), cscale(1.0 / (eta * eta), uw));
   const double zeta = in.zeta[s * J + j];
@@ -689,36 +899,50 @@ __global__ __launch_bounds__(256) void k_msg_kappa(MsgGeom G, MsgIn in, MsgWs W,
   const double2 aAe = csub(aAz, cscale(aAa, cm));
   const double eAe = W.kc[2 * sj] - 2.0 * cmulc(cm, aAz).x + cabs2(cm) * aAa;
   const double den = 1.0 + q * aAa;
-  if (t == 0 && p < P)
+  if (p < P)
     kappa[int64_t(sj) * P + p] =
         q * cabs2(aAe) / den - eAe - double(Nz) * log(kPi) - log(den) - W.kc[2 * sj + 1];
 }
 
-template <int GS>
-hipError_t launch_pairs(const MsgGeom& g, const MsgIn& in, const MsgOut& out, const MsgWs& w, hipStream_t st) {
-  const int Nz = g.nf * g.ny * g.nz;
+template <int GS, int NZ>
+hipError_t launch_pair(const MsgGeom& g, const MsgIn& in, const MsgOut& out, const MsgWs& w, hipStream_t st) {
   const int per = 256 / GS;
-  const dim3 grid_pair(unsigned((int64_t(in.P) + per - 1) / per), unsigned(g.J));
+  const dim3 grid(unsigned((int64_t(in.P) + per - 1) / per), unsigned(g.J));
+  k_msg_pair<GS, NZ><<<grid, 256, 0, st>>>(g, in, w, out.iota, out.nu);
+  return hipGetLastError();
+}
+
+template <int SC, int NZ>
+hipError_t launch_kappa(const MsgGeom& g, const MsgIn& in, const MsgOut& out, const MsgWs& w, hipStream_t st) {
+  const dim3 grid(unsigned((int64_t(in.P) + 255) / 256), unsigned(in.S * g.J));
+  k_msg_kappa<SC, NZ><<<grid, 256, 0, st>>>(g, in, w, msg_group(in.S), out.kappa);
+  return hipGetLastError();
+}
+
+template <int NZ>
+hipError_t launch_per_particle(const MsgGeom& g, const MsgIn& in, const MsgOut& out, const MsgWs& w,
+                               hipStream_t st) {
+  hipError_t e = hipSuccess;
   if (out.iota || out.nu) {
-    const size_t lds = size_t(Nz + 256 * kSlot) * sizeof(double2);
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_msg_pair<GS>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-    if (e != hipSuccess) return e;
-    k_msg_pair<GS><<<grid_pair, 256, lds, st>>>(g, in, w, out.iota, out.nu);
-    e = hipGetLastError();
+    const int gs = msg_group(in.S);
+    e = gs == 4 ? launch_pair<4, NZ>(g, in, out, w, st)
+                : (gs == 8 ? launch_pair<8, NZ>(g, in, out, w, st) : launch_pair<16, NZ>(g, in, out, w, st));
     if (e != hipSuccess) return e;
   }
   if (out.kappa) {
-    const size_t lds = size_t(in.S) * (Nz + 1) * sizeof(double2);
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_msg_kappa<GS>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-    if (e != hipSuccess) return e;
-    const dim3 grid(grid_pair.x, unsigned(in.S * g.J));
-    k_msg_kappa<GS><<<grid, 256, lds, st>>>(g, in, w, out.kappa);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    switch (in.S) {
+      case 1: return launch_kappa<1, NZ>(g, in, out, w, st);
+      case 2: return launch_kappa<2, NZ>(g, in, out, w, st);
+      case 3: return launch_kappa<3, NZ>(g, in, out, w, st);
+      case 4: return launch_kappa<4, NZ>(g, in, out, w, st);
+      case 5: return launch_kappa<5, NZ>(g, in, out, w, st);
+      case 6: return launch_kappa<6, NZ>(g, in, out, w, st);
+      case 7: return launch_kappa<7, NZ>(g, in, out, w, st);
+      case 8: return launch_kappa<8, NZ>(g, in, out, w, st);
+      default: return launch_kappa<16, NZ>(g, in, out, w, st);
+    }
   }
-  return hipSuccess;
+  return e;
 }
 
 }  // namespace
@@ -735,11 +959,22 @@ hipError_t launch_messages(const MsgGeom& g, const MsgIn& in, const MsgOut& out,
   const MsgWs w = carve(ws, g, in.S, in.P, nullptr);
   const int Nz = g.nf * g.ny * g.nz;
   const int nchunk = int((int64_t(in.P) + kChunk - 1) / kChunk);
-  k_msg_scalars<<<in.S + g.J, 256, 0, st>>>(in, g.J, w.rho, w.etam);
+  k_msg_scalars<<<in.S + g.J, 1024, 0, st>>>(in, g.J, w.rho, w.etam);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const size_t lds_r = size_t(kSub) * (g.nf + g.ny + g.nz + 2) * sizeof(double2);
-  k_msg_reduce<<<dim3(unsigned(nchunk), unsigned(in.S), unsigned(g.J)), 256, lds_r, st>>>(g, in, w.rho, w.part);
+  const dim3 grid_r(unsigned(nchunk), unsigned(in.S), unsigned(g.J));
+  if (g.nf * ((g.ny * g.nz + kRedCB - 1) / kRedCB) <= 256 && 3 * g.nf + g.ny * g.nz <= 256) {
+    const size_t lds_r = kRedR * (sizeof(Kron) + 2 * sizeof(double2)) +
+                         size_t(kRedSub) * (3 * g.nf + g.ny * g.nz) * sizeof(double2) +
+                         size_t(3) * Nz * sizeof(double2);
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_msg_reduce_tile),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_r));
+    if (e != hipSuccess) return e;
+    k_msg_reduce_tile<<<grid_r, 256, lds_r, st>>>(g, in, w.rho, w.part);
+  } else {
+    const size_t lds_r = size_t(kSub) * (g.nf + g.ny + g.nz + 2) * sizeof(double2);
+    k_msg_reduce<<<grid_r, 256, lds_r, st>>>(g, in, w.rho, w.part);
+  }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   k_msg_combine<<<dim3(unsigned(in.S), unsigned(g.J)), 256, 0, st>>>(g, in, nchunk, w.rho, w.part, w.avg);
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -750,14 +985,7 @@ hipError_t launch_messages(const MsgGeom& g, const MsgIn& in, const MsgOut& out,
   k_msg_setup<<<dim3(unsigned(in.S + 1), unsigned(g.J)), 256, lds_s, st>>>(g, in.S, msg_group(in.S), in.z, w,
                                                                            out.kappa0, out.omega);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  switch (msg_group(in.S)) {
-    case 4:
-      return launch_pairs<4>(g, in, out, w, st);
-    case 8:
-      return launch_pairs<8>(g, in, out, w, st);
-    default:
-      return launch_pairs<16>(g, in, out, w, st);
-  }
+  return g.nz == 4 ? launch_per_particle<4>(g, in, out, w, st) : launch_per_particle<0>(g, in, out, w, st);
 }
 
 }  // namespace ba

@@ -27,8 +27,6 @@ ba_status m_dev(const char* fn, hipError_t e) {
   return e == hipErrorOutOfMemory ? BA_ERR_NOMEM : BA_ERR_DEVICE;
 }
 
-int n_obs(const ba_msgs_s* h) { return h->geo.nf * h->geo.ny * h->geo.nz; }
-
 }  // namespace
 
 extern "C" {
@@ -91,7 +89,6 @@ ba_status ba_update_messages(ba_msgs h, const ba_msg_inputs* in, const ba_msg_ou
   const int S = in->n_feat, P = in->n_part;
   if (S < 1 || S > 16) return m_arg(fn, "n_feat must be in [1, 16]");
   if (P < 1 || P > (1 << 26)) return m_arg(fn, "n_part must be in [1, 2^26]");
-  if (S * (n_obs(h) + 1) > kMsgMaxLdsVec) return m_arg(fn, "n_feat * (N_z + 1) must be <= 6144");
   if (!in->z || !in->mt_pos || !in->w_beta || !in->sfv || !in->gamma || !in->mu || !in->w_alpha || !in->zeta ||
       !in->eta || !in->w_xi)
     return m_arg(fn, "null input buffer");

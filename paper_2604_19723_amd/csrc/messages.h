@@ -47,8 +47,6 @@ struct MsgOut {
 
 // lanes per (particle, array) group: the smallest of 4, 8, 16 that holds S
 int msg_group(int S);
-// largest S * (N_z + 1) whose dense vectors fit the PF-message kernel's LDS
-constexpr int kMsgMaxLdsVec = 6144;
 size_t msg_workspace_bytes(const MsgGeom& g, int S, int P);
 hipError_t launch_messages(const MsgGeom& g, const MsgIn& in, const MsgOut& out, void* ws, hipStream_t s);
 
