@@ -42,7 +42,7 @@ namespace {
 constexpr double kC = 299792458.0;
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kSub = 64;             // particles per LDS round of the reduction
-constexpr int kChunk = 1024;         // particles per reduction workgroup
+constexpr int kChunk = 512;          // particles per reduction workgroup
 constexpr int kMaxDots = 192;        // inner products of one setup workgroup
 constexpr int kSlot = 9;             // double2 per lane in the pair kernel's exchange
 
@@ -433,7 +433,10 @@ __global__ __launch_bounds__(256) void k_msg_reduce(MsgGeom G, MsgIn in, const d
 // consecutive il) while groups of nf * ceil(N_y N_z / kRedCB) threads split
 // the sub-round's particles. Groups are summed in fixed order.
 // Requires nf * ceil(N_y N_z / kRedCB) <= 256 and 3 nf + N_y N_z <= 256.
-constexpr int kRedR = 256;  // particles per round (paths formed)
+// LDS row stride of a staged particle: rows of consecutive particles start 16
+// dwords apart modulo 32 banks (a row of n complex values is 4n dwords)
+__host__ __device__ inline int stage_row(int n) { return n + ((4 - n % 8) + 8) % 8; }
+constexpr int kRedR = 128;  // particles per round (paths formed)
 constexpr int kRedSub = 32; // particles per expanded sub-round
 constexpr int kRedCB = 4;   // il columns of a thread's tile
 
@@ -444,7 +447,7 @@ __global__ __launch_bounds__(256) void k_msg_reduce_tile(MsgGeom G, MsgIn in, co
   const int S = in.S, P = in.P;
   const int ncb = (nyz + kRedCB - 1) / kRedCB;
   const int T = nf * ncb, NG = 256 / T;
-  const int per = 3 * nf + nyz;        // staged complex values per particle
+  const int per = stage_row(3 * nf + nyz);  // staged complex values per particle (padded)
   Kron* kp = reinterpret_cast<Kron*>(sm);                       // [kRedR]
   double2* wts = reinterpret_cast<double2*>(kp + kRedR);         // [kRedR][2]: (w1, w2), w3
   double2* stage = wts + 2 * kRedR;                              // [kRedSub][per]
@@ -453,7 +456,7 @@ __global__ __launch_bounds__(256) void k_msg_reduce_tile(MsgGeom G, MsgIn in, co
   const double zeta = in.zeta[s * J + j], rh = rho[s];
   const double pdd = 1.0 - zeta * rh, pd = 1.0 - rh;
   const int grp = threadIdx.x / T, rr = threadIdx.x - grp * T;
-  const int f = rr / ncb, c0 = (rr - f * ncb) * kRedCB;
+  const int f = rr / ncb, cb = rr - f * ncb;  // columns cb, cb + ncb, cb + 2 ncb, ...
   const bool act = grp < NG;
   double2 acc[3][kRedCB];
 #pragma unroll
@@ -511,11 +514,11 @@ __global__ __launch_bounds__(256) void k_msg_reduce_tile(MsgGeom G, MsgIn in, co
         for (int q = grp; q < np; q += NG) {
           const double2* row = stage + q * per;
           const double2 u0 = row[f], u1 = row[nf + f], u2 = row[2 * nf + f];
-          const double2* vr = row + 3 * nf + c0;
+          const double2* vr = row + 3 * nf + cb;
 #pragma unroll
           for (int c = 0; c < kRedCB; ++c) {
-            if (c0 + c < nyz) {
-              const double2 v = vr[c];
+            if (cb + c * ncb < nyz) {
+              const double2 v = vr[c * ncb];
               acc[0][c] = cmac(acc[0][c], u0, v);
               acc[1][c] = cmac(acc[1][c], u1, v);
               acc[2][c] = cmac(acc[2][c], u2, v);
@@ -533,8 +536,8 @@ __global__ __launch_bounds__(256) void k_msg_reduce_tile(MsgGeom G, MsgIn in, co
       for (int k = 0; k < 3; ++k)
 #pragma unroll
         for (int c = 0; c < kRedCB; ++c) {
-          if (c0 + c < nyz) {
-            double2* d = red + (k * nf + f) * nyz + c0 + c;
+          if (cb + c * ncb < nyz) {
+            double2* d = red + (k * nf + f) * nyz + cb + c * ncb;
             *d = g == 0 ? acc[k][c] : cadd(*d, acc[k][c]);
           }
         }
@@ -545,25 +548,36 @@ __global__ __launch_bounds__(256) void k_msg_reduce_tile(MsgGeom G, MsgIn in, co
   for (int e = threadIdx.x; e < 3 * Nz; e += 256) out[e] = red[e];
 }
 
-// m = rho zeta sum1, w = rho sum2, m4 = rho sum3, m3 = zeta m4 (chunks summed in order)
+// m = rho zeta sum1, w = rho sum2, m4 = rho sum3, m3 = zeta m4. Workgroup
+// (feature-array, sum, 64 elements); its four waves take every fourth chunk,
+// and the four partial sums are added in a fixed order.
 __global__ __launch_bounds__(256) void k_msg_combine(MsgGeom G, MsgIn in, int nchunk, const double* __restrict__ rho,
                                                      const double2* __restrict__ part, double2* __restrict__ avg) {
-  const int s = blockIdx.x, j = blockIdx.y, J = G.J, S = in.S;
-  const int Nz = G.nf * G.ny * G.nz;
+  __shared__ double2 red[4][64];
+  const int J = G.J, S = in.S, Nz = G.nf * G.ny * G.nz;
+  const int sj = blockIdx.x, s = sj / J, j = sj - s * J, kind = blockIdx.y;
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int e = blockIdx.z * 64 + lane;
+  double2 acc = {0.0, 0.0};
+  if (e < Nz) {
+    const int64_t cstride = int64_t(S) * J * 3 * Nz;
+    const double2* pc = part + (int64_t(s) * J + j) * 3 * Nz + int64_t(kind) * Nz + e;
+#pragma unroll 4
+    for (int c = g; c < nchunk; c += 4) acc = cadd(acc, pc[c * cstride]);
+  }
+  red[g][lane] = acc;
+  __syncthreads();
+  if (g != 0 || e >= Nz) return;
+  const double2 t = cadd(cadd(red[0][lane], red[1][lane]), cadd(red[2][lane], red[3][lane]));
   const double zeta = in.zeta[s * J + j], rh = rho[s];
   const int64_t vec = int64_t(S) * J * Nz;
-  for (int e = threadIdx.x; e < Nz; e += 256) {
-    double2 s1 = {0.0, 0.0}, s2 = s1, s3 = s1;
-    for (int c = 0; c < nchunk; ++c) {
-      const double2* pc = part + ((int64_t(c) * S + s) * J + j) * 3 * Nz;
-      s1 = cadd(s1, pc[e]);
-      s2 = cadd(s2, pc[Nz + e]);
-      s3 = cadd(s3, pc[2 * Nz + e]);
-    }
-    const int64_t o = (int64_t(s) * J + j) * Nz + e;
-    const double2 m4 = cscale(rh, s3);
-    avg[o] = cscale(rh * zeta, s1);
-    avg[vec + o] = cscale(rh, s2);
+  const int64_t o = (int64_t(s) * J + j) * Nz + e;
+  if (kind == 0) {
+    avg[o] = cscale(rh * zeta, t);
+  } else if (kind == 1) {
+    avg[vec + o] = cscale(rh, t);
+  } else {
+    const double2 m4 = cscale(rh, t);
     avg[2 * vec + o] = cscale(zeta, m4);
     avg[3 * vec + o] = m4;
   }
@@ -611,7 +625,7 @@ __device__ void serial_forward(const double2* L, double2* b, int n) {
 // at r = 0, 1 (Sherman-Morrison on top of A).
 // Workgroup (S, j): the noise message's Gram of all columns, M^H e and |e|^2
 // for e = z - sum_t m3_t, and |z|^2.
-__global__ __launch_bounds__(256) void k_msg_setup(MsgGeom G, int S, int GS, const double2* __restrict__ z,
+__global__ __launch_bounds__(1024) void k_msg_setup(MsgGeom G, int S, int GS, const double2* __restrict__ z,
                                                    MsgWs W, double* __restrict__ kappa0,
                                                    double* __restrict__ omega) {
   extern __shared__ double2 sm[];
@@ -624,7 +638,7 @@ __global__ __launch_bounds__(256) void k_msg_setup(MsgGeom G, int S, int GS, con
   double2* rhs = H + 256;        // [3][16]
   const int64_t vec = int64_t(S) * J * Nz;
   auto col = [&](int kind, int t) { return W.avg + kind * vec + (int64_t(t) * J + j) * Nz; };
-  for (int e = threadIdx.x; e < Nz; e += 256) {
+  for (int e = threadIdx.x; e < Nz; e += 1024) {
     double2 acc = z[int64_t(j) * Nz + e];
     for (int t = 0; t < S; ++t)
       if (t != s) acc = csub(acc, col(2, t)[e]);
@@ -635,7 +649,7 @@ __global__ __launch_bounds__(256) void k_msg_setup(MsgGeom G, int S, int GS, con
   const int nG = S * (S + 1) / 2;
   const int nd = nub ? nG + S + 2 : nG + 3 * S + 6;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int d = wave; d < nd; d += 4) {
+  for (int d = wave; d < nd; d += 16) {
     const double2 *x, *y;
     if (d < nG) {
       int t, u;
@@ -965,7 +979,7 @@ hipError_t launch_messages(const MsgGeom& g, const MsgIn& in, const MsgOut& out,
   const dim3 grid_r(unsigned(nchunk), unsigned(in.S), unsigned(g.J));
   if (g.nf * ((g.ny * g.nz + kRedCB - 1) / kRedCB) <= 256 && 3 * g.nf + g.ny * g.nz <= 256) {
     const size_t lds_r = kRedR * (sizeof(Kron) + 2 * sizeof(double2)) +
-                         size_t(kRedSub) * (3 * g.nf + g.ny * g.nz) * sizeof(double2) +
+                         size_t(kRedSub) * stage_row(3 * g.nf + g.ny * g.nz) * sizeof(double2) +
                          size_t(3) * Nz * sizeof(double2);
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_msg_reduce_tile),
                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_r));
@@ -976,13 +990,14 @@ hipError_t launch_messages(const MsgGeom& g, const MsgIn& in, const MsgOut& out,
     k_msg_reduce<<<grid_r, 256, lds_r, st>>>(g, in, w.rho, w.part);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  k_msg_combine<<<dim3(unsigned(in.S), unsigned(g.J)), 256, 0, st>>>(g, in, nchunk, w.rho, w.part, w.avg);
+  k_msg_combine<<<dim3(unsigned(in.S * g.J), 3u, unsigned((Nz + 63) / 64)), 256, 0, st>>>(g, in, nchunk, w.rho,
+                                                                                          w.part, w.avg);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const size_t lds_s = size_t(Nz + kMaxDots + 256 + 48) * sizeof(double2);
   e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_msg_setup), hipFuncAttributeMaxDynamicSharedMemorySize,
                           int(lds_s));
   if (e != hipSuccess) return e;
-  k_msg_setup<<<dim3(unsigned(in.S + 1), unsigned(g.J)), 256, lds_s, st>>>(g, in.S, msg_group(in.S), in.z, w,
+  k_msg_setup<<<dim3(unsigned(in.S + 1), unsigned(g.J)), 1024, lds_s, st>>>(g, in.S, msg_group(in.S), in.z, w,
                                                                            out.kappa0, out.omega);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   return g.nz == 4 ? launch_per_particle<4>(g, in, out, w, st) : launch_per_particle<0>(g, in, out, w, st);
