@@ -45,6 +45,7 @@ constexpr int kSub = 64;             // particles per LDS round of the reduction
 constexpr int kChunk = 512;          // particles per reduction workgroup
 constexpr int kMaxDots = 192;        // inner products of one setup workgroup
 constexpr int kSlot = 9;             // double2 per lane in the pair kernel's exchange
+constexpr size_t kMaxLds = 160 * 1024;  // LDS of one CU
 
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return {a.x + b.x, a.y + b.y}; }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return {a.x - b.x, a.y - b.y}; }
@@ -977,16 +978,21 @@ hipError_t launch_messages(const MsgGeom& g, const MsgIn& in, const MsgOut& out,
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const dim3 grid_r(unsigned(nchunk), unsigned(in.S), unsigned(g.J));
-  if (g.nf * ((g.ny * g.nz + kRedCB - 1) / kRedCB) <= 256 && 3 * g.nf + g.ny * g.nz <= 256) {
-    const size_t lds_r = kRedR * (sizeof(Kron) + 2 * sizeof(double2)) +
-                         size_t(kRedSub) * stage_row(3 * g.nf + g.ny * g.nz) * sizeof(double2) +
-                         size_t(3) * Nz * sizeof(double2);
+  const size_t lds_tile = kRedR * (sizeof(Kron) + 2 * sizeof(double2)) +
+                          size_t(kRedSub) * stage_row(3 * g.nf + g.ny * g.nz) * sizeof(double2) +
+                          size_t(3) * Nz * sizeof(double2);
+  if (g.nf * ((g.ny * g.nz + kRedCB - 1) / kRedCB) <= 256 && 3 * g.nf + g.ny * g.nz <= 256 &&
+      lds_tile <= kMaxLds) {
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_msg_reduce_tile),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_r));
+                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_tile));
     if (e != hipSuccess) return e;
-    k_msg_reduce_tile<<<grid_r, 256, lds_r, st>>>(g, in, w.rho, w.part);
+    k_msg_reduce_tile<<<grid_r, 256, lds_tile, st>>>(g, in, w.rho, w.part);
   } else {
+    // N_f + N_y + N_z + 2 <= 98 complex per particle: at most 100 KB
     const size_t lds_r = size_t(kSub) * (g.nf + g.ny + g.nz + 2) * sizeof(double2);
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_msg_reduce), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            int(lds_r));
+    if (e != hipSuccess) return e;
     k_msg_reduce<<<grid_r, 256, lds_r, st>>>(g, in, w.rho, w.part);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -561,7 +561,8 @@ MSG_SFVS = np.array([[2.0, 0.0, 0.0], [14.0, 0.0, 0.0], [0.0, 2.0, 0.0], [0.0, 1
 
 
 def message_config(n_part: int = 30000, n_feat: int = 6, snr_db: float = 20.0, n_f: int = 10,
-                   bandwidth: float = 100e6, spread: float = 0.05, seed: int = SEED_BASE + 7) -> MessageSet:
+                   bandwidth: float = 100e6, spread: float = 0.05, seed: int = SEED_BASE + 7,
+                   n_y: int = 4, n_z: int = 4) -> MessageSet:
     """Experiment-1 sized message workload: J = 4 URAs of 4 x 4 elements at half
     a wavelength, N_f = 10 bins over 100 MHz at 3.5 GHz (N_z = 160), P = 30 000
     particles, S = 6 features (LOS plus the four walls and the ceiling of a
@@ -578,7 +579,8 @@ def message_config(n_part: int = 30000, n_feat: int = 6, snr_db: float = 20.0, n
     normalised; PF weights (existence e_s = 0.99, 0.9, 0.8, 0.7, 0.6, 0.5, ...)
     e_s (1 + 0.2 U(-1, 1)) / sum; zeta U(0.5, 1); noise particles
     eta U(0.5, 2), weights 1/P. With n_feat above 6, the extra features reuse
-    the surfaces in order with SFVs moved by 0.25 m."""
+    the surfaces in order with SFVs moved by 0.25 m. n_y x n_z sets the URA
+    (4 x 4 in the paper's experiments)."""
     if not 1 <= n_feat <= 16:
         raise ValueError("n_feat must be in [1, 16]")
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed, spawn_key=(0x3E55,))))
@@ -588,7 +590,6 @@ def message_config(n_part: int = 30000, n_feat: int = 6, snr_db: float = 20.0, n
     pa = np.array([[1.5, 1.5, 2.2], [6.5, 1.5, 2.2], [6.5, 5.5, 2.2], [1.5, 5.5, 2.2]])
     rots = np.stack([_rot_z(math.atan2(centre[1] - p[1], centre[0] - p[0])) for p in pa])
     p_mt = np.array([3.2, 2.8, 1.2])
-    n_y = n_z = 4
     J = len(pa)
     f_base = (np.arange(n_f) - (n_f - 1) / 2.0) * (bandwidth / (n_f - 1)) if n_f > 1 else np.zeros(1)
     p_y = (np.arange(n_y) - (n_y - 1) / 2.0) * lam / 2
@@ -629,4 +630,4 @@ def message_config(n_part: int = 30000, n_feat: int = 6, snr_db: float = 20.0, n
     return MessageSet(z=z, mt_pos=mt_pos, w_beta=w_beta, sfv=sfv, gamma=gamma, mu=mu, w_alpha=w_alpha,
                       zeta=zeta, eta=eta, w_xi=w_xi, pa_pos=pa, pa_rot=rots, n_y=n_y, n_z=n_z, n_f=n_f,
                       fc=fc, bandwidth=bandwidth,
-                      name="messages_j4_ura4x4_nf%d_s%d_p%d" % (n_f, S, P))
+                      name="messages_j4_ura%dx%d_nf%d_s%d_p%d" % (n_y, n_z, n_f, S, P))

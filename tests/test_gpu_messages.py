@@ -63,6 +63,24 @@ def test_messages_match_oracle(S, P, n_f):
     close(got["omega"], om.pr_message(ms, avg=avg), sc[None, :, None], "omega")
 
 
+@pytest.mark.parametrize("S,P,n_f,n_y,n_z", [(5, 40, 4, 3, 2), (2, 3, 40, 5, 5), (4, 9, 1, 1, 1), (2, 2, 64, 4, 4)])
+def test_other_array_shapes(S, P, n_f, n_y, n_z):
+    # vertical sizes other than 4 take the recurrence path of the contractions;
+    # 40 bins on a 5 x 5 URA (N_z = 1000) and 64 bins on a 4 x 4 URA (N_z = 1024,
+    # too large a stage for the tiled sums) take the element-per-thread particle
+    # sums; a single element and bin is the degenerate array
+    ms = wl.message_config(n_part=P, n_feat=S, n_f=n_f, n_y=n_y, n_z=n_z, seed=wl.SEED_BASE + 300 + n_f)
+    got = run(ms)
+    sc = scale(ms)
+    avg = om.particle_averages(ms)
+    close(got["iota"], om.mt_message(ms), sc[:, None], "iota")
+    close(got["nu"], om.noise_message(ms, avg=avg), sc[:, None], "nu")
+    k1, k0 = om.pf_message(ms, avg=avg)
+    close(got["kappa"], k1, sc[None, :, None], "kappa")
+    close(got["kappa0"], k0, sc[None, :], "kappa0")
+    close(got["omega"], om.pr_message(ms, avg=avg), sc[None, :, None], "omega")
+
+
 def test_two_reduction_chunks_and_a_ragged_tail():
     # 1100 particles: two 1024-particle chunks of the particle sums, and the
     # last workgroup of the per-particle kernels only partly filled
