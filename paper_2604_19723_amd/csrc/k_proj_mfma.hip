@@ -11,7 +11,9 @@
 // MI355X mapping (v_mfma_f32_16x16x4f32, FP32 in and out):
 //  * one workgroup = one trial x a range of grid columns; 4 waves;
 //  * Q is built from R once per workgroup straight into MFMA A-operand
-//    registers (each wave owns RB row blocks of 16 rows, all K);
+//    registers (each wave owns RB row blocks of 16 rows, all K; at M = 64
+//    two waves split the 128 rows and the two wave pairs split the 16-column
+//    blocks of a chunk);
 //  * the steering table is stored in HBM already in B-fragment order (16
 //    columns per block, 4 k-steps per lane per 16-byte word), so one chunk of
 //    32 KB is a straight copy into LDS, done by the gfx950 LDS DMA
@@ -26,12 +28,12 @@
 namespace ba {
 namespace {
 
-template <int MP>
+template <int MP, int WRO>
 __global__ __launch_bounds__(256, 2) void k_proj_q(const float2* __restrict__ R,
                                                    const float4* __restrict__ Xg,
                                                    float* __restrict__ P, int M, int64_t G,
                                                    int nchunk, int chunks_per_wg, int nsplit) {
-  using C = QCfg<MP>;
+  using C = QCfg<MP, WRO>;
   extern __shared__ __attribute__((aligned(16))) float4 sX[];   // [2][CH4], dynamic: filled by LDS DMA
   __shared__ float red[2][C::WR][C::NB * 16];
 
@@ -52,7 +54,7 @@ __global__ __launch_bounds__(256, 2) void k_proj_q(const float2* __restrict__ R,
   };
 
   float a[C::RB][C::KS];
-  load_q_fragments<MP>(R + b * int64_t(M) * M, M, wr, lane, a);
+  load_q_fragments<MP, WRO>(R + b * int64_t(M) * M, M, wr, lane, a);
   fetch(c0, 0);
   lds_dma_wait();
   __syncthreads();
@@ -65,7 +67,7 @@ __global__ __launch_bounds__(256, 2) void k_proj_q(const float2* __restrict__ R,
     const float4* sxb = sX + buf * C::CH4;
     const float* sx = reinterpret_cast<const float*>(sxb);
     for (int jb = wc; jb < C::NB; jb += C::WC) {
-      const float part = block_quadratic<MP>(a, sxb + jb * (C::BLK / 4), sx + jb * C::BLK, wr, lane);
+      const float part = block_quadratic<MP, WRO>(a, sxb + jb * (C::BLK / 4), sx + jb * C::BLK, wr, lane);
       if (C::WR == 1) {
         const int64_t g = int64_t(c) * C::NB * 16 + jb * 16 + lane;
         if (lane < 16 && g < G) P[b * G + g] = part * invM2;
@@ -87,9 +89,9 @@ __global__ __launch_bounds__(256, 2) void k_proj_q(const float2* __restrict__ R,
   }
 }
 
-template <int MP>
+template <int MP, int WRO = 0>
 hipError_t launch_q(const Plan& p, int B, const float2* R, float* P, hipStream_t s) {
-  using C = QCfg<MP>;
+  using C = QCfg<MP, WRO>;
   const int nchunk = int((p.Gb + C::NB - 1) / C::NB);  // the table holds Xblocks >= nchunk * NB
   // split the grid columns over several workgroups when there are few trials
   int nsplit = 1;
@@ -98,7 +100,7 @@ hipError_t launch_q(const Plan& p, int B, const float2* R, float* P, hipStream_t
   nsplit = (nchunk + per - 1) / per;
   const int64_t nblk = int64_t(B) * nsplit;
   if (nblk > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_proj_q<MP>, dim3(unsigned(nblk)), dim3(256), 2 * C::CH4 * sizeof(float4), s, R,
+  hipLaunchKernelGGL((k_proj_q<MP, WRO>), dim3(unsigned(nblk)), dim3(256), 2 * C::CH4 * sizeof(float4), s, R,
                      reinterpret_cast<const float4*>(p.d_X), P, p.M, p.G, nchunk, per, nsplit);
   return hipGetLastError();
 }
@@ -110,7 +112,7 @@ hipError_t launch_spectrum_mfma(const Plan& p, int B, const float2* R, float* P,
     case 8: return launch_q<8>(p, B, R, P, s);
     case 16: return launch_q<16>(p, B, R, P, s);
     case 32: return launch_q<32>(p, B, R, P, s);
-    case 64: return launch_q<64>(p, B, R, P, s);
+    case 64: return launch_q<64, kProjWR<64>>(p, B, R, P, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -35,7 +35,8 @@ __device__ double parabolic(double pm, double p0, double pp) {
 
 template <int MP>
 __global__ __launch_bounds__(256) void k_window(WindowArgs A) {
-  using C = QCfg<MP>;
+  constexpr int WRO = kProjWR<MP>;
+  using C = QCfg<MP, WRO>;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   // LDS sized for the windows of this launch: nbmax blocks of one window, then
   // the spectrum rows of the K windows
@@ -57,7 +58,7 @@ __global__ __launch_bounds__(256) void k_window(WindowArgs A) {
   const float2* Rb = A.R + b * int64_t(M) * M;
 
   float a[C::RB][C::KS];
-  load_q_fragments<MP>(Rb, M, wr, lane, a);
+  load_q_fragments<MP, WRO>(Rb, M, wr, lane, a);
 
   if (threadIdx.x == 0) {
     float tr = 0.f;
@@ -95,7 +96,7 @@ __global__ __launch_bounds__(256) void k_window(WindowArgs A) {
     for (int v = threadIdx.x; v < nbw * (C::BLK / 4); v += 256) sX[v] = src[v];
     __syncthreads();
     for (int jb = wc; jb < nbw; jb += C::WC) {
-      const float part = block_quadratic<MP>(a, sX + jb * (C::BLK / 4),
+      const float part = block_quadratic<MP, WRO>(a, sX + jb * (C::BLK / 4),
                                              reinterpret_cast<const float*>(sX) + jb * C::BLK, wr, lane);
       if (lane < 16) red[wr][jb * 16 + lane] = part;
     }

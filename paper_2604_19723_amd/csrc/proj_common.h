@@ -8,12 +8,13 @@ namespace ba {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-template <int MP>
+template <int MP, int WRO = 0>
 struct QCfg {
   static constexpr int K = 2 * MP;                 // GEMM depth = rows of Q
   static constexpr int KS = K / 4;                 // MFMA k-steps
   static constexpr int RBLK = K / 16;              // 16-row blocks of Q
-  static constexpr int WR = RBLK >= 8 ? 4 : (RBLK >= 4 ? 2 : 1);  // waves along rows
+  // waves along rows (WRO > 0 overrides the default split)
+  static constexpr int WR = WRO > 0 ? WRO : (RBLK >= 8 ? 4 : (RBLK >= 4 ? 2 : 1));
   static constexpr int RB = RBLK / WR;             // row blocks per wave
   static constexpr int WC = 4 / WR;                // waves along columns
   static constexpr int BLK = K * 16;               // floats per 16-column block
@@ -21,6 +22,15 @@ struct QCfg {
   static constexpr int CH4 = 8192 / 4;             // float4 per chunk
   static constexpr int F4 = CH4 / 256;             // float4 per thread per chunk
 };
+
+// Row split of the register-resident projection at each padded size: for
+// MP = 64 two waves along rows (four row blocks each, the 16-column blocks
+// shared out between the two wave pairs) halves the B-fragment LDS reads and
+// gives each wave four independent accumulators. The full-grid kernel and the
+// refinement-window kernel use the same split, so window values equal the
+// full-grid values bit for bit.
+template <int MP>
+constexpr int kProjWR = MP == 64 ? 2 : 0;
 
 // Direct global -> LDS copy of 16 bytes per lane (global_load_lds_dwordx4):
 // lane i's word lands at lds_wave + 16 i. lds_wave must be wave-uniform and
@@ -54,10 +64,10 @@ __device__ __forceinline__ float qval(const float2* __restrict__ Rb, int M, int 
 }
 
 // A operand of the waves' rows: rows i = wr*RB*16 + rb*16 + lane%16, k = 4s + lane/16
-template <int MP>
+template <int MP, int WRO = 0>
 __device__ __forceinline__ void load_q_fragments(const float2* __restrict__ Rb, int M, int wr, int lane,
-                                                 float (&a)[QCfg<MP>::RB][QCfg<MP>::KS]) {
-  using C = QCfg<MP>;
+                                                 float (&a)[QCfg<MP, WRO>::RB][QCfg<MP, WRO>::KS]) {
+  using C = QCfg<MP, WRO>;
 #pragma unroll
   for (int rb = 0; rb < C::RB; ++rb)
 #pragma unroll
@@ -67,11 +77,11 @@ __device__ __forceinline__ void load_q_fragments(const float2* __restrict__ Rb, 
 
 // One 16-column block: returns, in lanes 0..15, this wave's partial
 // sum over its rows of x_g[i] (Q x_g)[i] for the block's columns.
-template <int MP>
-__device__ __forceinline__ float block_quadratic(const float (&a)[QCfg<MP>::RB][QCfg<MP>::KS],
+template <int MP, int WRO = 0>
+__device__ __forceinline__ float block_quadratic(const float (&a)[QCfg<MP, WRO>::RB][QCfg<MP, WRO>::KS],
                                                  const float4* __restrict__ bx, const float* __restrict__ xf,
                                                  int wr, int lane) {
-  using C = QCfg<MP>;
+  using C = QCfg<MP, WRO>;
   floatx4 acc[C::RB];
 #pragma unroll
   for (int rb = 0; rb < C::RB; ++rb) acc[rb] = floatx4{0.f, 0.f, 0.f, 0.f};
