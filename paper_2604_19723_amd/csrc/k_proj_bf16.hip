@@ -40,7 +40,7 @@ __device__ __forceinline__ float lo_half(unsigned w) { return __uint_as_float(w 
 __device__ __forceinline__ float hi_half(unsigned w) { return __uint_as_float(w & 0xffff0000u); }
 
 template <int PREC>
-__global__ __launch_bounds__(256, 1) void k_proj_qb(const float2* __restrict__ R, const uint4* __restrict__ Xb,
+__global__ __launch_bounds__(256, 2) void k_proj_qb(const float2* __restrict__ R, const uint4* __restrict__ Xb,
                                                     float* __restrict__ P, int B, int M, int64_t G, int nchunk,
                                                     int chunks_per_wg, int nsplit) {
   extern __shared__ __attribute__((aligned(16))) uint4 sXb[];  // [2][CHW], LDS DMA
@@ -95,35 +95,19 @@ __global__ __launch_bounds__(256, 1) void k_proj_qb(const float2* __restrict__ R
   for (int c = c0; c < c1; ++c) {
     const int buf = (c - c0) & 1;
     if (c + 1 < c1) BA_FETCH(c + 1, buf ^ 1);
-    // one wave per SIMD: the fragments and epilogue rows of block jb + 1 are
-    // read while block jb is multiplied, so no k-step waits on the LDS
-    uint4 bf[2 * NKC];
-    uint2 xf[RBB][2];
-    auto load_block = [&](int jb, uint4 (&b)[2 * NKC], uint2 (&x)[RBB][2]) {
-      const uint4* bx = sXb + buf * CHW + jb * BLKW;
-#pragma unroll
-      for (int q = 0; q < 2 * NKC; ++q) b[q] = lds_frag(bx, q * 64 + lane);
-#pragma unroll
-      for (int rb = 0; rb < RBB; ++rb) {
-        const int rbg = RBB * wr + rb, kc = rbg >> 1;
-        const int w = (rbg & 1) * 32 + ew;
-        x[rb][0] = lds_frag(reinterpret_cast<const uint2*>(bx + (kc * 2) * 64 + w), eh);
-        x[rb][1] = lds_frag(reinterpret_cast<const uint2*>(bx + (kc * 2 + 1) * 64 + w), eh);
-      }
-    };
-    load_block(0, bf, xf);
+    // two waves per SIMD: each k-step's fragments are read just before its
+    // MFMAs and the epilogue rows after them; the other wave's MFMAs cover
+    // the LDS latency
 #pragma unroll
     for (int jb = 0; jb < NBB; ++jb) {
-      uint4 bn[2 * NKC];
-      uint2 xn[RBB][2];
-      if (jb + 1 < NBB) load_block(jb + 1, bn, xn);
+      const uint4* bx = sXb + buf * CHW + jb * BLKW;
       floatx4 acc[RBB];
 #pragma unroll
       for (int rb = 0; rb < RBB; ++rb) acc[rb] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int kc = 0; kc < NKC; ++kc) {
-        const bf16x8 bh = __builtin_bit_cast(bf16x8, bf[2 * kc]);
-        const bf16x8 bl = __builtin_bit_cast(bf16x8, bf[2 * kc + 1]);
+        const bf16x8 bh = __builtin_bit_cast(bf16x8, lds_frag(bx, (2 * kc) * 64 + lane));
+        const bf16x8 bl = __builtin_bit_cast(bf16x8, lds_frag(bx, (2 * kc + 1) * 64 + lane));
 #pragma unroll
         for (int rb = 0; rb < RBB; ++rb) {
           const bf16x8 vah = __builtin_bit_cast(bf16x8, ah[rb][kc]);
@@ -134,6 +118,14 @@ __global__ __launch_bounds__(256, 1) void k_proj_qb(const float2* __restrict__ R
                                                               acc[rb], 0, 0, 0);
           }
         }
+      }
+      uint2 xf[RBB][2];
+#pragma unroll
+      for (int rb = 0; rb < RBB; ++rb) {
+        const int rbg = RBB * wr + rb, kc = rbg >> 1;
+        const int w = (rbg & 1) * 32 + ew;
+        xf[rb][0] = lds_frag(reinterpret_cast<const uint2*>(bx + (kc * 2) * 64 + w), eh);
+        xf[rb][1] = lds_frag(reinterpret_cast<const uint2*>(bx + (kc * 2 + 1) * 64 + w), eh);
       }
       float part = 0.f;
 #pragma unroll
@@ -147,15 +139,6 @@ __global__ __launch_bounds__(256, 1) void k_proj_qb(const float2* __restrict__ R
       part += __shfl_xor(part, 16, 64);
       part += __shfl_xor(part, 32, 64);
       if (lane < 16) red[buf][wt][wr][jb * 16 + lane] = part;
-      if (jb + 1 < NBB) {
-#pragma unroll
-        for (int q = 0; q < 2 * NKC; ++q) bf[q] = bn[q];
-#pragma unroll
-        for (int rb = 0; rb < RBB; ++rb) {
-          xf[rb][0] = xn[rb][0];
-          xf[rb][1] = xn[rb][1];
-        }
-      }
     }
     lds_dma_wait();
     __syncthreads();
