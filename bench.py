@@ -81,25 +81,59 @@ def rmse_by_snr(ts, refined_deg, idx):
 
 def cpu_baseline(ts, K, seconds):
     """The FP64 oracle on the first trials of the same workload, until the time
-    budget is spent. Steering is built once, outside the clock (as the GPU plan)."""
+    budget is spent, with every BLAS thread and then with one (a third of the
+    budget). Steering is built once, outside the clock (as the GPU plan)."""
     from oracle import bartlett as ob
+    cores, blas, limits = None, None, None
     try:
         import threadpoolctl
-        info = threadpoolctl.threadpool_info()
-        cores = max([i.get("num_threads", 1) for i in info if i.get("user_api") == "blas"] or [1])
+        info = [i for i in threadpoolctl.threadpool_info() if i.get("user_api") == "blas"]
+        cores = max([i.get("num_threads", 1) for i in info] or [1])
+        blas = ", ".join("%s %s" % (i.get("internal_api"), i.get("version")) for i in info) or None
+        limits = threadpoolctl.threadpool_limits
     except Exception:
-        cores = None
+        pass
     A = ob.steering(ts.pos_wl, ob.directions(ts.grid_kind, ts.grid))
-    n = 0
-    t0 = time.perf_counter()
-    while n < ts.n_trials and time.perf_counter() - t0 < seconds:
-        ob.grid_search(ts.Y[n].astype(np.complex128), ts.pos_wl, ts.grid_kind, ts.grid,
-                       ts.grid_shape, ts.wrap0, K, A=A)
-        n += 1
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "trials/s", "cores": cores, "kind": "oracle",
-            "sample": "first %d trials of the timed batch, FP64 numpy (covariance, spectrum via "
-                      "zgemm, peaks, refinement), %.1f s" % (n, dt)}
+
+    def run(budget):
+        n = 0
+        t0 = time.perf_counter()
+        while n < ts.n_trials and time.perf_counter() - t0 < budget:
+            ob.grid_search(ts.Y[n].astype(np.complex128), ts.pos_wl, ts.grid_kind, ts.grid,
+                           ts.grid_shape, ts.wrap0, K, A=A)
+            n += 1
+        return n, time.perf_counter() - t0
+
+    n, dt = run(seconds)
+    out = {"value": n / dt, "unit": "trials/s", "cores": cores, "kind": "oracle",
+           "sample": "first %d trials of the timed batch, FP64 numpy (covariance, spectrum via "
+                     "zgemm, peaks, refinement), %.1f s" % (n, dt),
+           "blas": blas}
+    if limits is not None:
+        with limits(limits=1, user_api="blas"):
+            n1, dt1 = run(seconds / 3)
+        out["value_1core"] = n1 / dt1
+        out["sample_1core"] = "first %d trials with one BLAS thread, %.1f s" % (n1, dt1)
+    return out
+
+
+def rmse_se_by_snr(ts, refined_deg, idx, nboot=200):
+    """Per SNR point: RMSE in degrees and its bootstrap standard error over
+    trials (200 resamples, fixed seed), estimates associated to the truths."""
+    from paper_2604_19723_amd import metrics
+    per = {}
+    for b in range(ts.n_trials):
+        if np.any(idx[b] < 0):
+            continue
+        e = metrics.associated_errors(refined_deg[b], ts.truth[b])
+        per.setdefault(float(ts.snr_db[b]), []).append(np.mean(e * e))
+    rng = np.random.default_rng(0)
+    out = {}
+    for s in sorted(per):
+        v = np.asarray(per[s])
+        boots = [np.sqrt(np.mean(v[rng.integers(0, len(v), len(v))])) for _ in range(nboot)]
+        out["%g" % s] = {"rmse": float(np.sqrt(np.mean(v))), "se": float(np.std(boots))}
+    return out
 
 
 def bench_sequential(args, workers):
@@ -625,6 +659,8 @@ def main():
     ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-f32-reference", action="store_true",
+                    help="with --precision bf16x3|bf16: skip timing the FP32 path on the same trials")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -713,6 +749,40 @@ def main():
         Pr = ob.spectrum(ob.covariance(ts.Y[b].astype(np.complex128)), A)
         errs.append(np.max(np.abs(P_h[b] - Pr)) / np.max(Pr))
 
+    vs_f32 = None
+    if args.precision in ("bf16x3", "bf16") and not args.no_f32_reference:
+        # the plain FP32 path on the same resident trials, same step structure
+        rmse_v = rmse_se_by_snr(ts, est_deg, idx_h)
+        with bb.plan_for(ts, bb.BA_PREC_F32) as plan32:
+            ws32 = bb.spectrum_workspace_for(plan32, B, dev)
+
+            def step32():
+                bb.ba_covariance(plan32, B, T, Y, R)
+                bb.ba_spectrum(plan32, B, R, P, ws32)
+                bb.ba_peaks(plan32, B, P, K, idx, val, ref)
+
+            for _ in range(args.warmup):
+                step32()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                step32()
+            torch.cuda.synchronize()
+            dt32 = time.perf_counter() - t0
+        idx32 = idx.cpu().numpy()
+        est32 = metrics.fractional_index_to_deg(ts.grid_kind, ts.grid, ts.grid_shape, ref.cpu().numpy())
+        rmse_f = rmse_se_by_snr(ts, est32, idx32)
+        eq = {s_: abs(rmse_v[s_]["rmse"] - rmse_f[s_]["rmse"]) <=
+              max(0.01 * rmse_f[s_]["rmse"], 2.0 * max(rmse_v[s_]["se"], rmse_f[s_]["se"]))
+              for s_ in rmse_f if s_ in rmse_v}
+        f32_tps = B * args.steps / dt32
+        vs_f32 = {"f32_trials_per_s": f32_tps, "ratio": (B * args.steps / dt) / f32_tps,
+                  "rmse_deg_by_snr": {k_: v_["rmse"] for k_, v_ in rmse_v.items()},
+                  "f32_rmse_deg_by_snr": {k_: v_["rmse"] for k_, v_ in rmse_f.items()},
+                  "equal_rmse_by_snr": eq, "equal_rmse": bool(eq) and all(eq.values()),
+                  "rule": "|RMSE - RMSE_f32| <= max(1 % RMSE_f32, 2 bootstrap SE), per SNR point"}
+        log("FP32 on the same trials: %.1f ms/step, ratio %.2f, equal RMSE %s" % (
+            dt32 / args.steps * 1e3, vs_f32["ratio"], vs_f32["equal_rmse"]))
     if args.calib_copy_mib:
         n = args.calib_copy_mib * 1024 * 256
         src = torch.ones(n, dtype=torch.float32, device=dev)
@@ -752,6 +822,8 @@ def main():
         "failed_trials": fails,
         "spot_parity_normwise_max": float(np.max(errs)),
     }
+    if vs_f32 is not None:
+        line["vs_f32_same_trials"] = vs_f32
     print(json.dumps(line), flush=True)
     plan.close()
     return 0
