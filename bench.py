@@ -469,7 +469,8 @@ def bench_learned(args, workers):
     X, U, Mk = L.make_training_set(plan, args.train_trials, 1234, dev, log=log)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t
-    net = bb.ba_mlp_create(4096, 512, 3, 4, 1024, bb.BA_PREC_BF16, 99)
+    # maximum batch above the test set: inference runs the whole set in one pass (training uses 1024)
+    net = bb.ba_mlp_create(4096, 512, 3, 4, 16384, bb.BA_PREC_BF16, 99)
     t = time.perf_counter()
     hist = L.train(net, X, U, Mk, args.epochs, 1024, 1e-3, 7, log=log)
     torch.cuda.synchronize()

@@ -19,7 +19,7 @@ DEV = "cuda"
 def test_trained_network_cuts_the_grid_at_equal_rmse():
     grid = wl.ula_grid(lr.G)
     plan = bb.ba_plan_create(lr.M, wl.ula_positions(lr.M), bb.BA_GRID_ULA_DEG, lr.G, grid, lr.G, 1, 0)
-    net = bb.ba_mlp_create(lr.M * lr.M, 512, 3, lr.K, 1024, bb.BA_PREC_BF16, 21)
+    net = bb.ba_mlp_create(lr.M * lr.M, 512, 3, lr.K, 16384, bb.BA_PREC_BF16, 21)
     try:
         X, U, Mk = lr.make_training_set(plan, 262144, 0xBA57_00F1, DEV)
         hist = lr.train(net, X, U, Mk, epochs=6, batch=1024, lr=1e-3, seed=3)
