@@ -53,6 +53,23 @@ def measured_traffic(key):
         return None
 
 
+# projection kernels that evaluate x^T Q x in its symmetric form (upper triangle of Q)
+SYMMETRIC_KERNELS = {"k_proj_q", "k_proj_qb"}
+
+
+def proj_flops_per_point(M, kernel):
+    """Algorithmic flops of one spectrum value of an M-element array. A kernel
+    in the symmetric form computes x^T Q x as 2 x^T U x over the upper triangle
+    of the 2M x 2M real Q, diagonal included: K (K + 1) / 2 multiply-adds with
+    K = 2M, plus the epilogue's K products and K sums (the way a symmetric
+    rank-k update is counted at half a GEMM). The full form Q x counts 8M^2,
+    plus 8M for its epilogue."""
+    if kernel in SYMMETRIC_KERNELS:
+        K = 2 * M
+        return float(K * (K + 1) + 2 * K)
+    return 8.0 * M * M + 8.0 * M
+
+
 def proj_kernel_name(precision, n_elem):
     """The kernel that evaluates the projection for a precision and array size."""
     if precision == "f32_valu":
@@ -184,7 +201,7 @@ def bench_sequential(args, workers):
     torch.cuda.synchronize()
     est_p = metrics.fractional_index_to_deg(ts.grid_kind, ts.grid, ts.grid_shape, out["refined"].cpu().numpy())
     rmse_plain, fails_plain = rmse_by_snr(ts, est_p, out["idx"].cpu().numpy())
-    flops = float(B) * K * (8.0 * M * M * G + 8.0 * M * G)
+    flops = float(B) * K * G * proj_flops_per_point(M, proj_kernel_name(args.precision, M))
     bound, peak = PEAK[args.precision]
     achieved = flops / (seq_ms * 1e-3) / 1e12
     value = B * args.steps / dt
@@ -266,7 +283,7 @@ def bench_proposal(args, workers):
     proj_ms, mom_ms, samp_ms = (float(np.mean(x)) for x in (proj, mom, samp))
     log("timed %d steps: %.3f ms/step; projection %.3f, moments %.3f, sampling %.3f ms" % (
         args.steps, dt / args.steps * 1e3, proj_ms, mom_ms, samp_ms))
-    flops = float(B) * (8.0 * M * M * G + 8.0 * M * G)
+    flops = float(B) * G * proj_flops_per_point(M, "k_proj_q")
     samp_bytes = float(B) * N * (2 * d + 1) * 8 + B * (d + d * d) * 8     # z in, particles + weights out
     mom_bytes = float(B) * G * 4 + B * (d + d * d) * 8
     wh = w.cpu().numpy()
@@ -731,7 +748,7 @@ def main():
     proj_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
     log("timed %d steps: %.3f ms/step, projection %.3f ms" % (args.steps, dt / args.steps * 1e3, proj_ms))
 
-    flops_proj = float(B) * (8.0 * M * M * G + 8.0 * M * G)
+    flops_proj = float(B) * G * proj_flops_per_point(M, proj_kernel_name(args.precision, M))
     bound, peak = PEAK[args.precision]
     achieved = flops_proj / (proj_ms * 1e-3) / 1e12
 
@@ -816,7 +833,9 @@ def main():
                      "traffic": measured_traffic("%s|%s|%s|b%d" % (
                          proj_kernel_name(args.precision, M), args.precision, ts.name, B)),
                      "kernel": proj_kernel_name(args.precision, M), "kernel_ms": proj_ms,
-                     "flops_per_launch": flops_proj},
+                     "flops_per_launch": flops_proj,
+                     "form": ("symmetric: upper triangle of the 2M x 2M real Q"
+                              if proj_kernel_name(args.precision, M) in SYMMETRIC_KERNELS else "full Q")},
         "cpu_baseline": cpu,
         "grid_points_trials_per_s": value * G,
         "rmse_deg_by_snr": rmse,

@@ -1,17 +1,22 @@
 // Split-precision Bartlett projection for arrays of up to 64 elements with Q
 // resident in registers (the BF16 counterpart of k_proj_q).
 //
-// Q X ~= Qh Xh + Qh Xl + Ql Xh on v_mfma_f32_16x16x32_bf16, FP32 accumulate
-// (hi = bf16(q), lo = bf16(q - hi), round to nearest even; the lo*lo term is
-// dropped). Q's hi/lo fragments are built from R once per workgroup; the BF16
-// steering chunks (hi and lo interleaved per k-step) arrive by LDS DMA one
-// chunk ahead. The quadratic-form epilogue takes x = xh + xl from the same
-// LDS chunk (16 significant bits, below the error of the dropped term).
+// U X ~= Uh Xh + Uh Xl + Ul Xh on v_mfma_f32_16x16x32_bf16, FP32 accumulate
+// (hi = bf16(u), lo = bf16(u - hi), round to nearest even; the lo*lo term is
+// dropped), with U the upper triangle of the symmetric Q (diagonal halved), so
+// x^T Q x = 2 x^T U x. Row block rb of U needs the k-steps of 32 from rb / 2
+// on; the pairs of row blocks (p, 7 - p) a wave holds need 5 of the 8 k-steps
+// of the full Q. U's hi/lo fragments are built from R once per workgroup;
+// the BF16 steering chunks (hi and lo interleaved per k-step) arrive by LDS
+// DMA one chunk ahead. The quadratic-form epilogue takes x = xh + xl from the
+// same LDS chunk (16 significant bits, below the error of the dropped term).
 //
 // A workgroup serves two trials, so every steering chunk brought on chip is
-// used twice: 4 waves = 2 trials x 2 halves of Q's 128 rows (4 row blocks
-// each). Per 16-column block a wave issues 4 x 4 x 3 = 48 MFMAs against 8
-// conflict-free 16-byte LDS reads and 8 8-byte epilogue reads.
+// used twice: 4 waves = 2 trials x 2 row waves. Row wave w holds the row
+// blocks {w, 7 - w, 2 + w, 5 - w}, whose first k-steps are {0, 3, 1, 2} for
+// either w, so both run the same code. Per 16-column block a wave issues
+// 10 x 3 = 30 MFMAs against 8 conflict-free 16-byte LDS reads and 8 8-byte
+// epilogue reads.
 #include "proj_common.h"
 
 namespace ba {
@@ -22,12 +27,21 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr int MPB = 64;             // padded element count
 constexpr int KB = 2 * MPB;         // 128 rows of Q
 constexpr int NKC = KB / 32;        // 4 k-steps of 32
-constexpr int WRB = 2, RBB = 4;     // row waves per trial, row blocks per wave
+constexpr int WRB = 2;              // row waves per trial
+constexpr int NSLOT = 4;            // row blocks per wave
+constexpr int NFRAG = 10;           // k-steps held per wave: 4 + 1 + 3 + 2
 constexpr int NTW = 2;              // trials per workgroup
 constexpr int BLKW = NKC * 2 * 64;  // 16-byte words per 16-column block (8 KB)
 constexpr int NBB = 4;              // blocks per 32 KB chunk
 constexpr int CHW = NBB * BLKW;     // 16-byte words per chunk
-static_assert(WRB * RBB * 16 == KB, "row waves must cover Q");
+
+// row block of slot j for row wave w, its first k-step, and its first register
+__device__ __forceinline__ constexpr int slot_rb(int j, int w) {
+  return j == 0 ? w : (j == 1 ? 7 - w : (j == 2 ? 2 + w : 5 - w));
+}
+__device__ __forceinline__ constexpr int slot_kc0(int j) { return j == 0 ? 0 : (j == 1 ? 3 : (j == 2 ? 1 : 2)); }
+__device__ __forceinline__ constexpr int slot_off(int j) { return j == 0 ? 0 : (j == 1 ? 4 : (j == 2 ? 5 : 8)); }
+static_assert(slot_off(3) + NKC - slot_kc0(3) == NFRAG, "fragment count");
 
 __device__ __forceinline__ unsigned short bf16_bits(float x) {
   unsigned u = __float_as_uint(x);
@@ -57,24 +71,28 @@ __global__ __launch_bounds__(256, 2) void k_proj_qb(const float2* __restrict__ R
   const int64_t b = pair * NTW + wt;
   const int64_t bq = b < B ? b : pair * NTW;
 
-  // A operand hi/lo: rows i = 16 (4 wr + rb) + lane%16, k = 32 kc + 8 (lane/16) + e
-  uint4 ah[RBB][NKC], al[RBB][NKC];
+  // A operand hi/lo of U: slot j, k-step kc >= slot_kc0(j): rows
+  // i = 16 slot_rb(j, wr) + lane%16, k = 32 kc + 8 (lane/16) + e
+  uint4 ah[NFRAG], al[NFRAG];
   const float2* Rb = R + bq * int64_t(M) * M;
 #pragma unroll
-  for (int rb = 0; rb < RBB; ++rb)
+  for (int j = 0; j < NSLOT; ++j)
 #pragma unroll
-    for (int kc = 0; kc < NKC; ++kc) {
+    for (int kc = slot_kc0(j); kc < NKC; ++kc) {
+      const int i = 16 * slot_rb(j, wr) + (lane & 15);
       unsigned short h[8], l[8];
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const float q = qval(Rb, M, MPB, 16 * (RBB * wr + rb) + (lane & 15), 32 * kc + 8 * (lane >> 4) + e);
+        const int k = 32 * kc + 8 * (lane >> 4) + e;
+        const float q = k < i ? 0.f : (k == i ? 0.5f : 1.f) * qval(Rb, M, MPB, i, k);
         h[e] = bf16_bits(q);
         l[e] = bf16_bits(q - __uint_as_float(unsigned(h[e]) << 16));
       }
-      ah[rb][kc] = make_uint4(h[0] | (unsigned(h[1]) << 16), h[2] | (unsigned(h[3]) << 16),
-                              h[4] | (unsigned(h[5]) << 16), h[6] | (unsigned(h[7]) << 16));
-      al[rb][kc] = make_uint4(l[0] | (unsigned(l[1]) << 16), l[2] | (unsigned(l[3]) << 16),
-                              l[4] | (unsigned(l[5]) << 16), l[6] | (unsigned(l[7]) << 16));
+      const int f = slot_off(j) + kc - slot_kc0(j);
+      ah[f] = make_uint4(h[0] | (unsigned(h[1]) << 16), h[2] | (unsigned(h[3]) << 16),
+                         h[4] | (unsigned(h[5]) << 16), h[6] | (unsigned(h[7]) << 16));
+      al[f] = make_uint4(l[0] | (unsigned(l[1]) << 16), l[2] | (unsigned(l[3]) << 16),
+                         l[4] | (unsigned(l[5]) << 16), l[6] | (unsigned(l[7]) << 16));
     }
 
 #define BA_FETCH(c, buf)                                                                  \
@@ -88,7 +106,7 @@ __global__ __launch_bounds__(256, 2) void k_proj_qb(const float2* __restrict__ R
   BA_FETCH(c0, 0);
   lds_dma_wait();
   __syncthreads();
-  const float invM2 = 1.0f / float(M * M);
+  const float scale = 2.0f / float(M * M);  // P = 2 x^T U x / M^2
   // epilogue: lane holds D rows 16 rbg + 4 (lane/16) + e, column lane%16; in the
   // B layout those are 4 consecutive values of one 16-byte word
   const int ew = (lane >> 5) * 16 + (lane & 15), eh = (lane >> 4) & 1;
@@ -101,40 +119,42 @@ __global__ __launch_bounds__(256, 2) void k_proj_qb(const float2* __restrict__ R
 #pragma unroll
     for (int jb = 0; jb < NBB; ++jb) {
       const uint4* bx = sXb + buf * CHW + jb * BLKW;
-      floatx4 acc[RBB];
+      floatx4 acc[NSLOT];
 #pragma unroll
-      for (int rb = 0; rb < RBB; ++rb) acc[rb] = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (int j = 0; j < NSLOT; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int kc = 0; kc < NKC; ++kc) {
         const bf16x8 bh = __builtin_bit_cast(bf16x8, lds_frag(bx, (2 * kc) * 64 + lane));
         const bf16x8 bl = __builtin_bit_cast(bf16x8, lds_frag(bx, (2 * kc + 1) * 64 + lane));
 #pragma unroll
-        for (int rb = 0; rb < RBB; ++rb) {
-          const bf16x8 vah = __builtin_bit_cast(bf16x8, ah[rb][kc]);
-          acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vah, bh, acc[rb], 0, 0, 0);
+        for (int j = 0; j < NSLOT; ++j) {
+          if (kc < slot_kc0(j)) continue;
+          const int f = slot_off(j) + kc - slot_kc0(j);
+          const bf16x8 vah = __builtin_bit_cast(bf16x8, ah[f]);
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vah, bh, acc[j], 0, 0, 0);
           if (PREC == BA_PREC_BF16X3) {
-            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vah, bl, acc[rb], 0, 0, 0);
-            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, al[rb][kc]), bh,
-                                                              acc[rb], 0, 0, 0);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vah, bl, acc[j], 0, 0, 0);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, al[f]), bh, acc[j], 0, 0,
+                                                             0);
           }
         }
       }
-      uint2 xf[RBB][2];
+      uint2 xf[NSLOT][2];
 #pragma unroll
-      for (int rb = 0; rb < RBB; ++rb) {
-        const int rbg = RBB * wr + rb, kc = rbg >> 1;
+      for (int j = 0; j < NSLOT; ++j) {
+        const int rbg = slot_rb(j, wr), kc = rbg >> 1;
         const int w = (rbg & 1) * 32 + ew;
-        xf[rb][0] = lds_frag(reinterpret_cast<const uint2*>(bx + (kc * 2) * 64 + w), eh);
-        xf[rb][1] = lds_frag(reinterpret_cast<const uint2*>(bx + (kc * 2 + 1) * 64 + w), eh);
+        xf[j][0] = lds_frag(reinterpret_cast<const uint2*>(bx + (kc * 2) * 64 + w), eh);
+        xf[j][1] = lds_frag(reinterpret_cast<const uint2*>(bx + (kc * 2 + 1) * 64 + w), eh);
       }
       float part = 0.f;
 #pragma unroll
-      for (int rb = 0; rb < RBB; ++rb) {
-        const uint2 xh = xf[rb][0], xl = xf[rb][1];
-        part += (lo_half(xh.x) + lo_half(xl.x)) * acc[rb][0];
-        part += (hi_half(xh.x) + hi_half(xl.x)) * acc[rb][1];
-        part += (lo_half(xh.y) + lo_half(xl.y)) * acc[rb][2];
-        part += (hi_half(xh.y) + hi_half(xl.y)) * acc[rb][3];
+      for (int j = 0; j < NSLOT; ++j) {
+        const uint2 xh = xf[j][0], xl = xf[j][1];
+        part += (lo_half(xh.x) + lo_half(xl.x)) * acc[j][0];
+        part += (hi_half(xh.x) + hi_half(xl.x)) * acc[j][1];
+        part += (lo_half(xh.y) + lo_half(xl.y)) * acc[j][2];
+        part += (hi_half(xh.y) + hi_half(xl.y)) * acc[j][3];
       }
       part += __shfl_xor(part, 16, 64);
       part += __shfl_xor(part, 32, 64);
@@ -146,7 +166,7 @@ __global__ __launch_bounds__(256, 2) void k_proj_qb(const float2* __restrict__ R
       const int t = threadIdx.x % (NBB * 16), tw = threadIdx.x / (NBB * 16);
       const int64_t bo = pair * NTW + tw;
       const int64_t g = int64_t(c) * NBB * 16 + t;
-      if (bo < B && g < G) P[bo * G + g] = (red[buf][tw][0][t] + red[buf][tw][1][t]) * invM2;
+      if (bo < B && g < G) P[bo * G + g] = (red[buf][tw][0][t] + red[buf][tw][1][t]) * scale;
     }
   }
 #undef BA_FETCH

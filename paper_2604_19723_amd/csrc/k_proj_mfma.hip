@@ -8,32 +8,37 @@
 // output never leaves the registers (Sec. IV-D.2 cost, written as a dense
 // contraction over the candidate set).
 //
+// Q is symmetric, so x^T Q x = 2 x^T U x with U its upper triangle (diagonal
+// halved): the GEMM runs over U only, about half the MFMAs of Q X.
+//
 // MI355X mapping (v_mfma_f32_16x16x4f32, FP32 in and out):
 //  * one workgroup = one trial x a range of grid columns; 4 waves;
-//  * Q is built from R once per workgroup straight into MFMA A-operand
-//    registers (each wave owns RB row blocks of 16 rows, all K; at M = 64
-//    two waves split the 128 rows and the two wave pairs split the 16-column
-//    blocks of a chunk);
+//  * U is built from R once per workgroup straight into MFMA A-operand
+//    registers; each wave owns the pair of 16-row blocks (p, 2M/16 - 1 - p),
+//    whose k ranges right of the diagonal add up to the same length for every
+//    p (at M = 64 the four waves take the four pairs and share all columns;
+//    smaller arrays split the 16-column blocks of a chunk between waves);
 //  * the steering table is stored in HBM already in B-fragment order (16
 //    columns per block, 4 k-steps per lane per 16-byte word), so one chunk of
-//    32 KB is a straight copy into LDS, done by the gfx950 LDS DMA
+//    8 KB is a straight copy into LDS, done by the gfx950 LDS DMA
 //    (global_load_lds_dwordx4, no registers involved) one chunk ahead, and
 //    every fragment read is a conflict-free ds_read_b128;
-//  * epilogue: the accumulator tile is multiplied by the matching rows of the
-//    same LDS tile, reduced across the 4 row-groups of a wave by two lane
-//    shuffles and across waves through LDS, then scaled by 1/M^2.
+//  * epilogue: the accumulator tiles are multiplied by the matching rows of
+//    the same LDS tile, reduced across the 4 row-groups of a wave by two lane
+//    shuffles and across waves through LDS in a fixed order, then scaled by
+//    2/M^2.
 // Element counts up to 64 are padded to MP in {8, 16, 32, 64} with zero rows.
 #include "proj_common.h"
 
 namespace ba {
 namespace {
 
-template <int MP, int WRO>
+template <int MP>
 __global__ __launch_bounds__(256, 2) void k_proj_q(const float2* __restrict__ R,
                                                    const float4* __restrict__ Xg,
                                                    float* __restrict__ P, int M, int64_t G,
                                                    int nchunk, int chunks_per_wg, int nsplit) {
-  using C = QCfg<MP, WRO>;
+  using C = QCfg<MP>;
   extern __shared__ __attribute__((aligned(16))) float4 sX[];   // [2][CH4], dynamic: filled by LDS DMA
   __shared__ float red[2][C::WR][C::NB * 16];
 
@@ -53,13 +58,13 @@ __global__ __launch_bounds__(256, 2) void k_proj_q(const float2* __restrict__ R,
     }
   };
 
-  float a[C::RB][C::KS];
-  load_q_fragments<MP, WRO>(R + b * int64_t(M) * M, M, wr, lane, a);
+  float a[C::VL];
+  load_q_fragments<MP>(R + b * int64_t(M) * M, M, wr, lane, a);
   fetch(c0, 0);
   lds_dma_wait();
   __syncthreads();
 
-  const float invM2 = 1.0f / float(M * M);
+  const float scale = 2.0f / float(M * M);  // P = 2 x^T U x / M^2
   for (int c = c0; c < c1; ++c) {
     const int buf = (c - c0) & 1;
     const bool more = c + 1 < c1;
@@ -67,10 +72,10 @@ __global__ __launch_bounds__(256, 2) void k_proj_q(const float2* __restrict__ R,
     const float4* sxb = sX + buf * C::CH4;
     const float* sx = reinterpret_cast<const float*>(sxb);
     for (int jb = wc; jb < C::NB; jb += C::WC) {
-      const float part = block_quadratic<MP, WRO>(a, sxb + jb * (C::BLK / 4), sx + jb * C::BLK, wr, lane);
+      const float part = block_quadratic<MP>(a, sxb + jb * (C::BLK / 4), sx + jb * C::BLK, wr, lane);
       if (C::WR == 1) {
         const int64_t g = int64_t(c) * C::NB * 16 + jb * 16 + lane;
-        if (lane < 16 && g < G) P[b * G + g] = part * invM2;
+        if (lane < 16 && g < G) P[b * G + g] = part * scale;
       } else if (lane < 16) {
         red[buf][wr][jb * 16 + lane] = part;
       }
@@ -83,15 +88,15 @@ __global__ __launch_bounds__(256, 2) void k_proj_q(const float2* __restrict__ R,
 #pragma unroll
         for (int w = 0; w < C::WR; ++w) s += red[buf][w][t];
         const int64_t g = int64_t(c) * C::NB * 16 + t;
-        if (g < G) P[b * G + g] = s * invM2;
+        if (g < G) P[b * G + g] = s * scale;
       }
     }
   }
 }
 
-template <int MP, int WRO = 0>
+template <int MP>
 hipError_t launch_q(const Plan& p, int B, const float2* R, float* P, hipStream_t s) {
-  using C = QCfg<MP, WRO>;
+  using C = QCfg<MP>;
   const int nchunk = int((p.Gb + C::NB - 1) / C::NB);  // the table holds Xblocks >= nchunk * NB
   // split the grid columns over several workgroups when there are few trials
   int nsplit = 1;
@@ -100,7 +105,7 @@ hipError_t launch_q(const Plan& p, int B, const float2* R, float* P, hipStream_t
   nsplit = (nchunk + per - 1) / per;
   const int64_t nblk = int64_t(B) * nsplit;
   if (nblk > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_proj_q<MP, WRO>), dim3(unsigned(nblk)), dim3(256), 2 * C::CH4 * sizeof(float4), s, R,
+  hipLaunchKernelGGL((k_proj_q<MP>), dim3(unsigned(nblk)), dim3(256), 2 * C::CH4 * sizeof(float4), s, R,
                      reinterpret_cast<const float4*>(p.d_X), P, p.M, p.G, nchunk, per, nsplit);
   return hipGetLastError();
 }
@@ -112,7 +117,7 @@ hipError_t launch_spectrum_mfma(const Plan& p, int B, const float2* R, float* P,
     case 8: return launch_q<8>(p, B, R, P, s);
     case 16: return launch_q<16>(p, B, R, P, s);
     case 32: return launch_q<32>(p, B, R, P, s);
-    case 64: return launch_q<64, kProjWR<64>>(p, B, R, P, s);
+    case 64: return launch_q<64>(p, B, R, P, s);
     default: return hipErrorInvalidValue;
   }
 }

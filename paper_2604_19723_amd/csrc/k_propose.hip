@@ -35,8 +35,7 @@ __device__ double parabolic(double pm, double p0, double pp) {
 
 template <int MP>
 __global__ __launch_bounds__(256) void k_window(WindowArgs A) {
-  constexpr int WRO = kProjWR<MP>;
-  using C = QCfg<MP, WRO>;
+  using C = QCfg<MP>;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   // LDS sized for the windows of this launch: nbmax blocks of one window, then
   // the spectrum rows of the K windows
@@ -57,8 +56,8 @@ __global__ __launch_bounds__(256) void k_window(WindowArgs A) {
   const int M = A.M, K = A.K;
   const float2* Rb = A.R + b * int64_t(M) * M;
 
-  float a[C::RB][C::KS];
-  load_q_fragments<MP, WRO>(Rb, M, wr, lane, a);
+  float a[C::VL];
+  load_q_fragments<MP>(Rb, M, wr, lane, a);
 
   if (threadIdx.x == 0) {
     float tr = 0.f;
@@ -88,7 +87,7 @@ __global__ __launch_bounds__(256) void k_window(WindowArgs A) {
   }
   __syncthreads();
 
-  const float invM2 = 1.0f / float(M * M);
+  const float scale = 2.0f / float(M * M);  // as the full-grid kernel: P = 2 x^T U x / M^2
   for (int k = 0; k < K; ++k) {
     const int jb0 = s_jb0[k], nbw = s_hi[k] / 16 - jb0 + 1;
     // the window's blocks are a contiguous slice of the table
@@ -96,7 +95,7 @@ __global__ __launch_bounds__(256) void k_window(WindowArgs A) {
     for (int v = threadIdx.x; v < nbw * (C::BLK / 4); v += 256) sX[v] = src[v];
     __syncthreads();
     for (int jb = wc; jb < nbw; jb += C::WC) {
-      const float part = block_quadratic<MP, WRO>(a, sX + jb * (C::BLK / 4),
+      const float part = block_quadratic<MP>(a, sX + jb * (C::BLK / 4),
                                              reinterpret_cast<const float*>(sX) + jb * C::BLK, wr, lane);
       if (lane < 16) red[wr][jb * 16 + lane] = part;
     }
@@ -105,7 +104,7 @@ __global__ __launch_bounds__(256) void k_window(WindowArgs A) {
       float s = 0.f;
 #pragma unroll
       for (int w = 0; w < C::WR; ++w) s += red[w][t];
-      sP[k * (16 * nbmax) + t] = s * invM2;
+      sP[k * (16 * nbmax) + t] = s * scale;
     }
     __syncthreads();
   }

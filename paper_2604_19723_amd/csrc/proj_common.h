@@ -8,29 +8,29 @@ namespace ba {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-template <int MP, int WRO = 0>
+// Register-resident projection in its symmetric form. Q is symmetric, so
+//   x^T Q x = 2 x^T U x,  U = the upper triangle of Q with its diagonal halved,
+// and the 16-row block rb of U is zero left of its diagonal block: it needs
+// only the k-steps s >= 4 rb. Each wave takes the pair of row blocks
+// (p, RBLK - 1 - p), whose k ranges together always span KS + 4 steps, so the
+// waves carry equal work and about half the MFMAs of the full Q x.
+template <int MP>
 struct QCfg {
   static constexpr int K = 2 * MP;                 // GEMM depth = rows of Q
   static constexpr int KS = K / 4;                 // MFMA k-steps
   static constexpr int RBLK = K / 16;              // 16-row blocks of Q
-  // waves along rows (WRO > 0 overrides the default split)
-  static constexpr int WR = WRO > 0 ? WRO : (RBLK >= 8 ? 4 : (RBLK >= 4 ? 2 : 1));
-  static constexpr int RB = RBLK / WR;             // row blocks per wave
+  static constexpr bool PAIRS = RBLK >= 2;         // a single block (MP = 8) has no partner
+  static constexpr int WR = PAIRS ? RBLK / 2 : 1;  // waves along rows, one pair each
   static constexpr int WC = 4 / WR;                // waves along columns
+  static constexpr int VL = PAIRS ? KS + 4 : KS;   // A-fragment registers per wave
+  // steering chunks of 8 KB (one 16-column block at M = 64): with the small
+  // register footprint of the symmetric form, short chunks let six
+  // workgroups share a CU and hide each other's barrier and DMA waits
   static constexpr int BLK = K * 16;               // floats per 16-column block
-  static constexpr int NB = 8192 / BLK;            // blocks per 32 KB chunk
-  static constexpr int CH4 = 8192 / 4;             // float4 per chunk
-  static constexpr int F4 = CH4 / 256;             // float4 per thread per chunk
+  static constexpr int NB = 2048 / BLK;            // blocks per chunk
+  static constexpr int CH4 = 2048 / 4;             // float4 per chunk
+  static_assert(WR >= 1 && WR <= 4, "at most four row waves");
 };
-
-// Row split of the register-resident projection at each padded size: for
-// MP = 64 two waves along rows (four row blocks each, the 16-column blocks
-// shared out between the two wave pairs) halves the B-fragment LDS reads and
-// gives each wave four independent accumulators. The full-grid kernel and the
-// refinement-window kernel use the same split, so window values equal the
-// full-grid values bit for bit.
-template <int MP>
-constexpr int kProjWR = MP == 64 ? 2 : 0;
 
 // Direct global -> LDS copy of 16 bytes per lane (global_load_lds_dwordx4):
 // lane i's word lands at lds_wave + 16 i. lds_wave must be wave-uniform and
@@ -63,51 +63,95 @@ __device__ __forceinline__ float qval(const float2* __restrict__ Rb, int M, int 
   return (iim == kim) ? r.x : (iim ? r.y : -r.y);
 }
 
-// A operand of the waves' rows: rows i = wr*RB*16 + rb*16 + lane%16, k = 4s + lane/16
-template <int MP, int WRO = 0>
-__device__ __forceinline__ void load_q_fragments(const float2* __restrict__ Rb, int M, int wr, int lane,
-                                                 float (&a)[QCfg<MP, WRO>::RB][QCfg<MP, WRO>::KS]) {
-  using C = QCfg<MP, WRO>;
-#pragma unroll
-  for (int rb = 0; rb < C::RB; ++rb)
-#pragma unroll
-    for (int s = 0; s < C::KS; ++s)
-      a[rb][s] = qval(Rb, M, MP, wr * C::RB * 16 + rb * 16 + (lane & 15), 4 * s + (lane >> 4));
+// U(i, k) for the symmetric form: Q(i, k) right of the diagonal, half the
+// diagonal, zero left of it
+__device__ __forceinline__ float uval(const float2* __restrict__ Rb, int M, int MP, int i, int k) {
+  if (k < i) return 0.f;
+  const float q = qval(Rb, M, MP, i, k);
+  return k == i ? 0.5f * q : q;
 }
 
-// One 16-column block: returns, in lanes 0..15, this wave's partial
-// sum over its rows of x_g[i] (Q x_g)[i] for the block's columns.
-template <int MP, int WRO = 0>
-__device__ __forceinline__ float block_quadratic(const float (&a)[QCfg<MP, WRO>::RB][QCfg<MP, WRO>::KS],
-                                                 const float4* __restrict__ bx, const float* __restrict__ xf,
-                                                 int wr, int lane) {
-  using C = QCfg<MP, WRO>;
-  floatx4 acc[C::RB];
+// A operand of wave wr's row-block pair, in its virtual step order: steps
+// v < KS - 4 wr hold row block wr at k-step 4 wr + v; the 4 (wr + 1) steps
+// after them hold row block RBLK - 1 - wr at k-step v - 4. Row i = 16 rb +
+// lane % 16, k = 4 s + lane / 16.
+template <int MP>
+__device__ __forceinline__ void load_q_fragments(const float2* __restrict__ Rb, int M, int wr, int lane,
+                                                 float (&a)[QCfg<MP>::VL]) {
+  using C = QCfg<MP>;
+  const int nlo = C::KS - 4 * wr;
 #pragma unroll
-  for (int rb = 0; rb < C::RB; ++rb) acc[rb] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int s4 = 0; s4 < C::KS / 4; ++s4) {
-    const float4 bv = bx[s4 * 64 + lane];
-#pragma unroll
-    for (int rb = 0; rb < C::RB; ++rb) {
-      acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 0], bv.x, acc[rb], 0, 0, 0);
-      acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 1], bv.y, acc[rb], 0, 0, 0);
-      acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 2], bv.z, acc[rb], 0, 0, 0);
-      acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 3], bv.w, acc[rb], 0, 0, 0);
-    }
+  for (int v = 0; v < C::VL; ++v) {
+    const bool lo = v < nlo;
+    const int rb = lo ? wr : C::RBLK - 1 - wr;
+    const int s = lo ? 4 * wr + v : v - 4;
+    a[v] = uval(Rb, M, MP, rb * 16 + (lane & 15), 4 * s + (lane >> 4));
   }
+}
+
+// x_i (U x)_i summed over the 16 rows of row block RB and the four values each
+// lane holds of it
+template <int RB>
+__device__ __forceinline__ float row_block_dot(const floatx4& acc, const float* __restrict__ xf, int lane) {
   float part = 0.f;
 #pragma unroll
-  for (int rb = 0; rb < C::RB; ++rb)
+  for (int r = 0; r < 4; ++r) {
+    const int i = RB * 16 + 4 * (lane >> 4) + r;
+    const int s = i >> 2;
+    part += xf[((s >> 2) * 64 + r * 16 + (lane & 15)) * 4 + (s & 3)] * acc[r];
+  }
+  return part;
+}
+
+template <int MP, int PP>
+__device__ __forceinline__ float pair_quadratic(const float (&a)[QCfg<MP>::VL], const float4* __restrict__ bx,
+                                                const float* __restrict__ xf, int lane) {
+  using C = QCfg<MP>;
+  constexpr int LO = PP, HI = C::RBLK - 1 - PP;  // HI >= LO; equal only without pairs
+  constexpr int NLO = C::KS - 4 * LO;
+  floatx4 alo = floatx4{0.f, 0.f, 0.f, 0.f}, ahi = alo;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = wr * C::RB * 16 + rb * 16 + 4 * (lane >> 4) + r;
-      const int s = i >> 2;
-      part += xf[((s >> 2) * 64 + r * 16 + (lane & 15)) * 4 + (s & 3)] * acc[rb][r];
+  for (int s4 = LO; s4 < C::RBLK; ++s4) {
+    const float4 bv = bx[s4 * 64 + lane];
+    const int vl = 4 * (s4 - LO);
+    alo = __builtin_amdgcn_mfma_f32_16x16x4f32(a[vl + 0], bv.x, alo, 0, 0, 0);
+    alo = __builtin_amdgcn_mfma_f32_16x16x4f32(a[vl + 1], bv.y, alo, 0, 0, 0);
+    alo = __builtin_amdgcn_mfma_f32_16x16x4f32(a[vl + 2], bv.z, alo, 0, 0, 0);
+    alo = __builtin_amdgcn_mfma_f32_16x16x4f32(a[vl + 3], bv.w, alo, 0, 0, 0);
+    if (C::PAIRS && s4 >= HI) {
+      const int vh = NLO + 4 * (s4 - HI);
+      ahi = __builtin_amdgcn_mfma_f32_16x16x4f32(a[vh + 0], bv.x, ahi, 0, 0, 0);
+      ahi = __builtin_amdgcn_mfma_f32_16x16x4f32(a[vh + 1], bv.y, ahi, 0, 0, 0);
+      ahi = __builtin_amdgcn_mfma_f32_16x16x4f32(a[vh + 2], bv.z, ahi, 0, 0, 0);
+      ahi = __builtin_amdgcn_mfma_f32_16x16x4f32(a[vh + 3], bv.w, ahi, 0, 0, 0);
     }
+  }
+  float part = row_block_dot<LO>(alo, xf, lane);
+  if (C::PAIRS) part += row_block_dot<HI>(ahi, xf, lane);
   part += __shfl_xor(part, 16, 64);
   part += __shfl_xor(part, 32, 64);
   return part;
+}
+
+// One 16-column block: returns, in lanes 0..15, this wave's partial sum
+// x^T U x over its row-block pair for the block's columns (half the wave's
+// share of the spectrum value times M^2).
+template <int MP>
+__device__ __forceinline__ float block_quadratic(const float (&a)[QCfg<MP>::VL], const float4* __restrict__ bx,
+                                                 const float* __restrict__ xf, int wr, int lane) {
+  using C = QCfg<MP>;
+  if constexpr (C::WR == 1) {
+    return pair_quadratic<MP, 0>(a, bx, xf, lane);
+  } else if constexpr (C::WR == 2) {
+    return wr == 0 ? pair_quadratic<MP, 0>(a, bx, xf, lane) : pair_quadratic<MP, 1>(a, bx, xf, lane);
+  } else {
+    switch (wr) {
+      case 0: return pair_quadratic<MP, 0>(a, bx, xf, lane);
+      case 1: return pair_quadratic<MP, 1>(a, bx, xf, lane);
+      case 2: return pair_quadratic<MP, 2>(a, bx, xf, lane);
+      default: return pair_quadratic<MP, 3>(a, bx, xf, lane);
+    }
+  }
 }
 
 }  // namespace ba
