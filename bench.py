@@ -54,13 +54,13 @@ def measured_traffic(key):
 
 
 # projection kernels that evaluate x^T Q x in its symmetric form (upper triangle of Q)
-SYMMETRIC_KERNELS = {"k_proj_q", "k_proj_qb"}
+SYMMETRIC_KERNELS = {"k_proj_q", "k_proj_qb", "k_proj_s"}
 
 
 def proj_flops_per_point(M, kernel):
     """Algorithmic flops of one spectrum value of an M-element array. A kernel
-    in the symmetric form computes x^T Q x as 2 x^T U x over the upper triangle
-    of the 2M x 2M real Q, diagonal included: K (K + 1) / 2 multiply-adds with
+    in the symmetric form computes x^T Q x as 2 x^T U x over one triangle of
+    the 2M x 2M real Q, diagonal included: K (K + 1) / 2 multiply-adds with
     K = 2M, plus the epilogue's K products and K sums (the way a symmetric
     rank-k update is counted at half a GEMM). The full form Q x counts 8M^2,
     plus 8M for its epilogue."""
@@ -834,7 +834,7 @@ def main():
                          proj_kernel_name(args.precision, M), args.precision, ts.name, B)),
                      "kernel": proj_kernel_name(args.precision, M), "kernel_ms": proj_ms,
                      "flops_per_launch": flops_proj,
-                     "form": ("symmetric: upper triangle of the 2M x 2M real Q"
+                     "form": ("symmetric: one triangle of the 2M x 2M real Q"
                               if proj_kernel_name(args.precision, M) in SYMMETRIC_KERNELS else "full Q")},
         "cpu_baseline": cpu,
         "grid_points_trials_per_s": value * G,

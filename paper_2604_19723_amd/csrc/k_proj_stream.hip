@@ -1,25 +1,32 @@
 // Bartlett spectrum for large arrays (2*Mp = 256 or 512 real rows) and the
 // BF16 split-precision projection, as a trial-batched GEMM with the quadratic
-// form fused into the epilogue: P_g = x_g^T Q x_g / M^2 (see k_proj_mfma.hip).
+// form fused into the epilogue: P_g = 2 x_g^T L x_g / M^2, L the lower
+// triangle of the symmetric Q with its diagonal halved (Q symmetric, so
+// x^T Q x = 2 x^T L x; see k_proj_mfma.hip).
 //
-// Stage 1, k_qprep: builds Q = [[Rr, -Ri], [Ri, Rr]] per trial from R and
-// writes it in MFMA A-fragment order: FP32 for v_mfma_f32_16x16x4f32, or the
-// BF16 hi/lo split (hi = bf16(q), lo = bf16(q - hi), round to nearest even)
-// for v_mfma_f32_16x16x32_bf16.
+// Stage 1, k_qprep: builds L per trial from R and writes it in MFMA
+// A-fragment order: FP32 for v_mfma_f32_16x16x4f32, or the BF16 hi/lo split
+// (hi = bf16(l), lo = bf16(l - hi), round to nearest even) for
+// v_mfma_f32_16x16x32_bf16.
 //
-// Stage 2, k_proj_s: one workgroup of 8 waves computes a
-// tile of 128 grid columns of one trial over all 2*Mp rows. Each wave owns
-// 2*Mp/waves rows and streams its own A fragments straight from L2, one
-// chunk ahead; the steering fragments of the tile go through LDS in chunks
-// of 32 k values, double-buffered by the LDS DMA. The
-// accumulators never leave the registers: the epilogue multiplies them by the
-// FP32 steering rows of the same tile and reduces over rows (lane shuffles,
-// then LDS across waves). Tiles are ordered so that each XCD walks through
-// whole trials: the workgroups resident on one XCD share one trial's Q in
-// that XCD's L2.
+// Stage 2, k_proj_s: one workgroup of 8 waves computes a tile of 128 grid
+// columns of one trial over all 2*Mp rows. Wave w owns the row blocks
+// w, w + 8, w + 16, ...; row block rb takes part in the k-chunks of 32 up to
+// its diagonal chunk rb / 2, so at every chunk the active row blocks are
+// spread evenly over the four SIMDs (waves w and w + 4 share one), and a row
+// block's sums are final in the very chunk whose steering rows it needs for
+// the quadratic form: the epilogue of each row block reads x from the LDS
+// chunk at that point and no steering value is fetched twice. Each wave
+// streams its own A fragments straight from L2, one chunk ahead; the
+// steering fragments of the tile go through LDS in chunks of 32 k values,
+// double-buffered by the LDS DMA. The per-wave sums are reduced over rows by
+// lane shuffles, then across waves through LDS. Tiles are ordered so that
+// each XCD walks through whole trials: the workgroups resident on one XCD
+// share one trial's L in that XCD's L2.
 //
-// BF16X3: Q X ~= Qh Xh + Qh Xl + Ql Xh (the lo*lo term dropped), FP32 accumulate.
-// BF16 (one pass, Qh Xh) exists as a precision ablation only.
+// BF16X3: L X ~= Lh Xh + Lh Xl + Ll Xh (the lo*lo term dropped), FP32
+// accumulate; the epilogue takes x = xh + xl (16 significant bits, below the
+// error of the dropped term). BF16 (one pass, Lh Xh) is a precision ablation.
 #include "proj_common.h"
 
 namespace ba {
@@ -43,18 +50,18 @@ __device__ __forceinline__ unsigned short bf16_rne(float x) {
 
 __device__ __forceinline__ float bf16_to_f(unsigned short h) { return __uint_as_float(unsigned(h) << 16); }
 
-__device__ __forceinline__ float qval(const float2* __restrict__ Rb, int M, int MP, int i, int k) {
-  const bool iim = i >= MP, kim = k >= MP;
-  const int ir = iim ? i - MP : i, kr = kim ? k - MP : k;
-  if (ir >= M || kr >= M) return 0.f;
-  const float2 r = Rb[ir * M + kr];
-  return (iim == kim) ? r.x : (iim ? r.y : -r.y);
+// L(i, k): Q left of the diagonal, half the diagonal, zero right of it
+__device__ __forceinline__ float lval(const float2* __restrict__ Rb, int M, int MP, int i, int k) {
+  if (k > i) return 0.f;
+  const float q = qval(Rb, M, MP, i, k);
+  return k == i ? 0.5f * q : q;
 }
 
-// FP32 layout: Qf[b][kc][rbg][h][lane][4]: k-chunk kc of 32, row block rbg,
-//   lane l, word h, element e holds Q[16 rbg + l%16][32 kc + 4 (4h + e) + l/16].
-// BF16 layout: Qb[b][kc][rbg][hl][lane][8]: lane l, element e holds
-//   (hi or lo of) Q[16 rbg + l%16][32 kc + 8 (l/16) + e].
+// FP32 layout: Lf[b][kc][rbg][h][lane][4]: k-chunk kc of 32, row block rbg,
+//   lane l, word h, element e holds L[16 rbg + l%16][32 kc + 4 (4h + e) + l/16].
+// BF16 layout: Lb[b][kc][rbg][hl][lane][8]: lane l, element e holds
+//   (hi or lo of) L[16 rbg + l%16][32 kc + 8 (l/16) + e].
+// Chunks right of a row block's diagonal hold zeros; the MFMAs skip them.
 template <int PREC>
 __global__ __launch_bounds__(256) void k_qprep(const float2* __restrict__ R, void* __restrict__ Qout,
                                                int M, int MP) {
@@ -71,7 +78,7 @@ __global__ __launch_bounds__(256) void k_qprep(const float2* __restrict__ R, voi
       const int h = v >> 8, l = (v >> 2) & 63, e = v & 3;
       const int i = 16 * rbg + (l & 15);
       const int k = 32 * kc + 4 * (4 * h + e) + (l >> 4);
-      Q[v] = qval(Rb, M, MP, i, k);
+      Q[v] = lval(Rb, M, MP, i, k);
     }
   } else {
     unsigned short* Q = static_cast<unsigned short*>(Qout) + 2 * (b * per_trial + (int64_t(kc) * nrb + rbg) * 512);
@@ -79,7 +86,7 @@ __global__ __launch_bounds__(256) void k_qprep(const float2* __restrict__ R, voi
       const int l = v >> 3, e = v & 7;
       const int i = 16 * rbg + (l & 15);
       const int k = 32 * kc + 8 * (l >> 4) + e;
-      const float q = qval(Rb, M, MP, i, k);
+      const float q = lval(Rb, M, MP, i, k);
       const unsigned short hi = bf16_rne(q);
       const unsigned short lo = bf16_rne(q - bf16_to_f(hi));
       Q[v] = hi;
@@ -87,6 +94,70 @@ __global__ __launch_bounds__(256) void k_qprep(const float2* __restrict__ R, voi
     }
   }
   (void)nkc;
+}
+
+// One k-chunk of the FP32 kernel for the last N row-block slots of a wave
+// (the ones not yet past their diagonal chunk); after each half of the A
+// fragments is used, the same half of the next chunk's fragments is loaded
+// for every slot (zeros for a finished slot: the loads stay unconditional and
+// their addresses one base plus constant offsets).
+template <int N, int RBW, int NRB, int WS>
+__device__ __forceinline__ void chunk_f32(floatx4 (&acc)[RBW][kCB], float4 (&a)[RBW][2],
+                                          const float4* __restrict__ sb, const float4* __restrict__ Qw,
+                                          int kc_next, bool more, int wave, int lane) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int c = 0; c < kCB; ++c) {
+      const float4 bv = lds_frag(sb, c * 128 + h * 64 + lane);
+#pragma unroll
+      for (int r = RBW - N; r < RBW; ++r) {
+        acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r][h].x, bv.x, acc[r][c], 0, 0, 0);
+        acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r][h].y, bv.y, acc[r][c], 0, 0, 0);
+        acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r][h].z, bv.z, acc[r][c], 0, 0, 0);
+        acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r][h].w, bv.w, acc[r][c], 0, 0, 0);
+      }
+    }
+    if (more) {
+#pragma unroll
+      for (int r = 0; r < RBW; ++r) {
+        a[r][h] = Qw[(int64_t(kc_next) * NRB + wave + WS * r) * 128 + h * 64 + lane];
+      }
+    }
+  }
+}
+
+// Quadratic-form sums of a finished row block rbg (rows 16 rbg + 4 (lane/16)
+// + e, column 16 c + lane%16 of the tile) against the steering rows of the
+// LDS chunk that holds them: FP32 chunk words [c][h][lane'][4] hold
+// x[32 kc + 4 (4 h + e') + lane'/16][16 c + lane'%16]
+__device__ __forceinline__ void fold_rows_f32(float (&part)[kCB], const floatx4 (&acc)[kCB],
+                                              const float* __restrict__ sbf, int rbg, int lane) {
+#pragma unroll
+  for (int c = 0; c < kCB; ++c)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      part[c] += sbf[(c * 128 + (rbg & 1) * 64 + 16 * e + (lane & 15)) * 4 + (lane >> 4)] * acc[c][e];
+}
+
+__device__ __forceinline__ float bf_lo(unsigned w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf_hi(unsigned w) { return __uint_as_float(w & 0xffff0000u); }
+
+// the same from a BF16 chunk, words [c][hi, lo][lane'][8] holding
+// x[32 kc + 8 (lane'/16) + e'][16 c + lane'%16]: the four rows of a lane are
+// four consecutive values of one word, x = xh + xl
+__device__ __forceinline__ void fold_rows_bf16(float (&part)[kCB], const floatx4 (&acc)[kCB],
+                                               const uint4* __restrict__ sb, int rbg, int lane) {
+  const int w = (rbg & 1) * 32 + (lane >> 5) * 16 + (lane & 15), eh = (lane >> 4) & 1;
+#pragma unroll
+  for (int c = 0; c < kCB; ++c) {
+    const uint2 xh = lds_frag(reinterpret_cast<const uint2*>(sb + c * 128 + w), eh);
+    const uint2 xl = lds_frag(reinterpret_cast<const uint2*>(sb + c * 128 + 64 + w), eh);
+    part[c] += (bf_lo(xh.x) + bf_lo(xl.x)) * acc[c][0];
+    part[c] += (bf_hi(xh.x) + bf_hi(xl.x)) * acc[c][1];
+    part[c] += (bf_lo(xh.y) + bf_lo(xl.y)) * acc[c][2];
+    part[c] += (bf_hi(xh.y) + bf_hi(xl.y)) * acc[c][3];
+  }
 }
 
 template <int MP, int PREC>
@@ -116,7 +187,15 @@ __global__ __launch_bounds__(64 * waves_for<PREC>(), 1) void k_proj_s(const void
   const int tile = int(L % ntile);
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int rb0 = wave * RBW;
+  // slot r holds row block wave + kWaves r, which takes part up to its
+  // diagonal k-chunk (wave + kWaves r) / 2: slots drop out in order, every 4
+  // chunks, each right after the chunk that finishes it
+  static_assert(kWaves == 8, "last chunk of slot r = wave / 2 + 4 r");
+  const int kc00 = wave >> 1;
+  auto first_active = [&](int kc) { return kc <= kc00 ? 0 : (kc - kc00 + 3) / 4; };
+  float part[kCB];
+#pragma unroll
+  for (int c = 0; c < kCB; ++c) part[c] = 0.f;
 
   floatx4 acc[RBW][kCB];
 #pragma unroll
@@ -148,7 +227,7 @@ __global__ __launch_bounds__(64 * waves_for<PREC>(), 1) void k_proj_s(const void
 #pragma unroll
     for (int r = 0; r < RBW; ++r)
 #pragma unroll
-      for (int h = 0; h < 2; ++h) a[r][h] = Qw[(int64_t(0) * NRB + rb0 + r) * 128 + h * 64 + lane];
+      for (int h = 0; h < 2; ++h) a[r][h] = Qw[int64_t(wave + kWaves * r) * 128 + h * 64 + lane];
     lds_dma_wait();
     __syncthreads();
     for (int kc = 0; kc < NKC; ++kc) {
@@ -156,24 +235,28 @@ __global__ __launch_bounds__(64 * waves_for<PREC>(), 1) void k_proj_s(const void
       const bool more = kc + 1 < NKC;
       if (more) BA_FETCH_B(kc + 1, buf ^ 1);
       const float4* sb = reinterpret_cast<const float4*>(sBd + buf * CHUNK16);
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-#pragma unroll
-        for (int c = 0; c < kCB; ++c) {
-          const float4 bv = lds_frag(sb, c * 128 + h * 64 + lane);
-#pragma unroll
-          for (int r = 0; r < RBW; ++r) {
-            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r][h].x, bv.x, acc[r][c], 0, 0, 0);
-            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r][h].y, bv.y, acc[r][c], 0, 0, 0);
-            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r][h].z, bv.z, acc[r][c], 0, 0, 0);
-            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r][h].w, bv.w, acc[r][c], 0, 0, 0);
-          }
-        }
-        if (more) {
-#pragma unroll
-          for (int r = 0; r < RBW; ++r) a[r][h] = Qw[(int64_t(kc + 1) * NRB + rb0 + r) * 128 + h * 64 + lane];
-        }
+      switch (RBW - min(RBW, first_active(kc))) {
+        case 0:
+          chunk_f32<0, RBW, NRB, kWaves>(acc, a, sb, Qw, kc + 1, more, wave, lane);
+          break;
+        case 1:
+          chunk_f32<1, RBW, NRB, kWaves>(acc, a, sb, Qw, kc + 1, more, wave, lane);
+          break;
+        case 2:
+          if constexpr (RBW >= 2) chunk_f32<2, RBW, NRB, kWaves>(acc, a, sb, Qw, kc + 1, more, wave, lane);
+          break;
+        case 3:
+          if constexpr (RBW >= 3) chunk_f32<3, RBW, NRB, kWaves>(acc, a, sb, Qw, kc + 1, more, wave, lane);
+          break;
+        default:
+          if constexpr (RBW >= 4) chunk_f32<4, RBW, NRB, kWaves>(acc, a, sb, Qw, kc + 1, more, wave, lane);
+          break;
       }
+      // the slot whose diagonal chunk this is: its rows' sums are final
+#pragma unroll
+      for (int r = 0; r < RBW; ++r)
+        if (kc == kc00 + 4 * r) fold_rows_f32(part, acc[r], reinterpret_cast<const float*>(sb),
+                                                       wave + kWaves * r, lane);
       lds_dma_wait();
       __syncthreads();
     }
@@ -182,8 +265,8 @@ __global__ __launch_bounds__(64 * waves_for<PREC>(), 1) void k_proj_s(const void
     uint4 ah[RBW], al[RBW], anh[RBW], anl[RBW];
 #pragma unroll
     for (int r = 0; r < RBW; ++r) {
-      ah[r] = Qw[(int64_t(0) * NRB + rb0 + r) * 128 + lane];
-      al[r] = Qw[(int64_t(0) * NRB + rb0 + r) * 128 + 64 + lane];
+      ah[r] = Qw[int64_t(wave + kWaves * r) * 128 + lane];
+      al[r] = Qw[int64_t(wave + kWaves * r) * 128 + 64 + lane];
     }
     lds_dma_wait();
     __syncthreads();
@@ -194,24 +277,30 @@ __global__ __launch_bounds__(64 * waves_for<PREC>(), 1) void k_proj_s(const void
         BA_FETCH_B(kc + 1, buf ^ 1);
 #pragma unroll
         for (int r = 0; r < RBW; ++r) {
-          anh[r] = Qw[(int64_t(kc + 1) * NRB + rb0 + r) * 128 + lane];
-          anl[r] = Qw[(int64_t(kc + 1) * NRB + rb0 + r) * 128 + 64 + lane];
+          anh[r] = Qw[(int64_t(kc + 1) * NRB + wave + kWaves * r) * 128 + lane];
+          anl[r] = Qw[(int64_t(kc + 1) * NRB + wave + kWaves * r) * 128 + 64 + lane];
         }
       }
-      // fragments of column block c + 1 are read while block c is multiplied
-      uint4 bh = lds_frag(sBd + buf * CHUNK16, lane);
-      uint4 bl = lds_frag(sBd + buf * CHUNK16, 64 + lane);
+      // slots r < first are past their diagonal chunk: their MFMAs are
+      // skipped by a uniform branch (one code path keeps the register budget
+      // of the dense kernel); the fragments of column block c + 1 are read
+      // while block c is multiplied
+      const int first = first_active(kc);
+      const uint4* sb = sBd + buf * CHUNK16;
+      uint4 bh = lds_frag(sb, lane);
+      uint4 bl = lds_frag(sb, 64 + lane);
 #pragma unroll
       for (int c = 0; c < kCB; ++c) {
         uint4 nh = bh, nl = bl;
         if (c + 1 < kCB) {
-          nh = lds_frag(sBd + buf * CHUNK16, (c + 1) * 128 + lane);
-          nl = lds_frag(sBd + buf * CHUNK16, (c + 1) * 128 + 64 + lane);
+          nh = lds_frag(sb, (c + 1) * 128 + lane);
+          nl = lds_frag(sb, (c + 1) * 128 + 64 + lane);
         }
         const bf16x8 vbh = __builtin_bit_cast(bf16x8, bh);
         const bf16x8 vbl = __builtin_bit_cast(bf16x8, bl);
 #pragma unroll
         for (int r = 0; r < RBW; ++r) {
+          if (r < first) continue;
           const bf16x8 vah = __builtin_bit_cast(bf16x8, ah[r]);
           acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vah, vbh, acc[r][c], 0, 0, 0);
           if (PREC == BA_PREC_BF16X3) {
@@ -223,6 +312,9 @@ __global__ __launch_bounds__(64 * waves_for<PREC>(), 1) void k_proj_s(const void
         bh = nh;
         bl = nl;
       }
+#pragma unroll
+      for (int r = 0; r < RBW; ++r)
+        if (kc == kc00 + 4 * r) fold_rows_bf16(part, acc[r], sb, wave + kWaves * r, lane);
       if (more) {
 #pragma unroll
         for (int r = 0; r < RBW; ++r) {
@@ -236,26 +328,6 @@ __global__ __launch_bounds__(64 * waves_for<PREC>(), 1) void k_proj_s(const void
   }
 
 #undef BA_FETCH_B
-  // epilogue: rows i = 16 (rb0 + r) + 4 (lane/16) + e, column 16 c + lane%16
-  float part[kCB];
-#pragma unroll
-  for (int c = 0; c < kCB; ++c) part[c] = 0.f;
-  const float* xf = reinterpret_cast<const float*>(Xf);
-#pragma unroll
-  for (int r = 0; r < RBW; ++r) {
-    const int rbg = rb0 + r;  // 16 rows = k-steps 4 rbg .. 4 rbg + 3, one 16-k group
-#pragma unroll
-    for (int c = 0; c < kCB; ++c) {
-      const int64_t blk = int64_t(tile) * kCB + c;
-      const float* xb = xf + blk * (int64_t(K) * 16) + int64_t(rbg) * 256;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        // k = 16 rbg + 4 (lane/16) + e -> s = 4 rbg + lane/16, lane' = e*16 + lane%16
-        const float xv = xb[(e * 16 + (lane & 15)) * 4 + (lane >> 4)];
-        part[c] += xv * acc[r][c][e];
-      }
-    }
-  }
 #pragma unroll
   for (int c = 0; c < kCB; ++c) {
     float v = part[c];
@@ -269,7 +341,7 @@ __global__ __launch_bounds__(64 * waves_for<PREC>(), 1) void k_proj_s(const void
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) s += red[w][threadIdx.x];
     const int64_t g = int64_t(tile) * kCB * 16 + threadIdx.x;
-    if (g < G) P[b * G + g] = s / float(M * M);
+    if (g < G) P[b * G + g] = s * (2.0f / float(M * M));  // P = 2 x^T L x / M^2
   }
 }
 
@@ -310,9 +382,7 @@ hipError_t launch_spectrum_stream(const Plan& p, int B, const float2* R, void* Q
     if (p.precision == BA_PREC_BF16X3) return launch_s<MPV, BA_PREC_BF16X3>(p, B, Qws, P, s); \
     return launch_s<MPV, BA_PREC_BF16>(p, B, Qws, P, s);                                   \
   }
-  // FP32 plans of up to 64 elements use the register-resident kernel instead
-  if (p.Mp == 64 && p.precision == BA_PREC_BF16X3) return launch_s<64, BA_PREC_BF16X3>(p, B, Qws, P, s);
-  if (p.Mp == 64 && p.precision == BA_PREC_BF16) return launch_s<64, BA_PREC_BF16>(p, B, Qws, P, s);
+  // plans of up to 64 elements use the register-resident kernels instead
   BA_S(128)
   BA_S(256)
 #undef BA_S
