@@ -431,7 +431,10 @@ def bench_ragged(args, workers):
     M = rs.n_elem.astype(np.float64)
     T = rs.n_snap.astype(np.float64)
     snap = routes == bb.BA_ROUTE_SNAPSHOTS
-    flops = np.where(snap, 8 * M * T * G, 8 * M * M * T + 8 * M * M * G + 8 * M * G).sum()
+    # covariance route: covariance 8M^2T, then the projection in the symmetric
+    # form (K (K + 1) + 2K per grid point, K = 2M); snapshot route: |S x|^2, 8MTG
+    K2 = 2 * M
+    flops = np.where(snap, 8 * M * T * G, 8 * M * M * T + (K2 * (K2 + 1) + 2 * K2) * G).sum()
     achieved = flops / (kms * 1e-3) / 1e12
     from paper_2604_19723_amd import metrics
     est = metrics.fractional_index_to_deg(1, rs.grid, (G, 1), ref.cpu().numpy())

@@ -263,11 +263,15 @@ __device__ __attribute__((noinline)) void stage_covariance_gram(const float2* __
   __syncthreads();
 }
 
-// the chunk loop for NACT active row blocks per wave (a prefix of its RB)
+// the chunk loop for NACT active row blocks per wave (a prefix of its RB,
+// row blocks rbg[0] < rbg[1]); on the covariance route the A operand is the
+// upper triangle U of Q, and row block rbg skips the k-steps left of its
+// diagonal block (uniform branches: cov and rbg are scalar)
 template <int MP, int WR, int NACT, int RB>
 __device__ __forceinline__ void project_chunks(const RArgs& A, const float4* __restrict__ Xg, int nchunk,
                                                const float (&a)[RB][RC<MP>::KS], bool cov, float scale,
-                                               float* __restrict__ Pout, unsigned char* smem) {
+                                               const int (&rbg)[RB], float* __restrict__ Pout,
+                                               unsigned char* smem) {
   using C = RC<MP>;
   constexpr int WC = (kThreads / 64) / WR;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -300,9 +304,11 @@ __device__ __forceinline__ void project_chunks(const RArgs& A, const float4* __r
 #pragma unroll
       for (int s4 = 0; s4 < C::KS / 4; ++s4) {
         if (NACT == 0) break;
+        if (cov && s4 < rbg[0]) continue;
         const float4 bv = bx[s4 * 64 + lane];
 #pragma unroll
         for (int rb = 0; rb < NACT; ++rb) {
+          if (cov && s4 < rbg[rb]) continue;
           acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 0], bv.x, acc[rb], 0, 0, 0);
           acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 1], bv.y, acc[rb], 0, 0, 0);
           acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 2], bv.z, acc[rb], 0, 0, 0);
@@ -312,11 +318,10 @@ __device__ __forceinline__ void project_chunks(const RArgs& A, const float4* __r
       float part = 0.f;
 #pragma unroll
       for (int rb = 0; rb < NACT; ++rb) {
-        const int rbg = rb * WR + wr;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           if (cov) {
-            const int i = 16 * rbg + 4 * (lane >> 4) + r;
+            const int i = 16 * rbg[rb] + 4 * (lane >> 4) + r;
             const int s = i >> 2;
             const float xv = xbf[jb * C::BLK + ((s >> 2) * 64 + r * 16 + (lane & 15)) * 4 + (s & 3)];
             part += xv * acc[rb][r];
@@ -358,7 +363,13 @@ __device__ __forceinline__ void trial_project(const RArgs& A, const RItem& it, c
   const int wr = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) % WR;
   const int M = it.M, T = it.T;
   const float2* Yb = A.Y + it.y_off;
-  const bool cov = it.route == kRouteCov;
+  const bool cov = __builtin_amdgcn_readfirstlane(it.route) == kRouteCov;
+  // row blocks of this wave: with two per wave the pair (wr, NRB - 1 - wr),
+  // whose spans right of the diagonal add up to NRB + 1 blocks for every wr
+  static_assert(RB == 1 || RB * WR == C::NRB, "pairs cover the row blocks");
+  int rbg[RB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) rbg[rb] = rb == 0 ? wr : C::NRB - 1 - wr;
   const int Tp = (T + 7) & ~7;
   const int nrb_act = cov ? C::NRB : min(C::NRB, Tp / 8);
 
@@ -374,14 +385,16 @@ __device__ __forceinline__ void trial_project(const RArgs& A, const RItem& it, c
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
       for (int s = 0; s < C::KS; ++s) {
-        const int i = 16 * (rb * WR + wr) + (lane & 15);
+        // U: Q right of the diagonal, half the diagonal, zero left of it
+        const int i = 16 * rbg[rb] + (lane & 15);
         const int k = 4 * s + (lane >> 4);
         const bool iim = i >= MP, kim = k >= MP;
         const int ir = iim ? i - MP : i, kr = kim ? k - MP : k;
         float q = 0.f;
-        if (i < C::K && ir < M && kr < M) {
+        if (k >= i && i < C::K && ir < M && kr < M) {
           const float2 r = sR[ir * M + kr];
           q = (iim == kim) ? r.x : (iim ? r.y : -r.y);
+          if (k == i) q *= 0.5f;
         }
         a[rb][s] = q;
       }
@@ -390,7 +403,7 @@ __device__ __forceinline__ void trial_project(const RArgs& A, const RItem& it, c
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
       for (int s = 0; s < C::KS; ++s) {
-        const int i = 16 * (rb * WR + wr) + (lane & 15);
+        const int i = 16 * rbg[rb] + (lane & 15);
         const int k = 4 * s + (lane >> 4);
         const bool second = i >= Tp;
         const int t = second ? i - Tp : i;
@@ -407,19 +420,20 @@ __device__ __forceinline__ void trial_project(const RArgs& A, const RItem& it, c
   }
   __syncthreads();  // LDS covariance consumed
 
-  // 2. projection over the active row blocks of this wave (rb * WR + wr < nrb_act)
-  const float scale = cov ? 1.0f / float(M * M) : 1.0f / (float(T) * float(M * M));
+  // 2. projection over the active row blocks of this wave (rbg[rb] < nrb_act);
+  // the covariance route's sums are x^T U x = (x^T Q x) / 2
+  const float scale = cov ? 2.0f / float(M * M) : 1.0f / (float(T) * float(M * M));
   float* Pout = A.P ? A.P + int64_t(it.trial) * A.G : nullptr;
   int nact = 0;
 #pragma unroll
-  for (int rb = 0; rb < RB; ++rb) nact += (rb * WR + wr < nrb_act) ? 1 : 0;
+  for (int rb = 0; rb < RB; ++rb) nact += (rbg[rb] < nrb_act) ? 1 : 0;
   static_assert(RB <= 2, "row blocks per wave");
   if (nact == RB)
-    project_chunks<MP, WR, RB, RB>(A, Xg, nchunk, a, cov, scale, Pout, smem);
+    project_chunks<MP, WR, RB, RB>(A, Xg, nchunk, a, cov, scale, rbg, Pout, smem);
   else if (RB == 2 && nact == 1)
-    project_chunks<MP, WR, (RB == 2 ? 1 : 0), RB>(A, Xg, nchunk, a, cov, scale, Pout, smem);
+    project_chunks<MP, WR, (RB == 2 ? 1 : 0), RB>(A, Xg, nchunk, a, cov, scale, rbg, Pout, smem);
   else
-    project_chunks<MP, WR, 0, RB>(A, Xg, nchunk, a, cov, scale, Pout, smem);
+    project_chunks<MP, WR, 0, RB>(A, Xg, nchunk, a, cov, scale, rbg, Pout, smem);
 }
 
 // 3. peaks from the LDS row (same rule as the standalone peak kernel)
