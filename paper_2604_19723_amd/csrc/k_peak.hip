@@ -9,8 +9,9 @@
 // and every comparison with NaN is false. Ties in value go to the lower index.
 //
 // One workgroup per trial. Each lane scans a strided slice of the grid
-// (coalesced) and keeps a sorted top-KC list in registers; the lists meet in
-// LDS and K rounds of a wave-shuffle argmax pick the winners in order.
+// (coalesced; a 1-D row is staged in LDS first) and keeps a sorted top-KC list
+// in registers; the lists meet in LDS and K rounds of a wave-shuffle argmax
+// pick the winners in order.
 #include <climits>
 
 #include "ba_internal.h"
@@ -18,6 +19,10 @@
 
 namespace ba {
 namespace {
+
+// 1-D candidate rows staged in LDS: 30 KB, which with the 32 KB of merge lists
+// (16 per lane) stays within the 64 KB a workgroup gets without opting in
+constexpr int kPeakRowMax = 7680;
 
 __device__ __forceinline__ bool better(float va, int ia, float vb, int ib) {
   return va > vb || (va == vb && ia < ib);
@@ -74,7 +79,11 @@ __device__ double parabolic(double pm, double p0, double pp) {
   return d > 0.5 ? 0.5 : (d < -0.5 ? -0.5 : d);
 }
 
-template <int KC>
+// ONED: a 1-D grid (s1 == 1) whose candidate row fits in LDS is staged there
+// with coalesced loads first, and each point meets its two neighbours in LDS
+// (same rule as is_local_max: the earlier neighbour strictly, the later one
+// with >=, wrap of the row when wrap0, every comparison with NaN false).
+template <int KC, bool ONED>
 __global__ __launch_bounds__(256) void k_peaks(const float* __restrict__ P, int64_t G, int s1,
                                                int rows, int wrap0, int k, int* __restrict__ idx,
                                                float* __restrict__ val,
@@ -91,10 +100,37 @@ __global__ __launch_bounds__(256) void k_peaks(const float* __restrict__ P, int6
     li[j] = INT_MAX;
   }
   const int64_t ncand = int64_t(rows) * s1;
-  for (int64_t g = tid; g < ncand; g += 256) {
-    const float p = Pb[g];
-    const int i0 = int(g / s1), i1 = int(g % s1);
-    if (is_local_max(Pb, i0, i1, p, s1, rows, wrap0)) insert<KC>(lv, li, p, int(g));
+  if (ONED) {
+    extern __shared__ float sRow[];  // [rows]
+    // eight loads in flight per lane before their values are stored
+    for (int g0 = 0; g0 < rows; g0 += 8 * 256) {
+      float v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int g = g0 + j * 256 + tid;
+        v[j] = g < rows ? Pb[g] : 0.f;
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int g = g0 + j * 256 + tid;
+        if (g < rows) sRow[g] = v[j];
+      }
+    }
+    __syncthreads();
+    for (int g = tid; g < rows; g += 256) {
+      const float p = sRow[g];
+      bool ok = p == p;
+      const int gm = g - 1, gp = g + 1;
+      if (wrap0 || gm >= 0) ok = ok && p > sRow[gm < 0 ? gm + rows : gm];
+      if (wrap0 || gp < rows) ok = ok && p >= sRow[gp >= rows ? gp - rows : gp];
+      if (ok) insert<KC>(lv, li, p, g);
+    }
+  } else {
+    for (int64_t g = tid; g < ncand; g += 256) {
+      const float p = Pb[g];
+      const int i0 = int(g / s1), i1 = int(g % s1);
+      if (is_local_max(Pb, i0, i1, p, s1, rows, wrap0)) insert<KC>(lv, li, p, int(g));
+    }
   }
 
   __shared__ float sv[256 * KC];
@@ -272,8 +308,16 @@ __global__ __launch_bounds__(256) void k_moments(const float* __restrict__ P, in
 hipError_t launch_peaks(const Plan& p, int B, const float* P, int k, int* idx, float* val,
                         double* refined, hipStream_t s) {
   const dim3 grid{static_cast<uint32_t>(B)}, block{256u};
-#define BA_PK(KCV) \
-  hipLaunchKernelGGL(k_peaks<KCV>, grid, block, 0, s, P, p.G, p.shape1, p.rows, p.wrap0, k, idx, val, refined, p.ndim)
+  // a 1-D candidate row of up to kPeakRowMax points is staged in LDS
+  const bool oned = p.shape1 == 1 && p.rows <= kPeakRowMax;
+  const size_t lds = oned ? size_t(p.rows) * sizeof(float) : 0;
+#define BA_PK(KCV)                                                                                        \
+  if (oned)                                                                                               \
+    hipLaunchKernelGGL((k_peaks<KCV, true>), grid, block, lds, s, P, p.G, p.shape1, p.rows, p.wrap0, k, idx, \
+                       val, refined, p.ndim);                                                             \
+  else                                                                                                    \
+    hipLaunchKernelGGL((k_peaks<KCV, false>), grid, block, 0, s, P, p.G, p.shape1, p.rows, p.wrap0, k, idx, \
+                       val, refined, p.ndim)
   if (k <= 1)
     BA_PK(1);
   else if (k <= 2)
