@@ -11,12 +11,15 @@
 // DMA one chunk ahead. The quadratic-form epilogue takes x = xh + xl from the
 // same LDS chunk (16 significant bits, below the error of the dropped term).
 //
-// A workgroup serves two trials, so every steering chunk brought on chip is
-// used twice: 4 waves = 2 trials x 2 row waves. Row wave w holds the row
-// blocks {w, 7 - w, 2 + w, 5 - w}, whose first k-steps are {0, 3, 1, 2} for
-// either w, so both run the same code. Per 16-column block a wave issues
-// 10 x 3 = 30 MFMAs against 8 conflict-free 16-byte LDS reads and 8 8-byte
-// epilogue reads.
+// A workgroup serves two trials, and each wave carries both: every steering
+// chunk brought on chip and every B fragment and epilogue row read from LDS
+// serves the two trials. 4 waves = 2 row waves x 2 column halves of the
+// chunk. Row wave w holds the row blocks {w, 7 - w, 2 + w, 5 - w}, whose
+// first k-steps are {0, 3, 1, 2} for either w, so both run the same code. Per
+// 16-column block a wave issues 2 x 10 x 3 = 60 MFMAs against 8
+// conflict-free 16-byte LDS reads and 8 8-byte epilogue reads. The 160
+// registers of hi/lo fragments leave room for two waves per SIMD; the
+// prologue that builds them spills, the main loop does not.
 #include "proj_common.h"
 
 namespace ba {
@@ -61,39 +64,41 @@ __global__ __launch_bounds__(256, 2) void k_proj_qb(const float2* __restrict__ R
   __shared__ float red[2][NTW][WRB][NBB * 16];
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int wr = wave % WRB, wt = wave / WRB;
+  const int wr = wave % WRB, wc = wave / WRB;  // row wave, column half
   const int64_t pair = blockIdx.x / nsplit;
   const int c0 = (blockIdx.x % nsplit) * chunks_per_wg;
   const int c1 = min(c0 + chunks_per_wg, nchunk);
   if (c0 >= c1) return;
-  // an odd batch leaves the last pair with one trial: its second half repeats
-  // the first and stores nothing
-  const int64_t b = pair * NTW + wt;
-  const int64_t bq = b < B ? b : pair * NTW;
 
-  // A operand hi/lo of U: slot j, k-step kc >= slot_kc0(j): rows
-  // i = 16 slot_rb(j, wr) + lane%16, k = 32 kc + 8 (lane/16) + e
-  uint4 ah[NFRAG], al[NFRAG];
-  const float2* Rb = R + bq * int64_t(M) * M;
+  // A operand hi/lo of U for both trials: slot j, k-step kc >= slot_kc0(j):
+  // rows i = 16 slot_rb(j, wr) + lane%16, k = 32 kc + 8 (lane/16) + e. An odd
+  // batch leaves the last pair with one trial: its second copy repeats the
+  // first and stores nothing.
+  uint4 ah[NTW][NFRAG], al[NTW][NFRAG];
 #pragma unroll
-  for (int j = 0; j < NSLOT; ++j)
+  for (int t = 0; t < NTW; ++t) {
+    const int64_t bq = pair * NTW + t < B ? pair * NTW + t : pair * NTW;
+    const float2* Rb = R + bq * int64_t(M) * M;
 #pragma unroll
-    for (int kc = slot_kc0(j); kc < NKC; ++kc) {
-      const int i = 16 * slot_rb(j, wr) + (lane & 15);
-      unsigned short h[8], l[8];
+    for (int j = 0; j < NSLOT; ++j)
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int k = 32 * kc + 8 * (lane >> 4) + e;
-        const float q = k < i ? 0.f : (k == i ? 0.5f : 1.f) * qval(Rb, M, MPB, i, k);
-        h[e] = bf16_bits(q);
-        l[e] = bf16_bits(q - __uint_as_float(unsigned(h[e]) << 16));
+      for (int kc = slot_kc0(j); kc < NKC; ++kc) {
+        const int i = 16 * slot_rb(j, wr) + (lane & 15);
+        unsigned short h[8], l[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int k = 32 * kc + 8 * (lane >> 4) + e;
+          const float q = k < i ? 0.f : (k == i ? 0.5f : 1.f) * qval(Rb, M, MPB, i, k);
+          h[e] = bf16_bits(q);
+          l[e] = bf16_bits(q - __uint_as_float(unsigned(h[e]) << 16));
+        }
+        const int f = slot_off(j) + kc - slot_kc0(j);
+        ah[t][f] = make_uint4(h[0] | (unsigned(h[1]) << 16), h[2] | (unsigned(h[3]) << 16),
+                              h[4] | (unsigned(h[5]) << 16), h[6] | (unsigned(h[7]) << 16));
+        al[t][f] = make_uint4(l[0] | (unsigned(l[1]) << 16), l[2] | (unsigned(l[3]) << 16),
+                              l[4] | (unsigned(l[5]) << 16), l[6] | (unsigned(l[7]) << 16));
       }
-      const int f = slot_off(j) + kc - slot_kc0(j);
-      ah[f] = make_uint4(h[0] | (unsigned(h[1]) << 16), h[2] | (unsigned(h[3]) << 16),
-                         h[4] | (unsigned(h[5]) << 16), h[6] | (unsigned(h[7]) << 16));
-      al[f] = make_uint4(l[0] | (unsigned(l[1]) << 16), l[2] | (unsigned(l[3]) << 16),
-                         l[4] | (unsigned(l[5]) << 16), l[6] | (unsigned(l[7]) << 16));
-    }
+  }
 
 #define BA_FETCH(c, buf)                                                                  \
   do {                                                                                    \
@@ -113,52 +118,61 @@ __global__ __launch_bounds__(256, 2) void k_proj_qb(const float2* __restrict__ R
   for (int c = c0; c < c1; ++c) {
     const int buf = (c - c0) & 1;
     if (c + 1 < c1) BA_FETCH(c + 1, buf ^ 1);
-    // two waves per SIMD: each k-step's fragments are read just before its
-    // MFMAs and the epilogue rows after them; the other wave's MFMAs cover
-    // the LDS latency
+    // each B fragment and epilogue row read from LDS serves both trials
 #pragma unroll
-    for (int jb = 0; jb < NBB; ++jb) {
+    for (int jj = 0; jj < NBB / 2; ++jj) {
+      const int jb = 2 * jj + wc;
       const uint4* bx = sXb + buf * CHW + jb * BLKW;
-      floatx4 acc[NSLOT];
+      floatx4 acc[NTW][NSLOT];
 #pragma unroll
-      for (int j = 0; j < NSLOT; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (int t = 0; t < NTW; ++t)
+#pragma unroll
+        for (int j = 0; j < NSLOT; ++j) acc[t][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int kc = 0; kc < NKC; ++kc) {
         const bf16x8 bh = __builtin_bit_cast(bf16x8, lds_frag(bx, (2 * kc) * 64 + lane));
         const bf16x8 bl = __builtin_bit_cast(bf16x8, lds_frag(bx, (2 * kc + 1) * 64 + lane));
 #pragma unroll
-        for (int j = 0; j < NSLOT; ++j) {
-          if (kc < slot_kc0(j)) continue;
-          const int f = slot_off(j) + kc - slot_kc0(j);
-          const bf16x8 vah = __builtin_bit_cast(bf16x8, ah[f]);
-          acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vah, bh, acc[j], 0, 0, 0);
-          if (PREC == BA_PREC_BF16X3) {
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vah, bl, acc[j], 0, 0, 0);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, al[f]), bh, acc[j], 0, 0,
-                                                             0);
+        for (int t = 0; t < NTW; ++t)
+#pragma unroll
+          for (int j = 0; j < NSLOT; ++j) {
+            if (kc < slot_kc0(j)) continue;
+            const int f = slot_off(j) + kc - slot_kc0(j);
+            const bf16x8 vah = __builtin_bit_cast(bf16x8, ah[t][f]);
+            acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vah, bh, acc[t][j], 0, 0, 0);
+            if (PREC == BA_PREC_BF16X3) {
+              acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vah, bl, acc[t][j], 0, 0, 0);
+              acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, al[t][f]), bh,
+                                                                  acc[t][j], 0, 0, 0);
+            }
           }
-        }
       }
-      uint2 xf[NSLOT][2];
+      float part[NTW];
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) part[t] = 0.f;
 #pragma unroll
       for (int j = 0; j < NSLOT; ++j) {
         const int rbg = slot_rb(j, wr), kc = rbg >> 1;
         const int w = (rbg & 1) * 32 + ew;
-        xf[j][0] = lds_frag(reinterpret_cast<const uint2*>(bx + (kc * 2) * 64 + w), eh);
-        xf[j][1] = lds_frag(reinterpret_cast<const uint2*>(bx + (kc * 2 + 1) * 64 + w), eh);
-      }
-      float part = 0.f;
+        const uint2 xh = lds_frag(reinterpret_cast<const uint2*>(bx + (kc * 2) * 64 + w), eh);
+        const uint2 xl = lds_frag(reinterpret_cast<const uint2*>(bx + (kc * 2 + 1) * 64 + w), eh);
+        const float x0 = lo_half(xh.x) + lo_half(xl.x), x1 = hi_half(xh.x) + hi_half(xl.x);
+        const float x2 = lo_half(xh.y) + lo_half(xl.y), x3 = hi_half(xh.y) + hi_half(xl.y);
 #pragma unroll
-      for (int j = 0; j < NSLOT; ++j) {
-        const uint2 xh = xf[j][0], xl = xf[j][1];
-        part += (lo_half(xh.x) + lo_half(xl.x)) * acc[j][0];
-        part += (hi_half(xh.x) + hi_half(xl.x)) * acc[j][1];
-        part += (lo_half(xh.y) + lo_half(xl.y)) * acc[j][2];
-        part += (hi_half(xh.y) + hi_half(xl.y)) * acc[j][3];
+        for (int t = 0; t < NTW; ++t) {
+          part[t] += x0 * acc[t][j][0];
+          part[t] += x1 * acc[t][j][1];
+          part[t] += x2 * acc[t][j][2];
+          part[t] += x3 * acc[t][j][3];
+        }
       }
-      part += __shfl_xor(part, 16, 64);
-      part += __shfl_xor(part, 32, 64);
-      if (lane < 16) red[buf][wt][wr][jb * 16 + lane] = part;
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) {
+        float v = part[t];
+        v += __shfl_xor(v, 16, 64);
+        v += __shfl_xor(v, 32, 64);
+        if (lane < 16) red[buf][t][wr][jb * 16 + lane] = v;
+      }
     }
     lds_dma_wait();
     __syncthreads();
