@@ -838,7 +838,9 @@ def main():
                      "kernel": proj_kernel_name(args.precision, M), "kernel_ms": proj_ms,
                      "flops_per_launch": flops_proj,
                      "form": ("symmetric: one triangle of the 2M x 2M real Q"
-                              if proj_kernel_name(args.precision, M) in SYMMETRIC_KERNELS else "full Q")},
+                              if proj_kernel_name(args.precision, M) in SYMMETRIC_KERNELS else "full Q"),
+                     # the dense count 8M^2G + 8MG of the full complex product, for reference
+                     "achieved_dense_count": float(B) * G * (8.0 * M * M + 8.0 * M) / (proj_ms * 1e-3) / 1e12},
         "cpu_baseline": cpu,
         "grid_points_trials_per_s": value * G,
         "rmse_deg_by_snr": rmse,
