@@ -126,15 +126,16 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       }
 }
 
-// ---------------------------------------------------------------- BF16 GEMM, 128 x 128 tiles
+// ---------------------------------------------------------------- BF16 GEMM, 128 x 128 or 64 x 64 tiles
 //
-// 4 waves, each a 64 x 64 sub-tile (4 x 4 MFMA blocks). Operand tiles are
-// stored in LDS as BF16, k-contiguous, rows padded to 40 elements (80 bytes):
-// a fragment (8 consecutive k of one row) is one conflict-free 16-byte read.
-// Global loads go 4 elements at a time along whichever dimension is
-// contiguous and are issued one k-tile ahead (double buffering through
-// registers).
-constexpr int BT = 128, BK = 32, BLD = 40;
+// 4 waves, each a (BT/2) x (BT/2) sub-tile ((BT/32) x (BT/32) MFMA blocks).
+// Operand tiles are stored in LDS as BF16, k-contiguous, rows padded to 40
+// elements (80 bytes): a fragment (8 consecutive k of one row) is one
+// conflict-free 16-byte read. Global loads go 4 elements at a time along
+// whichever dimension is contiguous and are issued one k-tile ahead (double
+// buffering through registers). The 64-row tiles serve products too small to
+// give the 128-row tiles two workgroups per CU.
+constexpr int BK = 32, BLD = 40;
 
 __device__ __forceinline__ void load4(const float* __restrict__ p, int64_t so, int64_t sc, int r, int c,
                                       int nr, int nc, float (&v)[4]) {
@@ -152,21 +153,24 @@ __device__ __forceinline__ void load4(const float* __restrict__ p, int64_t so, i
   for (int e = 0; e < 4; ++e) v[e] = (inr && c + e < nc) ? p[int64_t(r) * so + int64_t(c + e) * sc] : 0.f;
 }
 
-// tile loader: operand X(i, k) = P[i si + k sk] for i in [i0, i0+128), k in [k0, k0+32);
-// each of 256 threads loads 4 groups of 4 elements
+// tile loader: operand X(i, k) = P[i si + k sk] for i in [i0, i0+BT), k in [k0, k0+32);
+// each of 256 threads loads BT/32 groups of 4 elements
+template <int BT>
 struct TileLoad {
-  float v[4][4];
+  static constexpr int NG = BT / 32;  // groups per thread
+  static constexpr int IG = BT / 4;   // groups of 4 i per k row
+  float v[NG][4];
   __device__ void load(const float* P, int64_t si, int64_t sk, int i0, int k0, int ni, int nk, int tid) {
     if (sk == 1) {  // k contiguous: groups of 4 k
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < NG; ++j) {
         const int g = j * 256 + tid, i = g >> 3, k4 = (g & 7) * 4;
         load4(P, si, 1, i0 + i, k0 + k4, ni, nk, v[j]);
       }
     } else {        // i contiguous: groups of 4 i
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int g = j * 256 + tid, k = g >> 5, i4 = (g & 31) * 4;
+      for (int j = 0; j < NG; ++j) {
+        const int g = j * 256 + tid, k = g / IG, i4 = (g % IG) * 4;
         load4(P, sk, si, k0 + k, i0 + i4, nk, ni, v[j]);
       }
     }
@@ -174,15 +178,15 @@ struct TileLoad {
   __device__ void store(__bf16 (*S)[BLD], bool kcontig, int tid) const {
     if (kcontig) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < NG; ++j) {
         const int g = j * 256 + tid, i = g >> 3, k4 = (g & 7) * 4;
 #pragma unroll
         for (int e = 0; e < 4; ++e) S[i][k4 + e] = static_cast<__bf16>(v[j][e]);
       }
     } else {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int g = j * 256 + tid, k = g >> 5, i4 = (g & 31) * 4;
+      for (int j = 0; j < NG; ++j) {
+        const int g = j * 256 + tid, k = g / IG, i4 = (g % IG) * 4;
 #pragma unroll
         for (int e = 0; e < 4; ++e) S[i4 + e][k] = static_cast<__bf16>(v[j][e]);
       }
@@ -190,20 +194,22 @@ struct TileLoad {
   }
 };
 
+template <int BT>
 __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
+  constexpr int NI = BT / 32;  // MFMA blocks per wave and dimension
   __shared__ __attribute__((aligned(16))) __bf16 As[2][BT][BLD];
   __shared__ __attribute__((aligned(16))) __bf16 Bs[2][BT][BLD];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = wave & 1, wn = wave >> 1;
   const int m0 = blockIdx.y * BT, n0 = blockIdx.x * BT;
   const bool a_k = g.sak == 1, b_k = g.sbk == 1;
-  floatx4 acc[4][4];
+  floatx4 acc[NI][NI];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < NI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < NI; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  TileLoad la, lb;
+  TileLoad<BT> la, lb;
   // B(k, n) = B[k sbk + n sbn]: as an operand indexed (n, k) it has si = sbn, sk = sbk
   la.load(g.A, g.sam, g.sak, m0, 0, g.M, g.K, tid);
   lb.load(g.B, g.sbn, g.sbk, n0, 0, g.N, g.K, tid);
@@ -218,16 +224,16 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
       la.load(g.A, g.sam, g.sak, m0, (t + 1) * BK, g.M, g.K, tid);
       lb.load(g.B, g.sbn, g.sbk, n0, (t + 1) * BK, g.N, g.K, tid);
     }
-    bf16x8 af[4], bfr[4];
+    bf16x8 af[NI], bfr[NI];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      af[i] = *reinterpret_cast<const bf16x8*>(&As[buf][wm * 64 + i * 16 + (lane & 15)][8 * (lane >> 4)]);
-      bfr[i] = *reinterpret_cast<const bf16x8*>(&Bs[buf][wn * 64 + i * 16 + (lane & 15)][8 * (lane >> 4)]);
+    for (int i = 0; i < NI; ++i) {
+      af[i] = *reinterpret_cast<const bf16x8*>(&As[buf][wm * (BT / 2) + i * 16 + (lane & 15)][8 * (lane >> 4)]);
+      bfr[i] = *reinterpret_cast<const bf16x8*>(&Bs[buf][wn * (BT / 2) + i * 16 + (lane & 15)][8 * (lane >> 4)]);
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < NI; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+      for (int j = 0; j < NI; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
     if (more) {
       la.store(As[buf ^ 1], a_k, tid);
       lb.store(Bs[buf ^ 1], b_k, tid);
@@ -235,13 +241,13 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < NI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < NI; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
-        const int n = n0 + wn * 64 + j * 16 + (lane & 15);
+        const int m = m0 + wm * (BT / 2) + i * 16 + 4 * (lane >> 4) + r;
+        const int n = n0 + wn * (BT / 2) + j * 16 + (lane & 15);
         if (m >= g.M || n >= g.N) continue;
         float v = acc[i][j][r];
         const int64_t o = int64_t(m) * g.ldc + n;
@@ -377,8 +383,15 @@ __global__ __launch_bounds__(256) void k_pack(const float2* __restrict__ R, floa
 hipError_t launch_gemm(const GemmArgs& g, int prec, hipStream_t s) {
   const dim3 grid(unsigned((g.N + TN - 1) / TN), unsigned((g.M + TM - 1) / TM));
   if (prec == BA_PREC_BF16) {
-    const dim3 gb(unsigned((g.N + BT - 1) / BT), unsigned((g.M + BT - 1) / BT));
-    hipLaunchKernelGGL(k_gemm_bf16, gb, dim3(256), 0, s, g);
+    // 128-row tiles when they give every CU two workgroups, else 64-row tiles
+    const int64_t n128 = int64_t((g.N + 127) / 128) * ((g.M + 127) / 128);
+    if (n128 >= 512) {
+      const dim3 gb(unsigned((g.N + 127) / 128), unsigned((g.M + 127) / 128));
+      hipLaunchKernelGGL(k_gemm_bf16<128>, gb, dim3(256), 0, s, g);
+    } else {
+      const dim3 gb(unsigned((g.N + 63) / 64), unsigned((g.M + 63) / 64));
+      hipLaunchKernelGGL(k_gemm_bf16<64>, gb, dim3(256), 0, s, g);
+    }
   } else
     hipLaunchKernelGGL(k_gemm<BA_PREC_F32>, grid, dim3(256), 0, s, g);
   return hipGetLastError();
