@@ -37,12 +37,12 @@ template <int MP>
 __global__ __launch_bounds__(256) void k_window(WindowArgs A) {
   using C = QCfg<MP>;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  // LDS sized for the windows of this launch: nbmax blocks of one window, then
-  // the spectrum rows of the K windows
+  // LDS: two steering chunks (one in flight by LDS DMA), then the spectrum
+  // rows of the K windows, sized for the windows of this launch
   const int nbmax = window_blocks(A.hw);
-  float4* sX = reinterpret_cast<float4*>(smem);                                   // [nbmax][BLK]
-  float* sP = reinterpret_cast<float*>(smem + size_t(nbmax) * C::BLK * 4);        // [kMaxProp][nbmax*16]
-  __shared__ float red[C::WR][16 * kMaxWinBlocks];
+  float4* sX = reinterpret_cast<float4*>(smem);                                   // [2][CH4]
+  float* sP = reinterpret_cast<float*>(smem + size_t(2) * C::CH4 * 16);          // [kMaxProp][nbmax*16]
+  __shared__ float red[2][C::WR][16 * C::NB];
   __shared__ int s_lo[kMaxProp], s_hi[kMaxProp], s_jb0[kMaxProp];
   __shared__ float s_tr;
   __shared__ float wv[4];
@@ -87,27 +87,54 @@ __global__ __launch_bounds__(256) void k_window(WindowArgs A) {
   }
   __syncthreads();
 
+  // The windows' 16-column blocks are contiguous slices of the table; they
+  // are taken in chunks of NB blocks (8 KB, the full-grid kernel's chunk), over
+  // all windows in turn, the next chunk in flight by LDS DMA while the current
+  // one is multiplied. Values and reduction order are those of k_proj_q.
   const float scale = 2.0f / float(M * M);  // as the full-grid kernel: P = 2 x^T U x / M^2
-  for (int k = 0; k < K; ++k) {
-    const int jb0 = s_jb0[k], nbw = s_hi[k] / 16 - jb0 + 1;
-    // the window's blocks are a contiguous slice of the table
-    const float4* src = A.X + int64_t(jb0) * (C::BLK / 4);
-    for (int v = threadIdx.x; v < nbw * (C::BLK / 4); v += 256) sX[v] = src[v];
-    __syncthreads();
-    for (int jb = wc; jb < nbw; jb += C::WC) {
-      const float part = block_quadratic<MP>(a, sX + jb * (C::BLK / 4),
-                                             reinterpret_cast<const float*>(sX) + jb * C::BLK, wr, lane);
-      if (lane < 16) red[wr][jb * 16 + lane] = part;
+  auto nbw = [&](int k) { return s_hi[k] / 16 - s_jb0[k] + 1; };
+  auto fetch = [&](int k, int c, int buf) {
+    const int nvalid = min(C::NB, nbw(k) - c * C::NB);
+    const float4* src = A.X + int64_t(s_jb0[k] + c * C::NB) * (C::BLK / 4);
+#pragma unroll
+    for (int f = 0; f < C::CH4 / 4 / 64; ++f) {
+      const int o = wave * (C::CH4 / 4) + f * 64;  // one DMA lies inside one block
+      if (o / (C::BLK / 4) < nvalid) lds_dma16(src + o + lane, sX + buf * C::CH4 + o);
     }
+  };
+  int k = 0, c = 0;
+  fetch(0, 0, 0);
+  lds_dma_wait();
+  __syncthreads();
+  for (int t = 0;; ++t) {
+    int kn = k, cn = c + 1;
+    if (cn * C::NB >= nbw(k)) {
+      kn = k + 1;
+      cn = 0;
+    }
+    const bool more = kn < K;
+    const int buf = t & 1;
+    if (more) fetch(kn, cn, buf ^ 1);  // the other buffer was last read before the previous barrier
+    const float4* sxb = sX + buf * C::CH4;
+    const float* sx = reinterpret_cast<const float*>(sxb);
+    const int nvalid = min(C::NB, nbw(k) - c * C::NB);
+    for (int jb = wc; jb < nvalid; jb += C::WC) {
+      const float part = block_quadratic<MP>(a, sxb + jb * (C::BLK / 4), sx + jb * C::BLK, wr, lane);
+      if (lane < 16) red[buf][wr][jb * 16 + lane] = part;
+    }
+    lds_dma_wait();
     __syncthreads();
-    for (int t = threadIdx.x; t < nbw * 16; t += 256) {
+    for (int q = threadIdx.x; q < nvalid * 16; q += 256) {
       float s = 0.f;
 #pragma unroll
-      for (int w = 0; w < C::WR; ++w) s += red[w][t];
-      sP[k * (16 * nbmax) + t] = s * scale;
+      for (int w = 0; w < C::WR; ++w) s += red[buf][w][q];
+      sP[k * (16 * nbmax) + c * C::NB * 16 + q] = s * scale;
     }
-    __syncthreads();
+    if (!more) break;
+    k = kn;
+    c = cn;
   }
+  __syncthreads();
 
   // window maxima
   for (int k = 0; k < K; ++k) {
@@ -216,8 +243,9 @@ __global__ void k_zero_count(int* count) {
 }  // namespace
 
 size_t window_lds_bytes(int Mp, int hw) {
+  (void)Mp;  // two 8 KB steering chunks at every element count
   const size_t nb = size_t(window_blocks(hw));
-  return nb * (2 * Mp * 16) * 4 + size_t(kMaxProp) * 16 * nb * 4;
+  return size_t(2) * 8192 + size_t(kMaxProp) * 16 * nb * 4;
 }
 
 hipError_t launch_window(const WindowArgs& a, int Mp, int B, hipStream_t s) {
