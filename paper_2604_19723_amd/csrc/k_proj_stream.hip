@@ -61,7 +61,7 @@ __device__ __forceinline__ float lval(const float2* __restrict__ Rb, int M, int 
 //   lane l, word h, element e holds L[16 rbg + l%16][32 kc + 4 (4h + e) + l/16].
 // BF16 layout: Lb[b][kc][rbg][hl][lane][8]: lane l, element e holds
 //   (hi or lo of) L[16 rbg + l%16][32 kc + 8 (l/16) + e].
-// Chunks right of a row block's diagonal hold zeros; the MFMAs skip them.
+// Chunks right of a row block's diagonal hold zeros; neither loaded nor multiplied.
 template <int PREC>
 __global__ __launch_bounds__(256) void k_qprep(const float2* __restrict__ R, void* __restrict__ Qout,
                                                int M, int MP) {
@@ -99,12 +99,11 @@ __global__ __launch_bounds__(256) void k_qprep(const float2* __restrict__ R, voi
 // One k-chunk of the FP32 kernel for the last N row-block slots of a wave
 // (the ones not yet past their diagonal chunk); after each half of the A
 // fragments is used, the same half of the next chunk's fragments is loaded
-// for every slot (zeros for a finished slot: the loads stay unconditional and
-// their addresses one base plus constant offsets).
+// for the slots still active there (first_next on).
 template <int N, int RBW, int NRB, int WS>
 __device__ __forceinline__ void chunk_f32(floatx4 (&acc)[RBW][kCB], float4 (&a)[RBW][2],
                                           const float4* __restrict__ sb, const float4* __restrict__ Qw,
-                                          int kc_next, bool more, int wave, int lane) {
+                                          int kc_next, bool more, int first_next, int wave, int lane) {
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
 #pragma unroll
@@ -121,6 +120,7 @@ __device__ __forceinline__ void chunk_f32(floatx4 (&acc)[RBW][kCB], float4 (&a)[
     if (more) {
 #pragma unroll
       for (int r = 0; r < RBW; ++r) {
+        if (r < first_next) continue;  // past its diagonal chunk: nothing to load
         a[r][h] = Qw[(int64_t(kc_next) * NRB + wave + WS * r) * 128 + h * 64 + lane];
       }
     }
@@ -235,21 +235,22 @@ __global__ __launch_bounds__(64 * waves_for<PREC>(), 1) void k_proj_s(const void
       const bool more = kc + 1 < NKC;
       if (more) BA_FETCH_B(kc + 1, buf ^ 1);
       const float4* sb = reinterpret_cast<const float4*>(sBd + buf * CHUNK16);
+      const int fnext = more ? first_active(kc + 1) : RBW;
       switch (RBW - min(RBW, first_active(kc))) {
         case 0:
-          chunk_f32<0, RBW, NRB, kWaves>(acc, a, sb, Qw, kc + 1, more, wave, lane);
+          chunk_f32<0, RBW, NRB, kWaves>(acc, a, sb, Qw, kc + 1, more, fnext, wave, lane);
           break;
         case 1:
-          chunk_f32<1, RBW, NRB, kWaves>(acc, a, sb, Qw, kc + 1, more, wave, lane);
+          chunk_f32<1, RBW, NRB, kWaves>(acc, a, sb, Qw, kc + 1, more, fnext, wave, lane);
           break;
         case 2:
-          if constexpr (RBW >= 2) chunk_f32<2, RBW, NRB, kWaves>(acc, a, sb, Qw, kc + 1, more, wave, lane);
+          if constexpr (RBW >= 2) chunk_f32<2, RBW, NRB, kWaves>(acc, a, sb, Qw, kc + 1, more, fnext, wave, lane);
           break;
         case 3:
-          if constexpr (RBW >= 3) chunk_f32<3, RBW, NRB, kWaves>(acc, a, sb, Qw, kc + 1, more, wave, lane);
+          if constexpr (RBW >= 3) chunk_f32<3, RBW, NRB, kWaves>(acc, a, sb, Qw, kc + 1, more, fnext, wave, lane);
           break;
         default:
-          if constexpr (RBW >= 4) chunk_f32<4, RBW, NRB, kWaves>(acc, a, sb, Qw, kc + 1, more, wave, lane);
+          if constexpr (RBW >= 4) chunk_f32<4, RBW, NRB, kWaves>(acc, a, sb, Qw, kc + 1, more, fnext, wave, lane);
           break;
       }
       // the slot whose diagonal chunk this is: its rows' sums are final
@@ -267,6 +268,7 @@ __global__ __launch_bounds__(64 * waves_for<PREC>(), 1) void k_proj_s(const void
     for (int r = 0; r < RBW; ++r) {
       ah[r] = Qw[int64_t(wave + kWaves * r) * 128 + lane];
       al[r] = Qw[int64_t(wave + kWaves * r) * 128 + 64 + lane];
+      anh[r] = anl[r] = make_uint4(0u, 0u, 0u, 0u);
     }
     lds_dma_wait();
     __syncthreads();
@@ -275,8 +277,11 @@ __global__ __launch_bounds__(64 * waves_for<PREC>(), 1) void k_proj_s(const void
       const bool more = kc + 1 < NKC;
       if (more) {
         BA_FETCH_B(kc + 1, buf ^ 1);
+        // slots past their diagonal chunk load nothing (their registers keep
+        // stale values that no MFMA reads)
 #pragma unroll
         for (int r = 0; r < RBW; ++r) {
+          if (r < first_active(kc + 1)) continue;
           anh[r] = Qw[(int64_t(kc + 1) * NRB + wave + kWaves * r) * 128 + lane];
           anl[r] = Qw[(int64_t(kc + 1) * NRB + wave + kWaves * r) * 128 + 64 + lane];
         }
