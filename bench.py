@@ -748,7 +748,8 @@ def main():
         log("step %d enqueued" % k) if k == 0 else None
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    proj_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    proj_times = [a.elapsed_time(b) for a, b in evs]
+    proj_ms = float(np.mean(proj_times))
     log("timed %d steps: %.3f ms/step, projection %.3f ms" % (args.steps, dt / args.steps * 1e3, proj_ms))
 
     flops_proj = float(B) * G * proj_flops_per_point(M, proj_kernel_name(args.precision, M))
@@ -836,6 +837,7 @@ def main():
                      "traffic": measured_traffic("%s|%s|%s|b%d" % (
                          proj_kernel_name(args.precision, M), args.precision, ts.name, B)),
                      "kernel": proj_kernel_name(args.precision, M), "kernel_ms": proj_ms,
+                     "kernel_ms_median": float(np.median(proj_times)),
                      "flops_per_launch": flops_proj,
                      "form": ("symmetric: one triangle of the 2M x 2M real Q"
                               if proj_kernel_name(args.precision, M) in SYMMETRIC_KERNELS else "full Q"),
