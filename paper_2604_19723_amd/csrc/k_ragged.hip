@@ -9,14 +9,16 @@
 //  1. covariance route: R = (1/T) sum_t y_t y_t^H into LDS on the vector ALUs
 //     (snapshot chunks staged in LDS, 4 x BN register blocks over the upper
 //     triangle, the snapshot range split over thread groups when the matrix
-//     is small, partial sums combined in a fixed order); Q = [[Rr, -Ri],
-//     [Ri, Rr]] then goes into MFMA A-operand registers;
+//     is small, partial sums combined in a fixed order; the matrix-core
+//     Gram form for the 64- and 128-element classes); the upper triangle U
+//     of Q = [[Rr, -Ri], [Ri, Rr]] (diagonal halved, x^T Q x = 2 x^T U x)
+//     then goes into MFMA A-operand registers;
 //     snapshot route (few snapshots): the A operand is S = [[Yr, Yi],
 //     [Yi, -Yr]] read straight from the snapshots, rows 2T instead of 2M;
 //  2. projection on v_mfma_f32_16x16x4f32 against the steering table of the
 //     trial's size class (the first Mp elements of the plan's geometry:
 //     exact, a per-point phase common to all elements cancels in |a^H y|^2),
-//     the epilogue forming x^T (Q x) or sum |S x|^2 into an LDS spectrum row;
+//     the epilogue forming 2 x^T (U x) or sum |S x|^2 into an LDS spectrum row;
 //  3. peak pick and FP64 refinement from that LDS row.
 #include <climits>
 
