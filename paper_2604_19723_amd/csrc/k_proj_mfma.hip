@@ -100,9 +100,10 @@ hipError_t launch_q(const Plan& p, int B, const float2* R, float* P, hipStream_t
   const int nchunk = int((p.Gb + C::NB - 1) / C::NB);  // the table holds Xblocks >= nchunk * NB
   // split the grid columns over several workgroups until there are enough of
   // them for the last round of workgroups on the CUs to be a small tail
-  // (10 000 trials: two column halves, 10.58 -> 10.42 ms)
+  // (10 000 trials: two column halves, 10.58 -> 10.42 ms), keeping at least
+  // 32 chunks per workgroup to pay for building U in its registers
   int nsplit = 1;
-  while (int64_t(B) * nsplit < 16384 && nsplit < nchunk) nsplit *= 2;
+  while (int64_t(B) * nsplit < 16384 && 2 * nsplit * 32 <= nchunk) nsplit *= 2;
   const int per = (nchunk + nsplit - 1) / nsplit;
   nsplit = (nchunk + per - 1) / per;
   const int64_t nblk = int64_t(B) * nsplit;
