@@ -686,8 +686,8 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: the grid search shards by trials with no "
-              "cross-GPU exchange in the timed path, and this build measures the single-GPU "
-              "kernel (use --gpus 1)", file=sys.stderr)
+              "cross-GPU exchange in the timed path, so it measures one GPU's share at its "
+              "real shape (use --gpus 1)", file=sys.stderr)
         return 2
 
     from paper_2604_19723_amd import workload as wl
