@@ -19,7 +19,8 @@
 // 16-column block a wave issues 2 x 10 x 3 = 60 MFMAs against 8
 // conflict-free 16-byte LDS reads and 8 8-byte epilogue reads. The 160
 // registers of hi/lo fragments leave room for two waves per SIMD; the
-// prologue that builds them spills, the main loop does not.
+// workgroup builds them in LDS first, so no wave holds conversion
+// temporaries beside them (no spills).
 #include "proj_common.h"
 
 namespace ba {
@@ -71,34 +72,46 @@ __global__ __launch_bounds__(256, 2) void k_proj_qb(const float2* __restrict__ R
   if (c0 >= c1) return;
 
   // A operand hi/lo of U for both trials: slot j, k-step kc >= slot_kc0(j):
-  // rows i = 16 slot_rb(j, wr) + lane%16, k = 32 kc + 8 (lane/16) + e. An odd
-  // batch leaves the last pair with one trial: its second copy repeats the
-  // first and stores nothing.
+  // rows i = 16 slot_rb(j, wr) + lane%16, k = 32 kc + 8 (lane/16) + e. The
+  // workgroup builds one trial's fragments at a time in LDS (the steering
+  // buffers, not in use yet: [row block][k-step][hi, lo][lane] words, 64 KB),
+  // all 256 threads converting R in turn, and each wave then reads its own.
+  // An odd batch leaves the last pair with one trial: its second copy repeats
+  // the first and stores nothing.
   uint4 ah[NTW][NFRAG], al[NTW][NFRAG];
+  static_assert(8 * NKC * 2 * 64 <= 2 * CHW, "a trial's fragments fit the steering buffers");
 #pragma unroll
   for (int t = 0; t < NTW; ++t) {
     const int64_t bq = pair * NTW + t < B ? pair * NTW + t : pair * NTW;
     const float2* Rb = R + bq * int64_t(M) * M;
+    if (t > 0) __syncthreads();  // the previous trial's fragments have been read
+    for (int it = threadIdx.x; it < 8 * NKC * 64; it += 256) {
+      const int ln = it & 63, rk = it >> 6, rbg = rk / NKC, kc = rk % NKC;
+      const int i = 16 * rbg + (ln & 15);
+      unsigned short h[8], l[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = 32 * kc + 8 * (ln >> 4) + e;
+        const float q = k < i ? 0.f : (k == i ? 0.5f : 1.f) * qval(Rb, M, MPB, i, k);
+        h[e] = bf16_bits(q);
+        l[e] = bf16_bits(q - __uint_as_float(unsigned(h[e]) << 16));
+      }
+      sXb[(rk * 2 + 0) * 64 + ln] = make_uint4(h[0] | (unsigned(h[1]) << 16), h[2] | (unsigned(h[3]) << 16),
+                                               h[4] | (unsigned(h[5]) << 16), h[6] | (unsigned(h[7]) << 16));
+      sXb[(rk * 2 + 1) * 64 + ln] = make_uint4(l[0] | (unsigned(l[1]) << 16), l[2] | (unsigned(l[3]) << 16),
+                                               l[4] | (unsigned(l[5]) << 16), l[6] | (unsigned(l[7]) << 16));
+    }
+    __syncthreads();
 #pragma unroll
     for (int j = 0; j < NSLOT; ++j)
 #pragma unroll
       for (int kc = slot_kc0(j); kc < NKC; ++kc) {
-        const int i = 16 * slot_rb(j, wr) + (lane & 15);
-        unsigned short h[8], l[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int k = 32 * kc + 8 * (lane >> 4) + e;
-          const float q = k < i ? 0.f : (k == i ? 0.5f : 1.f) * qval(Rb, M, MPB, i, k);
-          h[e] = bf16_bits(q);
-          l[e] = bf16_bits(q - __uint_as_float(unsigned(h[e]) << 16));
-        }
-        const int f = slot_off(j) + kc - slot_kc0(j);
-        ah[t][f] = make_uint4(h[0] | (unsigned(h[1]) << 16), h[2] | (unsigned(h[3]) << 16),
-                              h[4] | (unsigned(h[5]) << 16), h[6] | (unsigned(h[7]) << 16));
-        al[t][f] = make_uint4(l[0] | (unsigned(l[1]) << 16), l[2] | (unsigned(l[3]) << 16),
-                              l[4] | (unsigned(l[5]) << 16), l[6] | (unsigned(l[7]) << 16));
+        const int f = slot_off(j) + kc - slot_kc0(j), rk = slot_rb(j, wr) * NKC + kc;
+        ah[t][f] = sXb[(rk * 2 + 0) * 64 + lane];
+        al[t][f] = sXb[(rk * 2 + 1) * 64 + lane];
       }
   }
+  __syncthreads();  // every wave holds its fragments before the steering DMA reuses the buffers
 
 #define BA_FETCH(c, buf)                                                                  \
   do {                                                                                    \
