@@ -34,7 +34,7 @@ __device__ double parabolic(double pm, double p0, double pp) {
 }
 
 template <int MP>
-__global__ __launch_bounds__(256) void k_window(WindowArgs A) {
+__global__ __launch_bounds__(256, 6) void k_window(WindowArgs A) {
   using C = QCfg<MP>;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   // LDS: two steering chunks (one in flight by LDS DMA), then the spectrum
