@@ -501,11 +501,11 @@ def bench_learned(args, workers):
     chosen = next((r for r in ev["learned"] if L.equal_rmse(r["rmse"], ev["plain"]["rmse"])), ev["learned"][-1])
     log("validation: plain %s; chosen tau %.2f (fallback %.3f, rmse %s)" % (
         ev["plain"]["rmse"], chosen["tau"], chosen["fallback"], chosen["rmse"]))
-    et = L.evaluate(plan, net, test, [chosen["tau"]], dev)
+    et = L.evaluate(plan, net, test, [chosen["tau"]], dev, steps=args.steps, warmup=args.warmup)
     lt, pt = et["learned"][0], et["plain"]
     line = {
         "metric": "MC trials/sec and grid-points*trials/sec at fixed RMSE; % MFMA/HBM peak",
-        "value": lt["trials_per_s"], "unit": "trials/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "value": lt["trials_per_s"], "unit": "trials/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": lt["seconds"] * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "bf16 network + f32 windows",
         "data": "synthetic (seeded signal model; training stream drawn on the device)",

@@ -122,9 +122,10 @@ def train(net, X, U, Mk, epochs, batch, lr, seed, log=None):
     return hist
 
 
-def evaluate(plan, net, ts, taus, device, hw=50):
+def evaluate(plan, net, ts, taus, device, hw=50, steps=1, warmup=1):
     """Plain full grid vs learned proposal on a numpy-generated trial set:
-    RMSE (deg) per threshold, fallback rate and timings."""
+    RMSE (deg) per threshold, fallback rate and timings (mean over `steps`
+    timed passes after `warmup` untimed ones)."""
     import torch
     n = ts.n_trials
     Y = torch.from_numpy(ts.y_c64()).to(device)
@@ -139,12 +140,14 @@ def evaluate(plan, net, ts, taus, device, hw=50):
         bb.ba_spectrum(plan, n, R, P)
         bb.ba_peaks(plan, n, P, K, idx, val, ref)
 
-    plain()
+    for _ in range(max(warmup, 1)):
+        plain()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plain()
+    for _ in range(steps):
+        plain()
     torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
+    t_plain = (time.perf_counter() - t0) / steps
     base = _rmse(ts, idx.cpu().numpy(), ref.cpu().numpy()[..., 0])
 
     li = torch.empty((n, K), dtype=torch.int32, device=device)
@@ -157,12 +160,14 @@ def evaluate(plan, net, ts, taus, device, hw=50):
         def learned():
             bb.ba_covariance(plan, n, T, Y, R)
             return bb.ba_propose_refine(plan, net, n, R, K, hw, tau, li, lv, lr_, fell, ws)
-        learned()
+        for _ in range(max(warmup, 1)):
+            learned()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        nf = learned()
+        for _ in range(steps):
+            nf = learned()
         torch.cuda.synchronize()
-        t_l = time.perf_counter() - t0
+        t_l = (time.perf_counter() - t0) / steps
         r = _rmse(ts, li.cpu().numpy(), lr_.cpu().numpy())
         res.append(dict(tau=float(tau), fallback=nf / n, rmse=r, seconds=t_l, trials_per_s=n / t_l))
     return dict(plain=dict(rmse=base, seconds=t_plain, trials_per_s=n / t_plain), learned=res)
