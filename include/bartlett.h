@@ -333,11 +333,12 @@ ba_status ba_propose_workspace_size(ba_plan plan, int32_t n_trials, int32_t d_ou
  * Learned proposal + refinement: pack R, run the network (its first k outputs
  * are sin(direction) of the sources), scan only the full-grid points within
  * +-half_window of each proposal (nearest full-grid index), and take each
- * window's maximum as a peak, refined as on the full grid. A trial falls back
- * to the full-grid search (covariance already given) when a window maximum
- * lies on a window edge that is not a grid edge, when two windows find the
- * same point, on NaN, or when a peak's normalised cost P M / tr(R) is below
- * tau. Outputs are then the full-grid ones.
+ * window's maximum (ties to the lower index) as a peak, refined as on the
+ * full grid. A trial falls back to the full-grid search (covariance already
+ * given) when a proposal or any spectrum value inside a window is NaN, when a
+ * window maximum lies on a window edge that is not a grid edge, when two
+ * windows find the same point, or when a peak's normalised cost P M / tr(R)
+ * is not at least tau. Outputs are then the full-grid ones.
  *   plan        FP32 plan, M <= 64, uniform 1-D angle grid (BA_GRID_ULA_DEG).
  *   net         d_in = M^2, d_out >= k.
  *   R           dev c64 [B][M][M]; k in [1, 8]; half_window in [1, 100]; tau in [0, 1].
@@ -400,9 +401,9 @@ ba_status ba_sequential_peaks(ba_plan p, int32_t n_trials, const void* R, int32_
  * The paper's own birth-proposal workload (Sec. IV-D.2): the coherent
  * Bartlett spectrum P(s) = |sum_j (1/N_z) z_j^H psi_j(s)|^2 over J arrays for
  * candidate SFV positions s, where psi_j(s) is the path-loss compensated
- * wideband URA response (Sec. II-C) of the path that the surface with SFV s
+ * wideband URA response (Sec. II-B) of the path that the surface with SFV s
  * creates between the terminal and array j: virtual anchor, Householder mirror
- * and array rotation of Sec. II-B. Element order of psi_j: frequency slowest,
+ * and array rotation of Sec. II-A. Element order of psi_j: frequency slowest,
  * then the horizontal element, then the vertical one (b (x) a_y (x) a_z); the
  * pilot spectrum is flat; baseband frequencies are equally spaced over the
  * bandwidth and centred on zero; elements sit at half a wavelength, centred.
@@ -454,7 +455,7 @@ ba_status ba_coherent_moments(ba_coherent h, int32_t n_trials, const float* P, d
 /* ---------------------------------------------------------------- particle update messages
  *
  * The likelihood-to-variable update messages of the particle-based BP step
- * (Sec. IV-F; Supplementary Sec. S-V, efficient implementation), each a
+ * (Sec. IV-C; Supplementary Sec. S-V, efficient implementation), each a
  * complex Gaussian log-density log CN(z_j; mu, C) of the observation z_j of
  * array j with covariance eta I plus a low-rank part:
  *   iota  MT state message at every (MT particle p, array j);
@@ -465,7 +466,7 @@ ba_status ba_coherent_moments(ba_coherent h, int32_t n_trials, const float* P, d
  * Feature s = 0 is the line-of-sight path, s >= 1 surfaces given by SFVs. PF
  * particle p of every feature is paired with MT particle p, so a_s^(j,p) is
  * the response at array j of feature s's path for MT position x^p and SFV
- * v_s^p (geometry of Sec. II-B, response of Sec. II-C, as for the coherent
+ * v_s^p (geometry of Sec. II-A, response of Sec. II-B, as for the coherent
  * cost above: path loss included, element order b (x) a_y (x) a_z, centred
  * half-wavelength supports and frequency bins).
  * Moments (rho_s = sum_p w_alpha,s^p, zeta_s = zeta_s^(j)(1), eta~_j =

@@ -5,13 +5,13 @@ Test infrastructure only: the test suite, the smoke check and the CPU-baseline
 leg of the benchmark call this module; the product path never does.
 
 What the paper computes:
-  * geometry (Sec. II-B): an SFV position s is the mirror image of the origin
+  * geometry (Sec. II-A): an SFV position s is the mirror image of the origin
     across a flat surface; the virtual anchor of array j is that array's
     position mirrored across the same surface, eq. (posPA-SB); the
     Householder matrix of eq. (house) mirrors the vector from the virtual
     anchor to the mobile terminal, and the array's rotation takes it into the
     array's local frame, eq. (rangep);
-  * array response (Sec. II-C): path-loss compensated, eq. (array-response),
+  * array response (Sec. II-B): path-loss compensated, eq. (array-response),
     times the unit-modulus response of eq. (unit-modulus-array-response): the
     Kronecker product of the delay response over the baseband frequencies,
     eq. (delay-array-response), and the spatial responses of the URA's

@@ -5,10 +5,10 @@ variance message nu, evaluated at every particle-array pair.
 Test infrastructure only: the test suite, the smoke check and the CPU-baseline
 leg of the benchmark call this module; the product path never does.
 
-What the paper computes (Sec. IV-F, update messages; Supplementary Sec. S-V):
+What the paper computes (Sec. IV-C, update messages; Supplementary Sec. S-V):
 each message is a complex Gaussian density CN(z_j; mu, C) of the observation
 z_j of array j. Its mean and covariance are moment-matched to the Bernoulli
-mixture over feature existences (proposition of Sec. IV-F), then replaced by
+mixture over feature existences (proposition of Sec. IV-C), then replaced by
 the particle representations of Sec. S-V:
 
   * iota at MT particle p (Sec. S-V, MT state update message):
@@ -30,7 +30,7 @@ Here rho_s = sum_p w_alpha,s^p (the PF's existence probability), zeta_s =
 zeta_s^(j)(r = 1), eta~ = sum_p w_xi^(j,p) eta^(j,p) (the noise prior mean),
 a_s^(j,p) is the steering vector of feature s (s = 0: the line-of-sight path)
 for MT particle p paired with PF particle p (the SFV/VA geometry and array
-response of Sec. II-B/C, taken from the coherent-cost oracle), and the
+response of Secs. II-A and II-B, taken from the coherent-cost oracle), and the
 particle averages are
 
   m_s   = rho_s zeta_s sum_p w_beta^p sqrt(gamma_s^p + |mu_s^p|^2 (1 - zeta_s rho_s)) a_s^(j,p),
@@ -69,7 +69,7 @@ def geometry(ms):
 
 def steering(ms, s: int, p: int, j: int) -> np.ndarray:
     """a_s^(j,p): feature s (0 = line of sight) for MT particle p paired with
-    PF particle p, at array j [N_z] (Sec. II-B/C)."""
+    PF particle p, at array j [N_z] (Secs. II-A and II-B)."""
     f, py, pz = geometry(ms)
     sfv = None if s == 0 else ms.sfv[s, p]
     r = oc.local_vector(ms.mt_pos[p], sfv, ms.pa_pos[j], ms.pa_rot[j])

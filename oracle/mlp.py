@@ -1,7 +1,7 @@
 """FP64 oracle of the learned proposal network (test infrastructure only).
 
 The paper has no learned component (it names hybrid learned / model-based
-processing only as future work, Sec. VI). What is specified here is the
+processing only as future work, Sec. VII). What is specified here is the
 proposal network that predicts coarse directions from the sample covariance,
 so that only narrow windows of the Bartlett grid are scanned:
 

@@ -1,6 +1,6 @@
 // Host side of the coherent multi-array cost over SFV position candidates
 // (the paper's own birth-proposal workload, Sec. IV-D.2 with the geometry of
-// Sec. II-B and the array response of Sec. II-C).
+// Sec. II-A and the array response of Sec. II-B).
 #include <hip/hip_runtime.h>
 
 #include <cmath>

@@ -3,8 +3,8 @@
 //   P(s) = | sum_j (1/N_z) z_j^H psi_j(s) |^2,
 // with psi_j the path-loss compensated wideband URA response of the path
 // that a surface with SFV s creates between the terminal and array j
-// (virtual anchor, Householder mirror and array rotation of Sec. II-B; array
-// response of Sec. II-C).
+// (virtual anchor, Householder mirror and array rotation of Sec. II-A; array
+// response of Sec. II-B).
 //
 // Stacking the arrays, z^H psi(s) is one complex inner product of length
 // J N_z; with x_s = [Re psi; Im psi], u = [Re z; Im z] and v = [-Im z; Re z],

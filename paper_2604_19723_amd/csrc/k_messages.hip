@@ -1,4 +1,4 @@
-// Particle update messages (Sec. IV-F; Supplementary Sec. S-V), FP64.
+// Particle update messages (Sec. IV-C; Supplementary Sec. S-V), FP64.
 //
 // Every message is a complex Gaussian log-density log CN(z_j; mu, C) whose
 // covariance is eta I plus a low-rank part, evaluated with the matrix
@@ -9,7 +9,7 @@
 // the frequency bins are uniform and centred, so the response of a path is a
 // Kronecker product a = g (b (x) y (x) z) of three geometric sequences
 // (delay over the bins, horizontal and vertical phase over the elements;
-// Sec. II-C). Hence
+// Sec. II-B). Hence
 //   * a^H X for a dense X is a three-level contraction (N_z + N_f N_y + N_f
 //     complex MACs);
 //   * <a_s, a_t> is a product of three sums of N_f, N_y, N_z terms.
@@ -116,7 +116,7 @@ __device__ __forceinline__ double2 gsum(double2 v) {
 // (eqs. (array-response), (delay-array-response), (spatial-response-y/z)).
 // The local vector: LOS r = R^T (x - p_pa); surface with SFV v: virtual
 // anchor p_va = p_pa - (2 p_pa.v / |v|^2 - 1) v, Householder mirror of
-// x - p_va across v, then R^T (Sec. II-B).
+// x - p_va across v, then R^T (Sec. II-A).
 struct Kron {
   double2 g, b0, bs, y0, ys, z0, zs;
 };

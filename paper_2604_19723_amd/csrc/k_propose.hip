@@ -9,10 +9,11 @@
 // window points are exactly full-grid points). The maximum of each window
 // (ties to the lower index) is a local maximum of the full spectrum when it
 // lies strictly inside the window, and its parabolic refinement uses the
-// same neighbours as on the full grid. A trial falls back when a window
-// maximum sits on a window edge that is not a grid edge, when two windows
-// find the same point, when a value is NaN, or when the normalised cost
-// P M / tr(R) = a^H R a / (M tr R) of a peak is below the threshold tau.
+// same neighbours as on the full grid. A trial falls back when a proposal or
+// any spectrum value inside a window is NaN, when a window maximum sits on a
+// window edge that is not a grid edge, when two windows find the same point,
+// or when the normalised cost P M / tr(R) = a^H R a / (M tr R) of a peak is
+// not at least the threshold tau.
 #include <climits>
 
 #include "proj_common.h"
@@ -45,6 +46,7 @@ __global__ __launch_bounds__(256, 6) void k_window(WindowArgs A) {
   __shared__ float red[2][C::WR][16 * C::NB];
   __shared__ int s_lo[kMaxProp], s_hi[kMaxProp], s_jb0[kMaxProp];
   __shared__ float s_tr;
+  __shared__ int s_nan;  // a NaN proposal or window value was seen
   __shared__ float wv[4];
   __shared__ int wi[4];
   __shared__ float s_pv[kMaxProp];
@@ -65,7 +67,12 @@ __global__ __launch_bounds__(256, 6) void k_window(WindowArgs A) {
     s_tr = tr;
     // proposals sorted ascending, mapped to the nearest full-grid index
     float u[kMaxProp];
-    for (int k = 0; k < K; ++k) u[k] = A.U[b * A.dout + k];
+    int nanp = 0;
+    for (int k = 0; k < K; ++k) {
+      u[k] = A.U[b * A.dout + k];
+      if (u[k] != u[k]) nanp = 1;
+    }
+    s_nan = nanp;
     for (int i = 1; i < K; ++i)
       for (int j = i; j > 0 && u[j] < u[j - 1]; --j) {
         const float t = u[j];
@@ -74,7 +81,7 @@ __global__ __launch_bounds__(256, 6) void k_window(WindowArgs A) {
       }
     for (int k = 0; k < K; ++k) {
       float uk = u[k];
-      uk = uk != uk ? 0.f : fminf(1.f, fmaxf(-1.f, uk));
+      uk = uk != uk ? 0.f : fminf(1.f, fmaxf(-1.f, uk));  // a NaN proposal (the trial falls back) still gets a window
       const double th = asin(double(uk)) * (180.0 / M_PI);
       long long c = llrint((th - A.theta0) / A.step);
       c = c < 0 ? 0 : (c > A.G - 1 ? A.G - 1 : c);
@@ -143,7 +150,9 @@ __global__ __launch_bounds__(256, 6) void k_window(WindowArgs A) {
     int bi = INT_MAX;
     for (int g = lo + int(threadIdx.x); g <= hi; g += 256) {
       const float p = sP[k * (16 * nbmax) + (g - base)];
-      if (p == p && better(p, g, bv, bi)) {
+      if (p != p) {
+        s_nan = 1;  // every writer stores the same value
+      } else if (better(p, g, bv, bi)) {
         bv = p;
         bi = g;
       }
@@ -175,7 +184,7 @@ __global__ __launch_bounds__(256, 6) void k_window(WindowArgs A) {
   }
 
   if (threadIdx.x == 0) {
-    bool fail = false;
+    bool fail = s_nan != 0;
     for (int k = 0; k < K; ++k) {
       const int g = s_pi[k];
       if (g == INT_MAX) {

@@ -2,7 +2,7 @@
 association of estimates with the true directions.
 
 The paper associates estimates with the ground truth by the Hungarian method
-and leaves missed detections and false alarms out of the error (Sec. V,
+and leaves missed detections and false alarms out of the error (Sec. VI-A,
 caption of its estimation-error figures); on a line the optimal assignment
 for a squared cost is the sorted pairing.
 """

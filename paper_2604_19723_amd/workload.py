@@ -170,7 +170,7 @@ def _draw_angles_azel(rng, K, el_lo, el_hi, min_sep):
 def noise_variance(snr_db: float, K: int, snr_def: str) -> float:
     """Per-source reading: sigma^2 = 10^(-SNR/10) for unit-power sources. The
     sum-channel reading follows the paper's SNR definition on the summed
-    channel power per element (Sec. V-A, system parameters): sigma^2 = K 10^(-SNR/10)."""
+    channel power per element (Sec. VI-A, system parameters): sigma^2 = K 10^(-SNR/10)."""
     base = 10.0 ** (-snr_db / 10.0)
     if snr_def == "per_source":
         return base
@@ -425,7 +425,7 @@ def config5(n_trials: int, first_trial: int = 0, seed_offset: int = 0, K: int = 
 #
 # The paper's own birth-proposal workload: J URAs around a room receive a
 # wideband pilot from one terminal; the observation of array j is the sum of
-# its paths' path-loss compensated responses plus noise (Sec. II-C,
+# its paths' path-loss compensated responses plus noise (Sec. II-B,
 # eq. (observation-generative)). The residual after the known paths is taken
 # as exact, so a trial's observation holds the one new path (the reflection
 # at the wall whose SFV is to be found) plus white noise.
@@ -459,7 +459,7 @@ def _rot_z(a):
 
 
 def _path_response(p_mt, s, p_pa, rot, f_base, p_y, p_z, fc):
-    """Response of the reflected path at one array (signal model of Sec. II-B/C)."""
+    """Response of the reflected path at one array (signal model of Secs. II-A and II-B)."""
     lam = C_LIGHT / fc
     d_mt = p_mt - (p_pa - (2.0 * (p_pa @ s) / (s @ s) - 1.0) * s)   # from the virtual anchor
     w = d_mt - 2.0 * (d_mt @ s) / (s @ s) * s                        # mirrored across the surface
@@ -477,7 +477,7 @@ def coherent_config(n_trials: int = 1024, n_cand: int = 131072, snr_db: float = 
     6 m x 5 m x 2.5 m room, each turned towards the room's centre; the new
     feature is the wall x = 7 m (SFV (14, 0, 0) m); candidates are uniform in
     the 1 m cube around it. Noise is CN(0, eta) with eta set by the sum-channel
-    SNR of Sec. V (mean power of the noise-free observation over the N_z J
+    SNR of Sec. VI-A (mean power of the noise-free observation over the N_z J
     entries, divided by the SNR). The amplitude is common to the arrays (unit
     modulus, uniform phase per trial): the phase-coherent case the coherent
     cost is built for."""
@@ -513,7 +513,7 @@ def coherent_config(n_trials: int = 1024, n_cand: int = 131072, snr_db: float = 
 
 @dataclasses.dataclass
 class MessageSet:
-    """One time step of the particle-based update messages (Sec. IV-F and
+    """One time step of the particle-based update messages (Sec. IV-C and
     Supplementary Sec. S-V): the observation of every array and the particle
     representations the messages are evaluated on. Feature s = 0 is the
     line-of-sight path; features s >= 1 are surfaces given by their SFVs."""
@@ -546,7 +546,7 @@ class MessageSet:
 
 
 def _los_response(p_mt, p_pa, rot, f_base, p_y, p_z, fc):
-    """Response of the direct path at one array (signal model of Sec. II-B/C)."""
+    """Response of the direct path at one array (signal model of Secs. II-A and II-B)."""
     lam = C_LIGHT / fc
     r = rot.T @ (p_mt - p_pa)
     d = math.sqrt(r @ r)
