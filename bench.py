@@ -538,7 +538,7 @@ def message_flops(S, P, J, nf, ny, nz):
 
 
 def bench_messages(args, workers):
-    """Particle update messages of one BP time step (Sec. IV-F, Supplement
+    """Particle update messages of one BP time step (Sec. IV-C, Supplement
     S-V) at the Experiment-1 size: P = 30 000 particles, J = 4 URAs (4 x 4,
     10 bins: N_z = 160), S = 6 features (LOS + 5 surfaces). One step = one
     ba_update_messages call: particle sums, per-(feature, array) setup, MT and

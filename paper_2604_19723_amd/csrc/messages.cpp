@@ -1,4 +1,4 @@
-// Host side of the particle update messages (Sec. IV-F; Supplementary Sec. S-V).
+// Host side of the particle update messages (Sec. IV-C; Supplementary Sec. S-V).
 #include <hip/hip_runtime.h>
 
 #include <cmath>

@@ -1,4 +1,4 @@
-// Internal declarations of the particle update messages (Sec. IV-F and
+// Internal declarations of the particle update messages (Sec. IV-C and
 // Supplementary Sec. S-V): the MT state message iota and the noise message nu
 // at every (particle, array) pair, the PF state message kappa at every
 // (feature, particle, array) triple, and the PR message omega per (feature,
