@@ -683,6 +683,8 @@ def main():
     ap.add_argument("--no-f32-reference", action="store_true",
                     help="with --precision bf16x3|bf16: skip timing the FP32 path on the same trials")
     args = ap.parse_args()
+    if args.steps < 1 or args.warmup < 0 or args.trials < 1:
+        ap.error("--steps >= 1, --warmup >= 0 and --trials >= 1 required")
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: the grid search shards by trials with no "

@@ -127,6 +127,8 @@ def evaluate(plan, net, ts, taus, device, hw=50, steps=1, warmup=1):
     RMSE (deg) per threshold, fallback rate and timings (mean over `steps`
     timed passes after `warmup` untimed ones)."""
     import torch
+    if steps < 1:
+        raise ValueError("evaluate needs steps >= 1 timed passes")
     n = ts.n_trials
     Y = torch.from_numpy(ts.y_c64()).to(device)
     R = torch.empty((n, M, M), dtype=torch.complex64, device=device)

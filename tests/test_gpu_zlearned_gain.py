@@ -34,11 +34,16 @@ def test_trained_network_cuts_the_grid_at_equal_rmse():
         tau = min(ok)
         ev = lr.evaluate(plan, net, wl.config5(1400, seed_offset=7, snr_db=wl.C2_SNRS), [tau], DEV)
         plain, learned = ev["plain"], ev["learned"][0]
-        frac = (1 - learned["fallback"]) * (lr.K * 101) / lr.G + learned["fallback"]
+        # the window kernel projects every 16-column block a window touches:
+        # at most (2 hw) / 16 + 2 blocks per window, i.e. 128 points for hw = 50
+        hw = 50
+        pts = lr.K * 16 * ((2 * hw) // 16 + 2)
+        frac = (1 - learned["fallback"]) * pts / lr.G + learned["fallback"]
+        frac_window = (1 - learned["fallback"]) * (lr.K * (2 * hw + 1)) / lr.G + learned["fallback"]
         print("tau %.2f; plain RMSE %.4f (SE %.4f) %.0f trials/s; learned RMSE %.4f (SE %.4f) %.0f trials/s, "
-              "fallback %.3f, grid evaluated %.3f" % (
+              "fallback %.3f, grid evaluated %.3f (block-rounded; %.3f in window points)" % (
                   tau, plain["rmse"]["rmse"], plain["rmse"]["se"], plain["trials_per_s"], learned["rmse"]["rmse"],
-                  learned["rmse"]["se"], learned["trials_per_s"], learned["fallback"], frac))
+                  learned["rmse"]["se"], learned["trials_per_s"], learned["fallback"], frac, frac_window))
         assert lr.equal_rmse(learned["rmse"], plain["rmse"])
         assert frac < 0.5
     finally:

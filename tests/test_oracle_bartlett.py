@@ -317,6 +317,52 @@ def test_parabolic_refinement_exact_on_parabola():
     np.testing.assert_allclose(r[0], [4.2, 2.7], atol=1e-12)
 
 
+@pytest.mark.parametrize("wrap0", [1, 2])
+def test_parabolic_refinement_across_the_azimuth_wrap(wrap0):
+    # a separable parabola in the wrapped azimuth distance: its vertex lies
+    # between the last row and the first, so the peak row's neighbour on one
+    # side is across the wrap
+    s0, s1 = 12, 7
+    rows = s0 - 1 if wrap0 == 2 else s0
+    i0, i1 = np.meshgrid(np.arange(s0, dtype=float), np.arange(s1, dtype=float), indexing="ij")
+    for x0, peak_row in ((-0.3, 0), (rows - 1 + 0.4, rows - 1), (rows - 0.49, 0)):
+        d = (i0 - x0 + rows / 2.0) % rows - rows / 2.0
+        P = 50.0 - 0.5 * d ** 2 - 0.25 * (i1 - 2.7) ** 2
+        if wrap0 == 2:
+            P[s0 - 1] = -1e9          # the duplicate row is never a neighbour
+        idx, _ = ob.top_k(P.reshape(-1), 1, (s0, s1), wrap0)
+        assert idx[0] // s1 == peak_row
+        r = ob.refine(P.reshape(-1), idx, (s0, s1), wrap0)
+        want0 = x0 if peak_row == 0 and x0 < 0 else (x0 - rows if peak_row == 0 else x0)
+        np.testing.assert_allclose(r[0], [want0, 2.7], atol=1e-12)
+
+
+def test_proposal_moments_on_direction_vectors():
+    # mass 2 at the zenith, 1 each at polar angle a towards +x and -x: the mean is
+    # the zenith and the covariance of the offsets is diag(sin^2 a, 0, (1 - cos a)^2) / 2
+    a = 0.4
+    dirs = np.array([[0.0, 0.0, 1.0], [np.sin(a), 0.0, np.cos(a)], [-np.sin(a), 0.0, np.cos(a)]])
+    P = np.array([2.0, 1.0, 1.0])
+    mu, C = ob.proposal_moments(P, ob.GRID_DIRS, dirs.reshape(-1), (3, 1))
+    np.testing.assert_array_equal(mu, [0.0, 0.0, 1.0])
+    want = np.diag([np.sin(a) ** 2, 0.0, (1 - np.cos(a)) ** 2]) / 2.0
+    np.testing.assert_allclose(C, want, atol=1e-15)
+    # random directions: rotating the grid rotates the moments (mu -> Q mu,
+    # C -> Q C Q^T), and for unit vectors tr C = sum_g w_g (2 - 2 x_g . mu)
+    rng = np.random.default_rng(11)
+    X = rng.standard_normal((40, 3))
+    X /= np.linalg.norm(X, axis=1, keepdims=True)
+    P = rng.random(40)
+    mu, C = ob.proposal_moments(P, ob.GRID_DIRS, X.reshape(-1), (40, 1))
+    w = P / P.sum()
+    assert abs(np.trace(C) - np.sum(w * (2.0 - 2.0 * (X @ mu)))) < 1e-13
+    Q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    mu2, C2 = ob.proposal_moments(P, ob.GRID_DIRS, (X @ Q.T).reshape(-1), (40, 1))
+    np.testing.assert_allclose(mu2, Q @ mu, atol=1e-14)
+    np.testing.assert_allclose(C2, Q @ C @ Q.T, atol=1e-14)
+    assert np.all(np.linalg.eigvalsh(C) >= -1e-15)
+
+
 def test_proposal_moments_closed_forms():
     theta = np.linspace(-10, 10, 21)
     P = np.zeros(21)
