@@ -205,6 +205,28 @@ ba_status ba_run(ba_plan p, int32_t n_trials, int32_t n_snap, const void* Y, int
                  float* P, int32_t* idx, float* val, double* refined,
                  void* workspace, size_t workspace_bytes, void* stream);
 
+/* Bytes of the fixed device scratch array behind ba_run_noalloc (one per GPU). */
+#define BA_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+
+/*
+ * ba_run without a workspace argument and without any allocation, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc). The workspace is a
+ * file-scope device array of BA_NOALLOC_SCRATCH_BYTES bytes that the library
+ * holds on every GPU it runs on until the process ends; its address is looked
+ * up once per device, on the first call there.
+ *   Arguments, layouts and results are those of ba_run (same kernels, same
+ *   values bit for bit). The plan's device must be the current device.
+ *   Errors: BA_ERR_ARG when ba_workspace_size(p, n_trials, n_snap, P != NULL)
+ *   exceeds BA_NOALLOC_SCRATCH_BYTES (split the batch, or pass P so the
+ *   spectrum is not staged), and every error of ba_run; BA_ERR_DEVICE if the
+ *   array's address cannot be obtained.
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind: calls that overlap on one GPU (other streams or host threads) race.
+ */
+ba_status ba_run_noalloc(ba_plan p, int32_t n_trials, int32_t n_snap, const void* Y, int32_t k,
+                         float* P, int32_t* idx, float* val, double* refined, void* stream);
+
 
 /* ------------------------------------------------------------------ ragged batches */
 

@@ -78,6 +78,7 @@ _SIGS = {
     "ba_peaks": (_i32, [_vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp]),
     "ba_proposal_moments": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "ba_run": (_i32, [_vp, _i32, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "ba_run_noalloc": (_i32, [_vp, _i32, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp]),
     "ba_ragged_create": (_i32, [C.POINTER(_vp), _vp, _i32, _vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp]),
     "ba_ragged_launch": (_i32, [_vp, _vp]),
     "ba_ragged_autotune": (_i32, [_vp, C.c_char_p, _i32, _i32]),
@@ -346,6 +347,17 @@ def ba_run(plan: Plan, n_trials, n_snap, Y, k, P, idx, val, refined, workspace, 
         _dev(val, "f32", n_trials * k, "val"),
         _dev(refined, "f64", n_trials * k * nd, "refined", optional=True),
         C.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size(),
+        _stream(stream)))
+
+
+def ba_run_noalloc(plan: Plan, n_trials, n_snap, Y, k, P, idx, val, refined, stream=None):
+    """ba_run with the library's fixed scratch array as the workspace."""
+    M, G, nd = plan.M, plan.G, plan.ndim
+    _check("ba_run_noalloc", lib().ba_run_noalloc(
+        plan.handle, n_trials, n_snap, _dev(Y, "c64", n_trials * n_snap * M, "Y"), k,
+        _dev(P, "f32", n_trials * G, "P", optional=True), _dev(idx, "i32", n_trials * k, "idx"),
+        _dev(val, "f32", n_trials * k, "val"),
+        _dev(refined, "f64", n_trials * k * nd, "refined", optional=True),
         _stream(stream)))
 
 
