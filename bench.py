@@ -134,6 +134,13 @@ def cpu_baseline(ts, K, seconds):
     return out
 
 
+def trial_errors(ts, refined_deg, idx):
+    """Per trial the associated errors in degrees, None where a peak is missing."""
+    from paper_2604_19723_amd import metrics
+    return [None if np.any(idx[b] < 0) else metrics.associated_errors(refined_deg[b], ts.truth[b])
+            for b in range(ts.n_trials)]
+
+
 def rmse_se_by_snr(ts, refined_deg, idx, nboot=200):
     """Per SNR point: RMSE in degrees and its bootstrap standard error over
     trials (200 resamples, fixed seed), estimates associated to the truths."""
@@ -223,9 +230,8 @@ def bench_sequential(args, workers):
         "rmse_deg_by_snr": rmse, "failed_trials": fails,
         "plain_rmse_deg_by_snr": rmse_plain, "plain_failed_trials": fails_plain,
     }
-    print(json.dumps(line), flush=True)
     plan.close()
-    return 0
+    return line
 
 
 def bench_proposal(args, workers):
@@ -310,9 +316,8 @@ def bench_proposal(args, workers):
         "effective_sample_size_median": float(np.median(ess)),
         "particles_finite": bool(np.all(np.isfinite(ph))),
     }
-    print(json.dumps(line), flush=True)
     plan.close()
-    return 0
+    return line
 
 
 def bench_coherent(args, workers):
@@ -386,9 +391,8 @@ def bench_coherent(args, workers):
         "argmax_distance_m": {"median": float(np.median(err)), "p90": float(np.percentile(err, 90))},
         "spot_parity_normwise_max": max(spot),
     }
-    print(json.dumps(line), flush=True)
     h.close()
-    return 0
+    return line
 
 
 def bench_ragged(args, workers):
@@ -439,13 +443,15 @@ def bench_ragged(args, workers):
     from paper_2604_19723_amd import metrics
     est = metrics.fractional_index_to_deg(1, rs.grid, (G, 1), ref.cpu().numpy())
     idx_h = idx.cpu().numpy()
-    err2, fails = [], 0
+    err2, fails, errs = [], 0, []
     for i in range(n):
         K = int(rs.k[i])
         if np.any(idx_h[i, :K] < 0):
             fails += 1
+            errs.append(None)
             continue
         e = metrics.associated_errors(est[i, :K], rs.truth[i])
+        errs.append(e)
         err2.append(np.mean(e * e))
     value = n * args.steps / dt
     line = {
@@ -462,11 +468,11 @@ def bench_ragged(args, workers):
         "cpu_baseline": None,
         "grid_points_trials_per_s": value * G,
         "rmse_deg": float(np.sqrt(np.mean(err2))), "failed_trials": fails,
+        "accuracy": metrics.accuracy_summary(errs),
     }
-    print(json.dumps(line), flush=True)
     r.close()
     plan.close()
-    return 0
+    return line
 
 
 def bench_learned(args, workers):
@@ -496,11 +502,12 @@ def bench_learned(args, workers):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t
     del X, U, Mk
-    taus = [0.0, 0.02, 0.04, 0.06, 0.08, 0.1, 0.12, 0.14, 0.16, 0.18, 0.2, 0.22, 0.25]
+    taus = [0.0, 0.02, 0.04, 0.06, 0.08, 0.1, 0.12, 0.14, 0.16, 0.18, 0.2, 0.22, 0.25, 0.3, 0.35, 0.4]
     ev = L.evaluate(plan, net, val, taus, dev)
-    chosen = next((r for r in ev["learned"] if L.equal_rmse(r["rmse"], ev["plain"]["rmse"])), ev["learned"][-1])
-    log("validation: plain %s; chosen tau %.2f (fallback %.3f, rmse %s)" % (
-        ev["plain"]["rmse"], chosen["tau"], chosen["fallback"], chosen["rmse"]))
+    chosen = L.choose_tau(ev) or ev["learned"][-1]
+    log("validation: plain %s; chosen tau %.2f (fallback %.3f, rmse %s, paired %s)" % (
+        ev["plain"]["rmse"], chosen["tau"], chosen["fallback"], chosen["rmse"],
+        chosen["accuracy_vs_plain"]["equal"]))
     et = L.evaluate(plan, net, test, [chosen["tau"]], dev, steps=args.steps, warmup=args.warmup)
     lt, pt = et["learned"][0], et["plain"]
     line = {
@@ -516,13 +523,16 @@ def bench_learned(args, workers):
         "plain_trials_per_s": pt["trials_per_s"], "speedup_vs_plain": lt["trials_per_s"] / pt["trials_per_s"],
         "rmse_deg": lt["rmse"], "plain_rmse_deg": pt["rmse"],
         "equal_rmse": L.equal_rmse(lt["rmse"], pt["rmse"]), "fallback_rate": lt["fallback"],
+        "accuracy_vs_plain": lt["accuracy_vs_plain"], "equal_accuracy": L.equal_accuracy(lt, pt),
+        "index_identity_vs_plain": lt["index_identity_vs_plain"],
         "train_seconds": t_train, "data_seconds": t_data, "final_loss": hist[-1] if hist else None,
-        "validation": ev,
+        "validation": [{k: r[k] for k in ("tau", "fallback", "rmse", "trials_per_s", "index_identity_vs_plain")}
+                       | {"equal_accuracy": L.equal_accuracy(r, ev["plain"])} for r in ev["learned"]],
+        "validation_plain": ev["plain"],
     }
-    print(json.dumps(line), flush=True)
     net.close()
     plan.close()
-    return 0
+    return line
 
 
 def message_flops(S, P, J, nf, ny, nz):
@@ -622,9 +632,8 @@ def bench_messages(args, workers):
         "event_ms": {"all": ms_all, "prep": ms_prep, "prep_plus_pf": ms_pf},
     }
     line["spot_parity_rel_max"] = spot
-    print(json.dumps(line), flush=True)
     h.close()
-    return 0
+    return line
 
 
 def message_cpu_baseline(ms, seconds):
@@ -682,6 +691,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f32-reference", action="store_true",
                     help="with --precision bf16x3|bf16: skip timing the FP32 path on the same trials")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default workload only: skip the URA BF16x3, uneven-batch and learned-proposal "
+                         "measurements that follow the headline")
     args = ap.parse_args()
     if args.steps < 1 or args.warmup < 0 or args.trials < 1:
         ap.error("--steps >= 1, --warmup >= 0 and --trials >= 1 required")
@@ -692,20 +704,56 @@ def main():
               "real shape (use --gpus 1)", file=sys.stderr)
         return 2
 
-    from paper_2604_19723_amd import workload as wl
     workers = min(16, len(os.sched_getaffinity(0)))
-    if args.workload == "ragged":
-        return bench_ragged(args, workers)
-    if args.workload == "learned":
-        return bench_learned(args, workers)
-    if args.workload == "sequential":
-        return bench_sequential(args, workers)
-    if args.workload == "proposal":
-        return bench_proposal(args, workers)
-    if args.workload == "coherent":
-        return bench_coherent(args, workers)
-    if args.workload == "messages":
-        return bench_messages(args, workers)
+    modes = {"ragged": bench_ragged, "learned": bench_learned, "sequential": bench_sequential,
+             "proposal": bench_proposal, "coherent": bench_coherent, "messages": bench_messages}
+    line = modes.get(args.workload, bench_grid)(args, workers)
+    if args.workload == "ula64" and args.precision == "f32" and not args.no_extras:
+        line["extras"] = run_extras(args, workers)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+# keys of a bench line that only the headline carries
+_LINE_ONLY = ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "cpu_baseline")
+
+
+def run_extras(args, workers):
+    """The other workloads, each at its full size, on the same GPU after the
+    headline: the URA in BF16x3 against FP32 on the same trials, the uneven
+    batch in one persistent launch under a HIP graph, and the learned proposal
+    against the plain FP32 search. Fewer timed steps than the headline (each
+    reports its own)."""
+    import torch
+    steps = max(1, min(args.steps, 5))
+    warm = max(1, min(args.warmup, 2))
+    base = dict(vars(args))
+    base.update(steps=steps, warmup=warm, no_cpu_baseline=True, calib_copy_mib=0, no_autotune=False,
+                no_f32_reference=False, no_extras=True)
+    jobs = [("ura256_bf16x3_vs_f32", bench_grid, dict(workload="ura256", precision="bf16x3", trials=2000)),
+            ("ragged", bench_ragged, dict(workload="ragged", precision="f32", trials=50000)),
+            ("learned", bench_learned, dict(workload="learned", precision="f32", trials=10000,
+                                            train_trials=1000000, epochs=8))]
+    out = {}
+    for name, fn, kw in jobs:
+        a = argparse.Namespace(**dict(base, **kw))
+        t = time.perf_counter()
+        try:
+            r = fn(a, workers)
+            out[name] = {k: v for k, v in r.items() if k not in _LINE_ONLY}
+        except Exception as e:  # one failing extra must not cost the headline line
+            out[name] = {"error": "%s: %s" % (type(e).__name__, e)}
+        out[name]["wall_s"] = time.perf_counter() - t
+        log("extra %s done in %.1f s" % (name, out[name]["wall_s"]))
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    return out
+
+
+def bench_grid(args, workers):
+    """The plain path (covariance, spectrum, peaks) on the ULA 64 or URA 256
+    workload in the chosen precision."""
+    from paper_2604_19723_amd import workload as wl
     t = time.perf_counter()
     if args.workload == "ula64":
         ts = wl.config2(args.trials, dtype=np.complex64, workers=workers)   # before the GPU is touched
@@ -800,13 +848,18 @@ def main():
               max(0.01 * rmse_f[s_]["rmse"], 2.0 * max(rmse_v[s_]["se"], rmse_f[s_]["se"]))
               for s_ in rmse_f if s_ in rmse_v}
         f32_tps = B * args.steps / dt32
+        acc = metrics.compare_accuracy(trial_errors(ts, est_deg, idx_h), trial_errors(ts, est32, idx32))
         vs_f32 = {"f32_trials_per_s": f32_tps, "ratio": (B * args.steps / dt) / f32_tps,
+                  "f32_ms_per_step": dt32 / args.steps * 1e3,
                   "rmse_deg_by_snr": {k_: v_["rmse"] for k_, v_ in rmse_v.items()},
                   "f32_rmse_deg_by_snr": {k_: v_["rmse"] for k_, v_ in rmse_f.items()},
                   "equal_rmse_by_snr": eq, "equal_rmse": bool(eq) and all(eq.values()),
-                  "rule": "|RMSE - RMSE_f32| <= max(1 % RMSE_f32, 2 bootstrap SE), per SNR point"}
-        log("FP32 on the same trials: %.1f ms/step, ratio %.2f, equal RMSE %s" % (
-            dt32 / args.steps * 1e3, vs_f32["ratio"], vs_f32["equal_rmse"]))
+                  "rule": "|RMSE - RMSE_f32| <= max(1 % RMSE_f32, 2 bootstrap SE), per SNR point",
+                  "index_identity": metrics.index_identity(idx_h, idx32),
+                  "accuracy_vs_f32": acc, "equal_accuracy": acc["equal_accuracy"]}
+        log("FP32 on the same trials: %.1f ms/step, ratio %.2f, equal RMSE %s, equal accuracy %s, "
+            "index identity %.4f" % (dt32 / args.steps * 1e3, vs_f32["ratio"], vs_f32["equal_rmse"],
+                                     acc["equal_accuracy"], vs_f32["index_identity"]))
     if args.calib_copy_mib:
         n = args.calib_copy_mib * 1024 * 256
         src = torch.ones(n, dtype=torch.float32, device=dev)
@@ -849,13 +902,13 @@ def main():
         "grid_points_trials_per_s": value * G,
         "rmse_deg_by_snr": rmse,
         "failed_trials": fails,
+        "accuracy": metrics.accuracy_summary(trial_errors(ts, est_deg, idx_h)),
         "spot_parity_normwise_max": float(np.max(errs)),
     }
     if vs_f32 is not None:
         line["vs_f32_same_trials"] = vs_f32
-    print(json.dumps(line), flush=True)
     plan.close()
-    return 0
+    return line
 
 
 if __name__ == "__main__":

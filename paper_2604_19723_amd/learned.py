@@ -150,7 +150,9 @@ def evaluate(plan, net, ts, taus, device, hw=50, steps=1, warmup=1):
         plain()
     torch.cuda.synchronize()
     t_plain = (time.perf_counter() - t0) / steps
-    base = _rmse(ts, idx.cpu().numpy(), ref.cpu().numpy()[..., 0])
+    idx_plain = idx.cpu().numpy()
+    base = _rmse(ts, idx_plain, ref.cpu().numpy()[..., 0])
+    err_plain = _trial_errors(ts, idx_plain, ref.cpu().numpy()[..., 0])
 
     li = torch.empty((n, K), dtype=torch.int32, device=device)
     lv = torch.empty((n, K), dtype=torch.float32, device=device)
@@ -170,9 +172,20 @@ def evaluate(plan, net, ts, taus, device, hw=50, steps=1, warmup=1):
             nf = learned()
         torch.cuda.synchronize()
         t_l = (time.perf_counter() - t0) / steps
-        r = _rmse(ts, li.cpu().numpy(), lr_.cpu().numpy())
-        res.append(dict(tau=float(tau), fallback=nf / n, rmse=r, seconds=t_l, trials_per_s=n / t_l))
+        idx_l, ref_l = li.cpu().numpy(), lr_.cpu().numpy()
+        r = _rmse(ts, idx_l, ref_l)
+        cmp = metrics.compare_accuracy(_trial_errors(ts, idx_l, ref_l), err_plain)
+        res.append(dict(tau=float(tau), fallback=nf / n, rmse=r, seconds=t_l, trials_per_s=n / t_l,
+                        accuracy_vs_plain=cmp, index_identity_vs_plain=metrics.index_identity(idx_l, idx_plain)))
     return dict(plain=dict(rmse=base, seconds=t_plain, trials_per_s=n / t_plain), learned=res)
+
+
+def _trial_errors(ts, idx, ref_grid):
+    """Per trial the associated errors in degrees (sorted pairing), None
+    where a peak is missing."""
+    deg = -90.0 + ref_grid * (180.0 / (G - 1))
+    return [None if np.any(idx[b] < 0) else metrics.associated_errors(deg[b], ts.truth[b])
+            for b in range(ts.n_trials)]
 
 
 def _rmse(ts, idx, ref_grid):
@@ -195,3 +208,17 @@ def _rmse(ts, idx, ref_grid):
 def equal_rmse(r_l, r_p):
     """|RMSE_l - RMSE_p| <= max(1 % RMSE_p, 2 SE)."""
     return abs(r_l["rmse"] - r_p["rmse"]) <= max(0.01 * r_p["rmse"], 2.0 * max(r_l["se"], r_p["se"]))
+
+
+def equal_accuracy(r, plain):
+    """A learned result (one entry of evaluate()["learned"]) matches the plain
+    search: equal RMSE, and equal median error, resolved fraction and RMSE over
+    resolved sources in the paired comparison on the same trials."""
+    return bool(equal_rmse(r["rmse"], plain["rmse"]) and r["accuracy_vs_plain"]["equal_accuracy"])
+
+
+def choose_tau(ev):
+    """The smallest threshold whose result matches the plain search
+    (equal_accuracy), or None."""
+    ok = [r for r in ev["learned"] if equal_accuracy(r, ev["plain"])]
+    return min(ok, key=lambda r: r["tau"]) if ok else None

@@ -346,12 +346,10 @@ def _ragged_sizes(rng, t_max):
     return K, M, T
 
 
-def config4(n_trials: int = 50000, first_trial: int = 0, n_grid: int = 3601,
-            t_max: int = 2048, dtype=np.complex128, workers: int = 1) -> RaggedSet:
-    """Uneven batch: M uniform over {8,16,32,64,128}, K uniform over 1..6,
-    T = clip(rint(exp(U[ln 16, ln t_max])), 16, t_max), SNR ~ U[-10, 20] dB.
-    Sizes are drawn first (the head of each trial's stream) to lay out the
-    pool; then ``workers`` threads fill their trials in place."""
+def config4_layout(n_trials: int = 50000, first_trial: int = 0, t_max: int = 2048):
+    """Sizes of the uneven batch without its data: K, M, T per trial (the head
+    of each trial's stream) and the trials' complex offsets in the pool.
+    Returns (K, M, T, offsets, pool elements)."""
     seed = SEED_BASE + 4
     Ms = np.empty(n_trials, np.int32)
     Ts = np.empty(n_trials, np.int32)
@@ -361,19 +359,34 @@ def config4(n_trials: int = 50000, first_trial: int = 0, n_grid: int = 3601,
     sizes = Ms.astype(np.int64) * Ts
     off = np.zeros(n_trials, np.int64)
     off[1:] = np.cumsum(sizes)[:-1]
-    pool = np.empty(int(sizes.sum()), dtype)
+    return Ks, Ms, Ts, off, int(sizes.sum())
+
+
+def config4_trial(i: int, t_max: int = 2048):
+    """Trial i of the uneven batch: (Y [T][M] complex128, truth degrees, SNR dB)."""
+    rng = trial_rng(SEED_BASE + 4, i)
+    K, M, T = _ragged_sizes(rng, t_max)
+    s = float(rng.uniform(-10.0, 20.0))
+    th = _draw_angles_1d(rng, K, -60.0, 60.0, 5.0)
+    y = _snapshots(rng, response(ula_positions(M), ula_dirs(th)), T, noise_variance(s, K, "per_source"))
+    return y, th, s
+
+
+def config4(n_trials: int = 50000, first_trial: int = 0, n_grid: int = 3601,
+            t_max: int = 2048, dtype=np.complex128, workers: int = 1) -> RaggedSet:
+    """Uneven batch: M uniform over {8,16,32,64,128}, K uniform over 1..6,
+    T = clip(rint(exp(U[ln 16, ln t_max])), 16, t_max), SNR ~ U[-10, 20] dB.
+    Sizes are drawn first (the head of each trial's stream) to lay out the
+    pool; then ``workers`` threads fill their trials in place."""
+    Ks, Ms, Ts, off, total = config4_layout(n_trials, first_trial, t_max)
+    pool = np.empty(total, dtype)
     snr = np.empty(n_trials)
     truth = [None] * n_trials
 
     def fill(lo, hi):
         for b in range(lo, hi):
-            rng = trial_rng(seed, first_trial + b)
-            K, M, T = _ragged_sizes(rng, t_max)
-            s = float(rng.uniform(-10.0, 20.0))
-            th = _draw_angles_1d(rng, K, -60.0, 60.0, 5.0)
-            y = _snapshots(rng, response(ula_positions(M), ula_dirs(th)), T,
-                           noise_variance(s, K, "per_source"))
-            pool[off[b]:off[b] + M * T] = y.reshape(-1)
+            y, th, s = config4_trial(first_trial + b, t_max)
+            pool[off[b]:off[b] + y.size] = y.reshape(-1)
             snr[b] = s
             truth[b] = th
 
