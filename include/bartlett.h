@@ -365,8 +365,11 @@ ba_status ba_propose_workspace_size(ba_plan plan, int32_t n_trials, int32_t d_ou
  *   net         d_in = M^2, d_out >= k.
  *   R           dev c64 [B][M][M]; k in [1, 8]; half_window in [1, 100]; tau in [0, 1].
  *   idx, val, refined  dev [B][k] (refined in grid units); fell_back dev uint8 [B].
- *   n_fallback  host int32 (may be NULL): trials that fell back.
- * Synchronises the stream once (to size the fallback batch).
+ *   n_fallback  dev int32 (may be NULL): receives the number of trials that
+ *               fell back (written on the stream; 0 when n_trials = 0).
+ * Enqueues everything and never waits for the device: the fallback kernels
+ * are launched for the whole batch and read the number of fallback trials on
+ * the device (so the call can be captured in a graph).
  */
 ba_status ba_propose_refine(ba_plan plan, ba_mlp net, int32_t n_trials, const void* R, int32_t k,
                             int32_t half_window, float tau, int32_t* idx, float* val, double* refined,

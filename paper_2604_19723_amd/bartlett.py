@@ -97,7 +97,7 @@ _SIGS = {
     "ba_mlp_dims": (_i32, [_vp, C.POINTER(_i32), C.POINTER(_i32)]),
     "ba_propose_workspace_size": (_i32, [_vp, _i32, _i32, _i32, C.POINTER(_sz)]),
     "ba_propose_refine": (_i32, [_vp, _vp, _i32, _vp, _i32, _i32, C.c_float, _vp, _vp, _vp, _vp,
-                                 C.POINTER(_i32), _vp, _sz, _vp]),
+                                 _vp, _vp, _sz, _vp]),
     "ba_proposal_sample": (_i32, [_vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp]),
     "ba_coherent_create": (_i32, [C.POINTER(_vp), _i32, _vp, _vp, _i32, _i32, _i32, C.c_double, C.c_double,
                                   _vp, C.c_int64, _vp]),
@@ -580,18 +580,18 @@ def ba_propose_workspace_size(plan: Plan, n_trials, d_out, k) -> int:
 
 
 def ba_propose_refine(plan: Plan, net: Mlp, n_trials, R, k, half_window, tau, idx, val, refined,
-                      fell_back, workspace, stream=None) -> int:
-    """Returns the number of trials that fell back to the full grid."""
+                      fell_back, workspace, stream=None, n_fallback=None):
+    """Enqueues the learned-proposal refinement; nothing waits for the device.
+    n_fallback: optional device int32 tensor that receives the number of
+    trials that fell back to the full grid."""
     M = plan.M
     need = ba_propose_workspace_size(plan, n_trials, net.dims[-1], k)
     ws, nbytes = _workspace(workspace, need)
-    nf = _i32()
     _check("ba_propose_refine", lib().ba_propose_refine(
         plan.handle, net.handle, n_trials, _dev(R, "c64", n_trials * M * M, "R"), k, half_window,
         float(tau), _dev(idx, "i32", n_trials * k, "idx"), _dev(val, "f32", n_trials * k, "val"),
         _dev(refined, "f64", n_trials * k, "refined"), _dev(fell_back, "u8", n_trials, "fell_back"),
-        C.byref(nf), ws, nbytes, _stream(stream)))
-    return nf.value
+        _dev(n_fallback, "i32", 1, "n_fallback", optional=True), ws, nbytes, _stream(stream)))
 
 
 # --------------------------------------------------------------------------- residual projector

@@ -49,11 +49,17 @@ hipError_t launch_spectrum_stream(const Plan& p, int B, const float2* R, void* Q
                                   hipStream_t s);
 hipError_t launch_spectrum_valu(const Plan& p, int B, const float2* R, float* P, hipStream_t s);
 hipError_t launch_spectrum_mfma(const Plan& p, int B, const float2* R, float* P, hipStream_t s);
+// FP32 spectrum of *count trials (read on the device, at most cap), the
+// launch sized for `expect` trials at a time
+hipError_t launch_spectrum_mfma_counted(const Plan& p, int cap, const int* count, int expect, const float2* R,
+                                        float* P, hipStream_t s);
 hipError_t launch_spectrum_qb(const Plan& p, int B, const float2* R, float* P, hipStream_t s);
 hipError_t launch_spectrum_snapshots(const Plan& p, int B, int T, const float2* Y, float* P,
                                      hipStream_t s);
+// count: when non-NULL, the batch is *count trials (read on the device,
+// at most B) and the launch is sized without reading it
 hipError_t launch_peaks(const Plan& p, int B, const float* P, int k, int* idx, float* val,
-                        double* refined, hipStream_t s);
+                        double* refined, hipStream_t s, const int* count = nullptr);
 hipError_t launch_moments(const Plan& p, int B, const float* P, double* mu_cov, hipStream_t s);
 
 // residual covariance R~ = Pi R Pi (Psi given as vectors [B][S][M], or as grid

@@ -14,6 +14,8 @@
 // pick the winners in order.
 #include <climits>
 
+#include <algorithm>
+
 #include "ba_internal.h"
 #include "coherent.h"
 
@@ -84,11 +86,10 @@ __device__ double parabolic(double pm, double p0, double pp) {
 // (same rule as is_local_max: the earlier neighbour strictly, the later one
 // with >=, wrap of the row when wrap0, every comparison with NaN false).
 template <int KC, bool ONED>
-__global__ __launch_bounds__(256) void k_peaks(const float* __restrict__ P, int64_t G, int s1,
-                                               int rows, int wrap0, int k, int* __restrict__ idx,
-                                               float* __restrict__ val,
-                                               double* __restrict__ refined, int ndim) {
-  const int64_t b = blockIdx.x;
+__device__ __forceinline__ void peaks_trial(int64_t b, const float* __restrict__ P, int64_t G, int s1,
+                                            int rows, int wrap0, int k, int* __restrict__ idx,
+                                            float* __restrict__ val,
+                                            double* __restrict__ refined, int ndim) {
   const float* Pb = P + b * G;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
@@ -213,6 +214,27 @@ __global__ __launch_bounds__(256) void k_peaks(const float* __restrict__ P, int6
   }
 }
 
+template <int KC, bool ONED>
+__global__ __launch_bounds__(256) void k_peaks(const float* __restrict__ P, int64_t G, int s1, int rows,
+                                               int wrap0, int k, int* __restrict__ idx, float* __restrict__ val,
+                                               double* __restrict__ refined, int ndim) {
+  peaks_trial<KC, ONED>(blockIdx.x, P, G, s1, rows, wrap0, k, idx, val, refined, ndim);
+}
+
+// The same over a batch whose size is only known on the device (*count
+// trials): workgroups step through the trials with the grid's stride.
+template <int KC, bool ONED>
+__global__ __launch_bounds__(256) void k_peaks_counted(const float* __restrict__ P, int64_t G, int s1, int rows,
+                                                       int wrap0, int k, int* __restrict__ idx,
+                                                       float* __restrict__ val, double* __restrict__ refined,
+                                                       int ndim, const int* __restrict__ count) {
+  const int64_t n = *count;
+  for (int64_t b = blockIdx.x; b < n; b += gridDim.x) {
+    peaks_trial<KC, ONED>(b, P, G, s1, rows, wrap0, k, idx, val, refined, ndim);
+    __syncthreads();  // the next trial reuses the shared staging
+  }
+}
+
 __device__ __forceinline__ double block_sum(double x, double* red) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -306,52 +328,58 @@ __global__ __launch_bounds__(256) void k_moments(const float* __restrict__ P, in
 }  // namespace
 
 hipError_t launch_peaks(const Plan& p, int B, const float* P, int k, int* idx, float* val,
-                        double* refined, hipStream_t s) {
-  const dim3 grid{static_cast<uint32_t>(B)}, block{256u};
+                        double* refined, hipStream_t s, const int* count) {
+  // counted: at most 2048 workgroups step through the device-side count
+  const dim3 grid{static_cast<uint32_t>(count ? std::min(B, 2048) : B)}, block{256u};
   // a 1-D candidate row of up to kPeakRowMax points is staged in LDS
   const bool oned = p.shape1 == 1 && p.rows <= kPeakRowMax;
   const size_t lds = oned ? size_t(p.rows) * sizeof(float) : 0;
-#define BA_PK(KCV)                                                                                        \
-  if (oned)                                                                                               \
-    hipLaunchKernelGGL((k_peaks<KCV, true>), grid, block, lds, s, P, p.G, p.shape1, p.rows, p.wrap0, k, idx, \
-                       val, refined, p.ndim);                                                             \
-  else                                                                                                    \
-    hipLaunchKernelGGL((k_peaks<KCV, false>), grid, block, 0, s, P, p.G, p.shape1, p.rows, p.wrap0, k, idx, \
-                       val, refined, p.ndim)
+#define BA_PK1(KCV, OD)                                                                                     \
+  if (count)                                                                                                 \
+    hipLaunchKernelGGL((k_peaks_counted<KCV, OD>), grid, block, OD ? lds : 0, s, P, p.G, p.shape1, p.rows,   \
+                       p.wrap0, k, idx, val, refined, p.ndim, count);                                        \
+  else                                                                                                       \
+    hipLaunchKernelGGL((k_peaks<KCV, OD>), grid, block, OD ? lds : 0, s, P, p.G, p.shape1, p.rows, p.wrap0, k, \
+                       idx, val, refined, p.ndim)
+#define BA_PK(KCV)       \
+  if (oned) {            \
+    BA_PK1(KCV, true);   \
+  } else {               \
+    BA_PK1(KCV, false);  \
+  }
   if (k <= 1)
-    BA_PK(1);
+    BA_PK(1)
   else if (k <= 2)
-    BA_PK(2);
+    BA_PK(2)
   else if (k <= 4)
-    BA_PK(4);
+    BA_PK(4)
   else if (k <= 8)
-    BA_PK(8);
+    BA_PK(8)
   else
-    BA_PK(16);
+    BA_PK(16)
 #undef BA_PK
+#undef BA_PK1
   return hipGetLastError();
 }
 
-// The same moments over a large point set X [G][3] (no wrap), in one pass:
-// with S0 = sum P, m = sum P x / S0 and S2 = sum P x x^T / S0,
-//   C = S2 - mu m^T - m mu^T + mu mu^T,
-// which equals sum w (x - mu)(x - mu)^T. Slices of the points go to separate
-// workgroups (FP64 partial sums and the slice's maximum), and one workgroup
-// per trial combines the slices in index order.
+// The same moments over a large point set X [G][3] (no wrap). The maximum
+// comes first: every slice of the points reports its best (value, index),
+// then every slice workgroup of a trial combines those few entries in index
+// order into the same mu and accumulates, in FP64, S0 = sum P and
+// S2 = sum P (x - mu)(x - mu)^T about it, so C = S2 / S0 is the weighted
+// second moment as defined, with no cancellation against |mu|^2; one
+// workgroup per trial sums the slices in index order (deterministic).
 constexpr int kPtSlice = 8192;
-constexpr int kPtParts = 11;  // S0, S1[3], S2[6], max value; the index goes separately
+constexpr int kPtParts = 7;  // S0, S2[6]
 
-__global__ __launch_bounds__(256) void k_point_partial(const float* __restrict__ P, int64_t G,
-                                                       const double* __restrict__ X, int nslice,
-                                                       double* __restrict__ part, int* __restrict__ part_idx) {
+__global__ __launch_bounds__(256) void k_point_max(const float* __restrict__ P, int64_t G, int nslice,
+                                                   float* __restrict__ part_val, int* __restrict__ part_idx) {
   const int64_t b = blockIdx.x / nslice;
   const int sl = int(blockIdx.x % nslice);
   const float* Pb = P + b * G;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  __shared__ double red[4];
   __shared__ float wv[4];
   __shared__ int wi[4];
-  double acc[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   float bv = -INFINITY;
   int bi = INT_MAX;
   const int64_t g1 = min(G, int64_t(sl + 1) * kPtSlice);
@@ -361,23 +389,6 @@ __global__ __launch_bounds__(256) void k_point_partial(const float* __restrict__
       bv = pf;
       bi = int(g);
     }
-    const double p = double(pf);
-    const double x0 = X[3 * g], x1 = X[3 * g + 1], x2 = X[3 * g + 2];
-    acc[0] += p;
-    acc[1] += p * x0;
-    acc[2] += p * x1;
-    acc[3] += p * x2;
-    acc[4] += p * x0 * x0;
-    acc[5] += p * x0 * x1;
-    acc[6] += p * x0 * x2;
-    acc[7] += p * x1 * x1;
-    acc[8] += p * x1 * x2;
-    acc[9] += p * x2 * x2;
-  }
-  double* o = part + (b * nslice + sl) * kPtParts;
-  for (int c = 0; c < 10; ++c) {
-    const double v = block_sum(acc[c], red);
-    if (tid == 0) o[c] = v;
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -399,57 +410,101 @@ __global__ __launch_bounds__(256) void k_point_partial(const float* __restrict__
         bv = wv[w];
         bi = wi[w];
       }
-    o[10] = double(bv);
+    part_val[b * nslice + sl] = bv;
     part_idx[b * nslice + sl] = bi;
   }
 }
 
-__global__ __launch_bounds__(64) void k_point_combine(const double* __restrict__ part,
-                                                      const int* __restrict__ part_idx, int nslice,
-                                                      const double* __restrict__ X, double* __restrict__ out) {
-  const int64_t b = blockIdx.x;
-  if (threadIdx.x != 0) return;
-  double S[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+// the trial's maximum from its slices' maxima, in slice (index) order
+__device__ __forceinline__ int trial_argmax(const float* __restrict__ part_val, const int* __restrict__ part_idx,
+                                            int64_t b, int nslice) {
   float bv = -INFINITY;
   int bi = INT_MAX;
   for (int sl = 0; sl < nslice; ++sl) {
-    const double* o = part + (b * nslice + sl) * kPtParts;
-    for (int c = 0; c < 10; ++c) S[c] += o[c];
-    const float v = float(o[10]);
     const int i = part_idx[b * nslice + sl];
+    const float v = part_val[b * nslice + sl];
     if (i != INT_MAX && better(v, i, bv, bi)) {
       bv = v;
       bi = i;
     }
   }
-  const double nan = __longlong_as_double(0x7ff8000000000000LL);
-  double mu[3], m[3];
-  for (int a = 0; a < 3; ++a) {
-    mu[a] = bi != INT_MAX ? X[int64_t(bi) * 3 + a] : nan;
-    m[a] = S[1 + a] / S[0];
+  return bi;
+}
+
+__global__ __launch_bounds__(256) void k_point_partial(const float* __restrict__ P, int64_t G,
+                                                       const double* __restrict__ X, int nslice,
+                                                       const float* __restrict__ part_val,
+                                                       const int* __restrict__ part_idx,
+                                                       double* __restrict__ part) {
+  const int64_t b = blockIdx.x / nslice;
+  const int sl = int(blockIdx.x % nslice);
+  const float* Pb = P + b * G;
+  const int tid = threadIdx.x;
+  __shared__ double red[4];
+  const int bi = trial_argmax(part_val, part_idx, b, nslice);
+  double* o = part + (b * nslice + sl) * kPtParts;
+  if (bi == INT_MAX) {  // every value NaN: no mean
+    if (tid < kPtParts) o[tid] = __longlong_as_double(0x7ff8000000000000LL);
+    return;
   }
-  const int q[3][3] = {{4, 5, 6}, {5, 7, 8}, {6, 8, 9}};
+  const double mu0 = X[3 * int64_t(bi)], mu1 = X[3 * int64_t(bi) + 1], mu2 = X[3 * int64_t(bi) + 2];
+  double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const int64_t g1 = min(G, int64_t(sl + 1) * kPtSlice);
+  for (int64_t g = int64_t(sl) * kPtSlice + tid; g < g1; g += 256) {
+    const double p = double(Pb[g]);
+    const double y0 = X[3 * g] - mu0, y1 = X[3 * g + 1] - mu1, y2 = X[3 * g + 2] - mu2;
+    acc[0] += p;
+    acc[1] += p * y0 * y0;
+    acc[2] += p * y0 * y1;
+    acc[3] += p * y0 * y2;
+    acc[4] += p * y1 * y1;
+    acc[5] += p * y1 * y2;
+    acc[6] += p * y2 * y2;
+  }
+  for (int c = 0; c < kPtParts; ++c) {
+    const double v = block_sum(acc[c], red);
+    if (tid == 0) o[c] = v;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_point_combine(const double* __restrict__ part,
+                                                      const float* __restrict__ part_val,
+                                                      const int* __restrict__ part_idx, int nslice,
+                                                      const double* __restrict__ X, double* __restrict__ out) {
+  const int64_t b = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  double S[kPtParts] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int sl = 0; sl < nslice; ++sl) {
+    const double* o = part + (b * nslice + sl) * kPtParts;
+    for (int c = 0; c < kPtParts; ++c) S[c] += o[c];
+  }
+  const int bi = trial_argmax(part_val, part_idx, b, nslice);
+  const double nan = __longlong_as_double(0x7ff8000000000000LL);
   double* o = out + b * 12;
-  for (int a = 0; a < 3; ++a) o[a] = mu[a];
+  for (int a = 0; a < 3; ++a) o[a] = bi != INT_MAX ? X[int64_t(bi) * 3 + a] : nan;
+  const int q[3][3] = {{1, 2, 3}, {2, 4, 5}, {3, 5, 6}};
   for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j)
-      o[3 + i * 3 + j] = S[q[i][j]] / S[0] - mu[i] * m[j] - m[i] * mu[j] + mu[i] * mu[j];
+    for (int j = 0; j < 3; ++j) o[3 + i * 3 + j] = S[q[i][j]] / S[0];
 }
 
 size_t point_moments_ws_bytes(int B, int64_t G) {
   const int64_t nslice = (G + kPtSlice - 1) / kPtSlice;
-  return size_t(B) * nslice * (kPtParts * sizeof(double) + sizeof(int)) + 256;
+  return size_t(B) * nslice * (kPtParts * sizeof(double) + sizeof(float) + sizeof(int)) + 256;
 }
 
 hipError_t launch_point_moments(int B, const float* P, int64_t G, const double* X, double* mu_cov, void* ws,
                                 hipStream_t s) {
   const int nslice = int((G + kPtSlice - 1) / kPtSlice);
   double* part = static_cast<double*>(ws);
-  int* part_idx = reinterpret_cast<int*>(part + size_t(B) * nslice * kPtParts);
+  float* part_val = reinterpret_cast<float*>(part + size_t(B) * nslice * kPtParts);
+  int* part_idx = reinterpret_cast<int*>(part_val + size_t(B) * nslice);
   const int64_t nblk = int64_t(nslice) * B;
   if (nblk > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_point_partial, dim3(unsigned(nblk)), dim3(256), 0, s, P, G, X, nslice, part, part_idx);
-  hipLaunchKernelGGL(k_point_combine, dim3(unsigned(B)), dim3(64), 0, s, part, part_idx, nslice, X, mu_cov);
+  hipLaunchKernelGGL(k_point_max, dim3(unsigned(nblk)), dim3(256), 0, s, P, G, nslice, part_val, part_idx);
+  hipLaunchKernelGGL(k_point_partial, dim3(unsigned(nblk)), dim3(256), 0, s, P, G, X, nslice, part_val, part_idx,
+                     part);
+  hipLaunchKernelGGL(k_point_combine, dim3(unsigned(B)), dim3(64), 0, s, part, part_val, part_idx, nslice, X,
+                     mu_cov);
   return hipGetLastError();
 }
 

@@ -28,26 +28,21 @@
 //    shuffles and across waves through LDS in a fixed order, then scaled by
 //    2/M^2.
 // Element counts up to 64 are padded to MP in {8, 16, 32, 64} with zero rows.
+#include <algorithm>
+
 #include "proj_common.h"
 
 namespace ba {
 namespace {
 
+// One trial's spectrum over the chunks [c0, c1) of the steering table.
 template <int MP>
-__global__ __launch_bounds__(256, 2) void k_proj_q(const float2* __restrict__ R,
-                                                   const float4* __restrict__ Xg,
-                                                   float* __restrict__ P, int M, int64_t G,
-                                                   int nchunk, int chunks_per_wg, int nsplit) {
+__device__ __forceinline__ void proj_q_trial(const float2* __restrict__ Rb, const float4* __restrict__ Xg,
+                                             float* __restrict__ Pb, int M, int64_t G, int c0, int c1,
+                                             float4* sX, float (*red)[QCfg<MP>::WR][QCfg<MP>::NB * 16]) {
   using C = QCfg<MP>;
-  extern __shared__ __attribute__((aligned(16))) float4 sX[];   // [2][CH4], dynamic: filled by LDS DMA
-  __shared__ float red[2][C::WR][C::NB * 16];
-
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wr = wave % C::WR, wc = wave / C::WR;
-  const int64_t b = blockIdx.x / nsplit;
-  const int c0 = (blockIdx.x % nsplit) * chunks_per_wg;
-  const int c1 = min(c0 + chunks_per_wg, nchunk);
-  if (c0 >= c1) return;  // uniform across the workgroup
 
   // each wave copies its quarter of a chunk, 64 lanes x 16 bytes per DMA
   auto fetch = [&](int c, int buf) {
@@ -59,7 +54,7 @@ __global__ __launch_bounds__(256, 2) void k_proj_q(const float2* __restrict__ R,
   };
 
   float a[C::VL];
-  load_q_fragments<MP>(R + b * int64_t(M) * M, M, wr, lane, a);
+  load_q_fragments<MP>(Rb, M, wr, lane, a);
   fetch(c0, 0);
   lds_dma_wait();
   __syncthreads();
@@ -75,7 +70,7 @@ __global__ __launch_bounds__(256, 2) void k_proj_q(const float2* __restrict__ R,
       const float part = block_quadratic<MP>(a, sxb + jb * (C::BLK / 4), sx + jb * C::BLK, wr, lane);
       if (C::WR == 1) {
         const int64_t g = int64_t(c) * C::NB * 16 + jb * 16 + lane;
-        if (lane < 16 && g < G) P[b * G + g] = part * scale;
+        if (lane < 16 && g < G) Pb[g] = part * scale;
       } else if (lane < 16) {
         red[buf][wr][jb * 16 + lane] = part;
       }
@@ -88,28 +83,75 @@ __global__ __launch_bounds__(256, 2) void k_proj_q(const float2* __restrict__ R,
 #pragma unroll
         for (int w = 0; w < C::WR; ++w) s += red[buf][w][t];
         const int64_t g = int64_t(c) * C::NB * 16 + t;
-        if (g < G) P[b * G + g] = s * scale;
+        if (g < G) Pb[g] = s * scale;
       }
     }
   }
 }
 
 template <int MP>
-hipError_t launch_q(const Plan& p, int B, const float2* R, float* P, hipStream_t s) {
+__global__ __launch_bounds__(256, 2) void k_proj_q(const float2* __restrict__ R,
+                                                   const float4* __restrict__ Xg,
+                                                   float* __restrict__ P, int M, int64_t G,
+                                                   int nchunk, int chunks_per_wg, int nsplit) {
+  using C = QCfg<MP>;
+  extern __shared__ __attribute__((aligned(16))) float4 sX[];   // [2][CH4], dynamic: filled by LDS DMA
+  __shared__ float red[2][C::WR][C::NB * 16];
+  const int64_t b = blockIdx.x / nsplit;
+  const int c0 = (blockIdx.x % nsplit) * chunks_per_wg;
+  const int c1 = min(c0 + chunks_per_wg, nchunk);
+  if (c0 >= c1) return;  // uniform across the workgroup
+  proj_q_trial<MP>(R + b * int64_t(M) * M, Xg, P + b * G, M, G, c0, c1, sX, red);
+}
+
+// The same over a batch whose size is only known on the device (*count
+// trials, count <= the launch's capacity): the workgroups of one column range
+// step through the trials with a stride of the number of trial slots in the
+// grid, so the host sizes the launch without reading the count.
+template <int MP>
+__global__ __launch_bounds__(256, 2) void k_proj_q_counted(const float2* __restrict__ R,
+                                                           const float4* __restrict__ Xg,
+                                                           float* __restrict__ P, int M, int64_t G,
+                                                           int nchunk, int chunks_per_wg, int nsplit,
+                                                           const int* __restrict__ count) {
+  using C = QCfg<MP>;
+  extern __shared__ __attribute__((aligned(16))) float4 sX[];
+  __shared__ float red[2][C::WR][C::NB * 16];
+  const int c0 = (blockIdx.x % nsplit) * chunks_per_wg;
+  const int c1 = min(c0 + chunks_per_wg, nchunk);
+  if (c0 >= c1) return;
+  const int64_t n = *count;
+  const int64_t stride = gridDim.x / nsplit;
+  for (int64_t b = blockIdx.x / nsplit; b < n; b += stride) {
+    proj_q_trial<MP>(R + b * int64_t(M) * M, Xg, P + b * G, M, G, c0, c1, sX, red);
+    __syncthreads();  // the next trial's first chunk reuses both LDS buffers
+  }
+}
+
+template <int MP>
+hipError_t launch_q(const Plan& p, int B, const float2* R, float* P, hipStream_t s, const int* count = nullptr,
+                    int expect = 0) {
   using C = QCfg<MP>;
   const int nchunk = int((p.Gb + C::NB - 1) / C::NB);  // the table holds Xblocks >= nchunk * NB
   // split the grid columns over several workgroups until there are enough of
   // them for the last round of workgroups on the CUs to be a small tail
   // (10 000 trials: two column halves, 10.58 -> 10.42 ms), keeping at least
-  // 32 chunks per workgroup to pay for building U in its registers
+  // 32 chunks per workgroup to pay for building U in its registers; a
+  // device-counted batch is split for the size the caller expects
+  const int Bs = count ? std::max(1, std::min(expect, B)) : B;
   int nsplit = 1;
-  while (int64_t(B) * nsplit < 16384 && 2 * nsplit * 32 <= nchunk) nsplit *= 2;
+  while (int64_t(Bs) * nsplit < 16384 && 2 * nsplit * 32 <= nchunk) nsplit *= 2;
   const int per = (nchunk + nsplit - 1) / nsplit;
   nsplit = (nchunk + per - 1) / per;
-  const int64_t nblk = int64_t(B) * nsplit;
+  const int64_t nblk = int64_t(count ? Bs : B) * nsplit;
   if (nblk > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_proj_q<MP>), dim3(unsigned(nblk)), dim3(256), 2 * C::CH4 * sizeof(float4), s, R,
-                     reinterpret_cast<const float4*>(p.d_X), P, p.M, p.G, nchunk, per, nsplit);
+  const size_t lds = 2 * C::CH4 * sizeof(float4);
+  if (count)
+    hipLaunchKernelGGL((k_proj_q_counted<MP>), dim3(unsigned(nblk)), dim3(256), lds, s, R,
+                       reinterpret_cast<const float4*>(p.d_X), P, p.M, p.G, nchunk, per, nsplit, count);
+  else
+    hipLaunchKernelGGL((k_proj_q<MP>), dim3(unsigned(nblk)), dim3(256), lds, s, R,
+                       reinterpret_cast<const float4*>(p.d_X), P, p.M, p.G, nchunk, per, nsplit);
   return hipGetLastError();
 }
 
@@ -121,6 +163,17 @@ hipError_t launch_spectrum_mfma(const Plan& p, int B, const float2* R, float* P,
     case 16: return launch_q<16>(p, B, R, P, s);
     case 32: return launch_q<32>(p, B, R, P, s);
     case 64: return launch_q<64>(p, B, R, P, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_spectrum_mfma_counted(const Plan& p, int cap, const int* count, int expect, const float2* R,
+                                        float* P, hipStream_t s) {
+  switch (p.Mp) {
+    case 8: return launch_q<8>(p, cap, R, P, s, count, expect);
+    case 16: return launch_q<16>(p, cap, R, P, s, count, expect);
+    case 32: return launch_q<32>(p, cap, R, P, s, count, expect);
+    case 64: return launch_q<64>(p, cap, R, P, s, count, expect);
     default: return hipErrorInvalidValue;
   }
 }

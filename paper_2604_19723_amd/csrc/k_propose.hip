@@ -17,6 +17,8 @@
 #include <climits>
 
 #include "proj_common.h"
+#include <algorithm>
+
 #include "propose.h"
 
 namespace ba {
@@ -237,12 +239,15 @@ __global__ void k_scatter(const int* __restrict__ list, const int* __restrict__ 
   ref[b * K + k] = ref_c[int64_t(i) * K + k];
 }
 
-// gather the covariances of the fallback trials into a compact batch
-__global__ void k_gather_r(const int* __restrict__ list, const float2* __restrict__ R, float2* __restrict__ Rc,
-                           int M) {
-  const int i = blockIdx.x;
-  const int64_t b = list[i];
-  for (int e = threadIdx.x; e < M * M; e += 256) Rc[int64_t(i) * M * M + e] = R[b * M * M + e];
+// gather the covariances of the *count fallback trials into a compact batch
+// (workgroups step through the list with the grid's stride)
+__global__ void k_gather_r(const int* __restrict__ list, const int* __restrict__ count,
+                           const float2* __restrict__ R, float2* __restrict__ Rc, int M) {
+  const int n = *count;
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const int64_t b = list[i];
+    for (int e = threadIdx.x; e < M * M; e += 256) Rc[int64_t(i) * M * M + e] = R[b * M * M + e];
+  }
 }
 
 __global__ void k_zero_count(int* count) {
@@ -283,8 +288,9 @@ hipError_t launch_zero_count(int* count, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_gather_r(const int* list, int n, const float2* R, float2* Rc, int M, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather_r, dim3(unsigned(n)), dim3(256), 0, s, list, R, Rc, M);
+hipError_t launch_gather_r(const int* list, const int* count, int n, const float2* R, float2* Rc, int M,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_r, dim3(unsigned(std::min(n, 2048))), dim3(256), 0, s, list, count, R, Rc, M);
   return hipGetLastError();
 }
 

@@ -73,8 +73,10 @@ ba_status ba_propose_refine(ba_plan plan, ba_mlp net, int32_t n_trials, const vo
   if (half_window < 1 || half_window > kMaxHalfWindow) return p_arg(fn, "half_window must be in [1, 100]");
   if (!(tau >= 0.f && tau <= 1.f)) return p_arg(fn, "tau must be in [0, 1]");
   if (n_trials < 0) return p_arg(fn, "n_trials >= 0 required");
-  if (n_fallback) *n_fallback = 0;
-  if (n_trials == 0) return BA_OK;
+  if (n_trials == 0) {
+    const hipError_t e0 = n_fallback ? launch_zero_count(n_fallback, static_cast<hipStream_t>(stream)) : hipSuccess;
+    return e0 == hipSuccess ? BA_OK : p_dev(fn, e0);
+  }
   if (!R || !idx || !val || !refined || !fell_back) return p_arg(fn, "null buffer");
   const Layout L = layout(p, n_trials, dout, k);
   if (!workspace || workspace_bytes < L.total) return p_arg(fn, "workspace smaller than ba_propose_workspace_size");
@@ -100,22 +102,24 @@ ba_status ba_propose_refine(ba_plan plan, ba_mlp net, int32_t n_trials, const vo
                  half_window, th0, step, tau, idx, val, refined, fell_back, list, count};
     e = launch_window(a, p.Mp, n_trials, s);
   }
-  int nf = 0;
-  if (e == hipSuccess) e = hipMemcpyAsync(&nf, count, sizeof(int), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e == hipSuccess && nf > 0) {
+  // full-grid fallback for the trials the window kernel listed: every launch
+  // is sized for the whole batch and reads the list's length on the device,
+  // so nothing here waits for the device
+  if (e == hipSuccess) {
     float2* Rc = reinterpret_cast<float2*>(ws + L.rc);
     float* Pc = reinterpret_cast<float*>(ws + L.pc);
     int* ic = reinterpret_cast<int*>(ws + L.ic);
     float* vc = reinterpret_cast<float*>(ws + L.vc);
     double* rc = reinterpret_cast<double*>(ws + L.refc);
-    e = launch_gather_r(list, nf, static_cast<const float2*>(R), Rc, p.M, s);
-    if (e == hipSuccess) e = launch_spectrum(p, nf, Rc, Pc, nullptr, s);
-    if (e == hipSuccess) e = launch_peaks(p, nf, Pc, k, ic, vc, rc, s);
-    if (e == hipSuccess) e = launch_scatter(list, count, nf, k, ic, vc, rc, idx, val, refined, s);
+    e = launch_gather_r(list, count, n_trials, static_cast<const float2*>(R), Rc, p.M, s);
+    // the projection's launch is shaped for a fallback batch of up to 1024
+    // trials at a time (larger ones loop)
+    if (e == hipSuccess) e = launch_spectrum_mfma_counted(p, n_trials, count, 1024, Rc, Pc, s);
+    if (e == hipSuccess) e = launch_peaks(p, n_trials, Pc, k, ic, vc, rc, s, count);
+    if (e == hipSuccess) e = launch_scatter(list, count, n_trials, k, ic, vc, rc, idx, val, refined, s);
+    if (e == hipSuccess && n_fallback) e = hipMemcpyAsync(n_fallback, count, sizeof(int), hipMemcpyDeviceToDevice, s);
   }
   if (e != hipSuccess) return p_dev(fn, e);
-  if (n_fallback) *n_fallback = nf;
   return BA_OK;
 }
 

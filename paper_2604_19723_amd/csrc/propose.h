@@ -31,7 +31,9 @@ __host__ __device__ inline int window_blocks(int hw) { return (2 * hw) / 16 + 2;
 size_t window_lds_bytes(int Mp, int hw);
 hipError_t launch_window(const WindowArgs& a, int Mp, int B, hipStream_t s);
 hipError_t launch_zero_count(int* count, hipStream_t s);
-hipError_t launch_gather_r(const int* list, int n, const float2* R, float2* Rc, int M, hipStream_t s);
+// n: the most trials the list can hold; *count (on the device) of them are used
+hipError_t launch_gather_r(const int* list, const int* count, int n, const float2* R, float2* Rc, int M,
+                           hipStream_t s);
 hipError_t launch_scatter(const int* list, const int* count, int n, int K, const int* idx_c, const float* val_c,
                           const double* ref_c, int* idx, float* val, double* ref, hipStream_t s);
 

@@ -160,18 +160,20 @@ def evaluate(plan, net, ts, taus, device, hw=50, steps=1, warmup=1):
     fell = torch.empty(n, dtype=torch.uint8, device=device)
     ws = torch.empty(bb.ba_propose_workspace_size(plan, n, net.dims[-1], K), dtype=torch.uint8, device=device)
     res = []
+    nfb = torch.zeros(1, dtype=torch.int32, device=device)
     for tau in taus:
         def learned():
             bb.ba_covariance(plan, n, T, Y, R)
-            return bb.ba_propose_refine(plan, net, n, R, K, hw, tau, li, lv, lr_, fell, ws)
+            bb.ba_propose_refine(plan, net, n, R, K, hw, tau, li, lv, lr_, fell, ws, n_fallback=nfb)
         for _ in range(max(warmup, 1)):
             learned()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            nf = learned()
+            learned()
         torch.cuda.synchronize()
         t_l = (time.perf_counter() - t0) / steps
+        nf = int(nfb.item())
         idx_l, ref_l = li.cpu().numpy(), lr_.cpu().numpy()
         r = _rmse(ts, idx_l, ref_l)
         cmp = metrics.compare_accuracy(_trial_errors(ts, idx_l, ref_l), err_plain)

@@ -89,7 +89,9 @@ def propose(plan, net, R, K, hw, tau):
     ref = torch.empty((B, K), dtype=torch.float64, device=DEV)
     fell = torch.empty(B, dtype=torch.uint8, device=DEV)
     ws = torch.empty(bb.ba_propose_workspace_size(plan, B, net.dims[-1], K), dtype=torch.uint8, device=DEV)
-    nf = bb.ba_propose_refine(plan, net, B, R, K, hw, tau, idx, val, ref, fell, ws)
+    nfb = torch.full((1,), -1, dtype=torch.int32, device=DEV)
+    bb.ba_propose_refine(plan, net, B, R, K, hw, tau, idx, val, ref, fell, ws, n_fallback=nfb)
+    nf = int(nfb.item())
     torch.cuda.synchronize()
     return dict(idx=idx.cpu().numpy(), val=val.cpu().numpy(), ref=ref.cpu().numpy(), fell=fell.cpu().numpy(),
                 nf=nf)
@@ -194,7 +196,9 @@ def run_both(Y, u, tau, hw=50):
     ref = torch.empty((B, 4), dtype=torch.float64, device=DEV)
     fell = torch.empty(B, dtype=torch.uint8, device=DEV)
     ws = torch.empty(bb.ba_propose_workspace_size(plan, B, 4, 4), dtype=torch.uint8, device=DEV)
-    nf = bb.ba_propose_refine(plan, net, B, R, 4, hw, tau, idx, val, ref, fell, ws)
+    nfb = torch.full((1,), -1, dtype=torch.int32, device=DEV)
+    bb.ba_propose_refine(plan, net, B, R, 4, hw, tau, idx, val, ref, fell, ws, n_fallback=nfb)
+    nf = int(nfb.item())
     torch.cuda.synchronize()
     out = dict(idx=idx.cpu().numpy(), val=val.cpu().numpy(), ref=ref.cpu().numpy(),
                fell=fell.cpu().numpy(), nf=nf,
@@ -260,7 +264,9 @@ def test_windows_other_sizes_and_edges(M, hw, deg):
     ref = torch.empty((B, K), dtype=torch.float64, device=DEV)
     fell = torch.empty(B, dtype=torch.uint8, device=DEV)
     ws = torch.empty(bb.ba_propose_workspace_size(plan, B, K, K), dtype=torch.uint8, device=DEV)
-    nf = bb.ba_propose_refine(plan, net, B, R, K, hw, 0.0, idx, val, ref, fell, ws)
+    nfb = torch.full((1,), -1, dtype=torch.int32, device=DEV)
+    bb.ba_propose_refine(plan, net, B, R, K, hw, 0.0, idx, val, ref, fell, ws, n_fallback=nfb)
+    nf = int(nfb.item())
     torch.cuda.synchronize()
     fell = fell.cpu().numpy()
     assert nf == int(fell.sum())
