@@ -323,7 +323,8 @@ def bench_proposal(args, workers):
 def bench_coherent(args, workers):
     """The paper's own proposal cost: J = 4 URAs (4 x 4, 10 frequency bins),
     coherent over the arrays, 131 072 SFV candidates; one step is the trial
-    rows, the fused GEMM + |.|^2 and the proposal moments for 1024 trials."""
+    rows, the fused GEMM + |.|^2, the proposal moments and 1024 birth
+    particles per trial for 1024 trials."""
     from paper_2604_19723_amd import workload as wl
     B = args.trials if args.trials != 10000 else 1024
     t = time.perf_counter()
@@ -341,7 +342,14 @@ def bench_coherent(args, workers):
     P = torch.empty((B, G), dtype=torch.float32, device=dev)
     mc = torch.empty((B, 12), dtype=torch.float64, device=dev)
     ws = bb.coherent_workspace_for(h, B, dev)
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    # birth particles of the new feature: 1024 per trial from N(mu, C) in the partition box
+    N = 1024
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(SEED_PROPOSAL)
+    zs = torch.randn((B, N, 3), dtype=torch.float64, device=dev, generator=gen)
+    part = torch.empty((B, N, 3), dtype=torch.float64, device=dev)
+    wgt = torch.empty((B, N), dtype=torch.float64, device=dev)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
 
     def step(ev=None):
         if ev is not None:
@@ -350,6 +358,11 @@ def bench_coherent(args, workers):
         if ev is not None:
             ev[1].record()
         bb.ba_coherent_moments(h, B, P, mc, ws)
+        if ev is not None:
+            ev[2].record()
+        bb.ba_coherent_sample(h, B, mc, N, zs, part, wgt)
+        if ev is not None:
+            ev[3].record()
 
     for _ in range(args.warmup):
         step()
@@ -359,8 +372,13 @@ def bench_coherent(args, workers):
         step(evs[k])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    k_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
-    log("timed %d steps: %.3f ms/step, spectrum %.3f ms" % (args.steps, dt / args.steps * 1e3, k_ms))
+    k_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    mom_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    samp_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
+    log("timed %d steps: %.3f ms/step, spectrum %.3f ms, moments %.3f ms, sampling %.3f ms" % (
+        args.steps, dt / args.steps * 1e3, k_ms, mom_ms, samp_ms))
+    wh = wgt.cpu().numpy()
+    ess = 1.0 / np.nansum(wh * wh, axis=1)
     flops = 8.0 * K * G * B          # complex inner products of length J N_z
     achieved = flops / (k_ms * 1e-3) / 1e12
     mu = mc[:, :3].cpu().numpy()
@@ -389,6 +407,9 @@ def bench_coherent(args, workers):
         "cpu_baseline": None,
         "grid_points_trials_per_s": value * G,
         "argmax_distance_m": {"median": float(np.median(err)), "p90": float(np.percentile(err, 90))},
+        "birth_particles": {"per_trial": N, "moments_ms": mom_ms, "sampling_ms": samp_ms,
+                            "sampling_gb_s": B * N * (3 * 8 * 2 + 8) / (samp_ms * 1e-3) / 1e9,
+                            "effective_sample_size_median": float(np.nanmedian(ess))},
         "spot_parity_normwise_max": max(spot),
     }
     h.close()

@@ -469,12 +469,29 @@ ba_status ba_coherent_spectrum(ba_coherent h, int32_t n_trials, const void* Z, f
 /*
  * Proposal moments over the candidates (Sec. IV-D.2): weights P / sum P, mean
  * = the candidate of maximum cost (lowest index among equal maxima),
- * covariance = weighted second central moment, in metres, evaluated in one
- * FP64 pass as S2/S0 - mu m^T - m mu^T + mu mu^T (m the weighted mean).
+ * covariance = weighted second central moment, in metres, accumulated in FP64
+ * about the maximum (sum P (x - mu)(x - mu)^T / sum P).
  *   mu_cov  dev double [B][3 + 9].
  */
 ba_status ba_coherent_moments(ba_coherent h, int32_t n_trials, const float* P, double* mu_cov, void* workspace,
                               size_t workspace_bytes, void* stream);
+
+/*
+ * Birth particles of the new feature's SFV position (Sec. IV-D.2 proposal
+ * density, and the birth-particle weights of Sec. IV-D): particle n of trial
+ * b is mu + L z[b][n] with C = L L^T from ba_coherent_moments, and its
+ * importance weight is proportional to the indicator of the partition over
+ * the proposal density (a target uniform on the partition), normalised to
+ * sum to one per trial. The partition is the axis-aligned box spanned by the
+ * plan's candidates (candidates are drawn from the partition).
+ *   mu_cov     dev double [B][12] (ba_coherent_moments).
+ *   z          dev double [B][N][3]: standard normal draws, supplied by the caller.
+ *   particles  dev double [B][N][3] (m); weights dev double [B][N].
+ * A covariance that is not positive definite gives particles = mu and equal
+ * weights; a trial with no particle inside the box gets NaN weights.
+ */
+ba_status ba_coherent_sample(ba_coherent h, int32_t n_trials, const double* mu_cov, int32_t n_particles,
+                             const double* z, double* particles, double* weights, void* stream);
 
 
 /* ---------------------------------------------------------------- particle update messages

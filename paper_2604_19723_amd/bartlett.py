@@ -106,6 +106,7 @@ _SIGS = {
     "ba_coherent_workspace_size": (_i32, [_vp, _i32, C.POINTER(_sz)]),
     "ba_coherent_spectrum": (_i32, [_vp, _i32, _vp, _vp, _vp, _sz, _vp]),
     "ba_coherent_moments": (_i32, [_vp, _i32, _vp, _vp, _vp, _sz, _vp]),
+    "ba_coherent_sample": (_i32, [_vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp]),
     "ba_residual_covariance": (_i32, [_vp, _i32, _vp, _i32, _vp, _vp, _vp]),
     "ba_sequential_workspace_size": (_i32, [_vp, _i32, C.POINTER(_sz)]),
     "ba_sequential_peaks": (_i32, [_vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
@@ -689,6 +690,15 @@ def ba_coherent_moments(h: Coherent, n_trials, P, mu_cov, workspace, stream=None
     _check("ba_coherent_moments", lib().ba_coherent_moments(
         h.handle, n_trials, _dev(P, "f32", n_trials * h.n_cand, "P"), _dev(mu_cov, "f64", n_trials * 12, "mu_cov"),
         ws, nbytes, _stream(stream)))
+
+
+def ba_coherent_sample(h: Coherent, n_trials, mu_cov, n_particles, z, particles, weights, stream=None):
+    """Birth particles in the candidates' bounding box from N(mu, C)."""
+    N = n_particles
+    _check("ba_coherent_sample", lib().ba_coherent_sample(
+        h.handle, n_trials, _dev(mu_cov, "f64", n_trials * 12, "mu_cov"), N,
+        _dev(z, "f64", n_trials * N * 3, "z"), _dev(particles, "f64", n_trials * N * 3, "particles"),
+        _dev(weights, "f64", n_trials * N, "weights"), _stream(stream)))
 
 
 def coherent_workspace_for(h: Coherent, n_trials, device="cuda"):

@@ -3,6 +3,7 @@
 // Sec. II-A and the array response of Sec. II-B).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -18,6 +19,7 @@ struct ba_coherent_s {
   int64_t G = 0, ctiles = 0;
   double* d_geom = nullptr;  // pa [J][3], rot [J][9], mt [3], freq [nf], py [ny], pz [nz]
   double* d_cand = nullptr;  // [G][3]
+  double box_lo[3] = {0.0, 0.0, 0.0}, box_hi[3] = {0.0, 0.0, 0.0};  // the candidates' bounding box (m)
   float* d_X = nullptr;      // [ctiles * 8 blocks][Kp * 16] in MFMA B-fragment order
   CohGeom geo{};
 };
@@ -80,6 +82,12 @@ ba_status ba_coherent_create(ba_coherent* out, int32_t n_arrays, const double* p
   h->fc = fc;
   h->G = n_cand;
   h->ctiles = (n_cand + 127) / 128;
+  for (int a = 0; a < 3; ++a) h->box_lo[a] = h->box_hi[a] = candidates[a];
+  for (int64_t g = 1; g < n_cand; ++g)
+    for (int a = 0; a < 3; ++a) {
+      h->box_lo[a] = std::min(h->box_lo[a], candidates[3 * g + a]);
+      h->box_hi[a] = std::max(h->box_hi[a], candidates[3 * g + a]);
+    }
   // geometry: element positions at half a wavelength, centred; baseband
   // frequencies equally spaced over the bandwidth and centred on zero
   const double lam = kCLight / fc;
@@ -180,6 +188,24 @@ ba_status ba_coherent_moments(ba_coherent h, int32_t n_trials, const float* P, d
   if (reinterpret_cast<uintptr_t>(workspace) & 255) return c_arg(fn, "workspace must be 256-byte aligned");
   const hipError_t e = launch_point_moments(n_trials, P, h->G, h->d_cand, mu_cov, workspace,
                                             static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? BA_OK : c_dev(fn, e);
+}
+
+ba_status ba_coherent_sample(ba_coherent h, int32_t n_trials, const double* mu_cov, int32_t n_particles,
+                             const double* z, double* particles, double* weights, void* stream) {
+  static const char* fn = "ba_coherent_sample";
+  if (!h) return c_arg(fn, "handle is NULL");
+  if (n_trials < 0 || n_particles < 0) return c_arg(fn, "n_trials >= 0 and n_particles >= 0 required");
+  if (n_trials == 0 || n_particles == 0) return BA_OK;
+  if (!mu_cov || !z || !particles || !weights) return c_arg(fn, "null buffer");
+  ProposalRegion reg{};
+  for (int a = 0; a < 3; ++a) {
+    reg.lo[a] = h->box_lo[a];
+    reg.hi[a] = h->box_hi[a];
+    reg.period[a] = 0.0;
+  }
+  const hipError_t e = launch_proposal_sample(n_trials, mu_cov, 3, n_particles, z, reg, particles, weights,
+                                              static_cast<hipStream_t>(stream));
   return e == hipSuccess ? BA_OK : c_dev(fn, e);
 }
 

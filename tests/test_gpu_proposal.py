@@ -91,3 +91,59 @@ def test_direction_grids_are_unsupported():
             bb.ba_proposal_sample(plan, 1, mc, 2, z, part, w)
     finally:
         plan.close()
+
+
+@pytest.mark.parametrize("B,G,N", [(6, 4096, 2048), (2, 131072, 1000)])
+def test_sfv_birth_particles_match_oracle(B, G, N):
+    # the paper's own proposal: moments over SFV position candidates in R^3,
+    # particles from N(mu, C) weighted by the partition box over the density
+    cs = wl.coherent_config(B, G)
+    with bb.ba_coherent_create(cs.pa_pos, cs.pa_rot, cs.n_y, cs.n_z, cs.n_f, cs.fc, cs.bandwidth, cs.p_mt,
+                               cs.candidates) as h:
+        P = torch.empty((B, G), dtype=torch.float32, device=DEV)
+        ws = bb.coherent_workspace_for(h, B, DEV)
+        bb.ba_coherent_spectrum(h, B, torch.from_numpy(np.ascontiguousarray(cs.Z)).to(DEV), P, ws)
+        mc = torch.empty((B, 12), dtype=torch.float64, device=DEV)
+        bb.ba_coherent_moments(h, B, P, mc, ws)
+        z = np.random.default_rng(5).standard_normal((B, N, 3))
+        part = torch.empty((B, N, 3), dtype=torch.float64, device=DEV)
+        w = torch.empty((B, N), dtype=torch.float64, device=DEV)
+        bb.ba_coherent_sample(h, B, mc, N, torch.from_numpy(z).to(DEV), part, w)
+        torch.cuda.synchronize()
+        mc, part, w = mc.cpu().numpy(), part.cpu().numpy(), w.cpu().numpy()
+    lo, hi = cs.candidates.min(axis=0), cs.candidates.max(axis=0)
+    n_in = 0
+    for b in range(B):
+        mu, C = mc[b, :3], mc[b, 3:].reshape(3, 3)
+        p_ref, w_ref = op.sample_and_weight(mu, C, z[b], lo, hi, np.zeros(3, bool))
+        np.testing.assert_allclose(part[b], p_ref, rtol=1e-13, atol=1e-13)
+        np.testing.assert_allclose(w[b], w_ref, rtol=1e-10, atol=1e-300, equal_nan=True)
+        n_in += int(np.sum(w[b] > 0))
+        assert np.isclose(np.sum(w[b]), 1.0)
+    assert n_in > 0
+
+
+def test_sfv_birth_degenerate_and_empty():
+    cs = wl.coherent_config(1, 64)
+    lo, hi = cs.candidates.min(axis=0), cs.candidates.max(axis=0)
+    mc = np.zeros((3, 12))
+    mc[0, :3] = cs.candidates[0]                        # C = 0: degenerate, particles at mu
+    mc[1, :3] = hi + 50.0                               # far outside the box: no particle inside
+    mc[1, 3:] = np.eye(3).reshape(-1) * 1e-4
+    mc[2, :3] = cs.candidates[1]
+    mc[2, 3:] = np.array([[1.0, 2.0, 0], [2.0, 1.0, 0], [0, 0, 1.0]]).reshape(-1)  # indefinite
+    z = np.random.default_rng(2).standard_normal((3, 100, 3))
+    with bb.ba_coherent_create(cs.pa_pos, cs.pa_rot, cs.n_y, cs.n_z, cs.n_f, cs.fc, cs.bandwidth, cs.p_mt,
+                               cs.candidates) as h:
+        part = torch.empty((3, 100, 3), dtype=torch.float64, device=DEV)
+        w = torch.empty((3, 100), dtype=torch.float64, device=DEV)
+        bb.ba_coherent_sample(h, 3, torch.from_numpy(mc).to(DEV), 100, torch.from_numpy(z).to(DEV), part, w)
+        torch.cuda.synchronize()
+        part, w = part.cpu().numpy(), w.cpu().numpy()
+    for b in range(3):
+        p_ref, w_ref = op.sample_and_weight(mc[b, :3], mc[b, 3:].reshape(3, 3), z[b], lo, hi, np.zeros(3, bool))
+        np.testing.assert_allclose(part[b], p_ref, rtol=1e-13, atol=1e-13)
+        np.testing.assert_allclose(w[b], w_ref, rtol=1e-10, atol=1e-300, equal_nan=True)
+    assert np.all(part[0] == cs.candidates[0]) and np.all(w[0] == 1.0 / 100)
+    assert np.all(np.isnan(w[1]))
+    assert np.all(part[2] == cs.candidates[1])
