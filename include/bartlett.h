@@ -255,7 +255,8 @@ typedef struct ba_ragged_s* ba_ragged;
  * Bartlett cost unchanged). Builds per-size-class steering tables, orders the
  * trials longest first, and captures one persistent fused launch
  * (covariance -> spectrum -> peaks per trial, trials taken from an atomic
- * ticket) in a HIP graph. Buffers are bound here; ba_ragged_launch replays.
+ * ticket) in a HIP graph. Buffers are bound here (ba_ragged_bind rebinds
+ * them); ba_ragged_launch replays.
  *   plan        FP32 plan, G <= 16384, 1-D or 2-D grid.
  *   desc        host, n_trials entries (copied).
  *   kmax        1..8: output row width; entries past a trial's k are -1 / NaN.
@@ -272,6 +273,18 @@ ba_status ba_ragged_create(ba_ragged* out, ba_plan plan, int32_t n_trials, const
 /* Replay the captured launch on a stream. The plan and the bound buffers must
  * stay alive; replays on one handle must not overlap. */
 ba_status ba_ragged_launch(ba_ragged r, void* stream);
+
+/*
+ * Bind other buffers to the handle for the replays that follow on `stream`
+ * (same meaning and sizes as in ba_ragged_create; the trials' layout in the
+ * pool is the one given at creation). The captured launch reads its buffer
+ * addresses from device memory, so the new buffers take effect in stream
+ * order without re-capturing: a replay already enqueued keeps the old ones.
+ *   pool_elems  must cover every trial's block.
+ * Errors: BA_ERR_ARG, BA_ERR_DEVICE.
+ */
+ba_status ba_ragged_bind(ba_ragged r, const void* Y_pool, int64_t pool_elems, float* P, int32_t* idx, float* val,
+                         double* refined, void* stream);
 
 /*
  * Autotune on this batch: per size class, the MFMA tile (waves along rows vs

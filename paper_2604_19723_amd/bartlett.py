@@ -81,6 +81,7 @@ _SIGS = {
     "ba_run_noalloc": (_i32, [_vp, _i32, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp]),
     "ba_ragged_create": (_i32, [C.POINTER(_vp), _vp, _i32, _vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp]),
     "ba_ragged_launch": (_i32, [_vp, _vp]),
+    "ba_ragged_bind": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp]),
     "ba_ragged_autotune": (_i32, [_vp, C.c_char_p, _i32, _i32]),
     "ba_ragged_routes": (_i32, [_vp, _vp]),
     "ba_ragged_config": (_i32, [_vp, _vp]),
@@ -436,6 +437,17 @@ def ba_ragged_create(plan: Plan, desc, kmax, Y_pool, P, idx, val, refined=None) 
         _dev(val, "f32", B * kmax, "val"),
         _dev(refined, "f64", B * kmax * plan.ndim, "refined", optional=True)))
     return Ragged(h, plan, B, kmax, (plan, Y_pool, P, idx, val, refined))
+
+
+def ba_ragged_bind(r: Ragged, Y_pool, P, idx, val, refined=None, stream=None):
+    """Retarget the captured launch at other buffers (stream-ordered)."""
+    B, G, kmax, nd = r.n_trials, r.plan.G, r.kmax, r.plan.ndim
+    _check("ba_ragged_bind", lib().ba_ragged_bind(
+        r.handle, _dev(Y_pool, "c64", 1, "Y_pool"), Y_pool.numel(),
+        _dev(P, "f32", B * G, "P", optional=True), _dev(idx, "i32", B * kmax, "idx"),
+        _dev(val, "f32", B * kmax, "val"), _dev(refined, "f64", B * kmax * nd, "refined", optional=True),
+        _stream(stream)))
+    r._keep = (r._keep, (Y_pool, P, idx, val, refined))   # earlier buffers may still be in use
 
 
 def ba_ragged_launch(r: Ragged, stream=None):

@@ -603,6 +603,16 @@ __global__ void k_ragged_reset(int32_t* counter) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
 }
 
+__global__ void k_ragged_bind(RArgs* args, const float2* Y, float* P, int32_t* idx, float* val, double* refined) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    args->Y = Y;
+    args->P = P;
+    args->idx = idx;
+    args->val = val;
+    args->refined = refined;
+  }
+}
+
 }  // namespace
 
 int ragged_blocks_per_chunk(int cls) {
@@ -622,6 +632,12 @@ hipError_t ragged_prepare() {
 
 hipError_t launch_ragged(const RArgs* d_args, int n_wg, hipStream_t s) {
   hipLaunchKernelGGL(k_ragged, dim3(unsigned(n_wg)), dim3(kThreads), kRaggedLds, s, d_args);
+  return hipGetLastError();
+}
+
+hipError_t launch_ragged_bind(RArgs* d_args, const float2* Y, float* P, int32_t* idx, float* val, double* refined,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_ragged_bind, dim3(1), dim3(64), 0, s, d_args, Y, P, idx, val, refined);
   return hipGetLastError();
 }
 

@@ -27,6 +27,7 @@ struct Ragged {
   std::vector<int> cls, tuned_route;   // per trial
   int kmax = 1;
   const float2* Y = nullptr;
+  int64_t pool_need = 0;               // complex elements the pool must hold
   float* P = nullptr;
   int32_t* idx = nullptr;
   float* val = nullptr;
@@ -262,6 +263,8 @@ ba_status ba_ragged_create(ba_ragged* out, ba_plan plan, int32_t n_trials, const
   r->desc.assign(desc, desc + n_trials);
   r->kmax = kmax;
   r->Y = static_cast<const float2*>(Y_pool);
+  for (int32_t i = 0; i < n_trials; ++i)
+    r->pool_need = std::max(r->pool_need, desc[i].y_offset + int64_t(desc[i].n_elem) * desc[i].n_snap);
   r->P = P;
   r->idx = idx;
   r->val = val;
@@ -306,6 +309,23 @@ ba_status ba_ragged_create(ba_ragged* out, ba_plan plan, int32_t n_trials, const
   }
   *out = r;
   return BA_OK;
+}
+
+ba_status ba_ragged_bind(ba_ragged r, const void* Y_pool, int64_t pool_elems, float* P, int32_t* idx, float* val,
+                         double* refined, void* stream) {
+  static const char* fn = "ba_ragged_bind";
+  if (!r) return rg_arg(fn, "handle is NULL");
+  if (!Y_pool || pool_elems < r->pool_need) return rg_arg(fn, "Y_pool is NULL or smaller than the trials' blocks");
+  if (!idx || !val) return rg_arg(fn, "idx and val are required");
+  r->Y = static_cast<const float2*>(Y_pool);
+  r->P = P;
+  r->idx = idx;
+  r->val = val;
+  r->refined = refined;
+  // the captured launch reads its arguments from device memory: rewriting
+  // the buffer fields there (in stream order) retargets every later replay
+  const hipError_t e = launch_ragged_bind(r->d_args, r->Y, P, idx, val, refined, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? BA_OK : rg_dev(fn, e);
 }
 
 ba_status ba_ragged_launch(ba_ragged r, void* stream) {

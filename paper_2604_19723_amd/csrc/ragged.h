@@ -54,5 +54,8 @@ int ragged_blocks_per_chunk(int cls);
 hipError_t ragged_prepare();
 hipError_t launch_ragged(const RArgs* d_args, int n_wg, hipStream_t s);
 hipError_t launch_ragged_reset(int32_t* counter, hipStream_t s);
+// rewrite the buffer fields of the device-side arguments (stream-ordered)
+hipError_t launch_ragged_bind(RArgs* d_args, const float2* Y, float* P, int32_t* idx, float* val, double* refined,
+                              hipStream_t s);
 
 }  // namespace ba

@@ -138,3 +138,44 @@ def test_autotune_keeps_parity_and_uses_cache(tmp_path):
     assert "|wr|" in text
     o2 = run(rs, autotune=cache)          # second run reads the cache
     assert np.array_equal(o["cfg"], o2["cfg"])
+
+
+def test_rebinding_buffers_retargets_the_graph():
+    rs = wl.config4(160, first_trial=7000)
+    B, G = rs.n_trials, len(rs.grid)
+    plan = ragged_plan(G)
+    YA = torch.from_numpy(rs.pool_c64()).to(DEV)
+    gen = torch.Generator(device=DEV)
+    gen.manual_seed(3)
+    YB = torch.randn(YA.numel(), dtype=torch.complex64, device=DEV, generator=gen)
+
+    def outs():
+        return (torch.full((B, G), -1.0, dtype=torch.float32, device=DEV),
+                torch.empty((B, KMAX), dtype=torch.int32, device=DEV),
+                torch.empty((B, KMAX), dtype=torch.float32, device=DEV),
+                torch.empty((B, KMAX, 1), dtype=torch.float64, device=DEV))
+
+    desc = bb.ragged_descriptors(rs)
+    oa, ob_ = outs(), outs()
+    with bb.ba_ragged_create(plan, desc, KMAX, YA, *oa) as r:
+        bb.ba_ragged_launch(r)
+        bb.ba_ragged_bind(r, YB, *ob_)
+        bb.ba_ragged_launch(r)
+        torch.cuda.synchronize()
+        ra = [t.clone() for t in oa]
+        routes = bb.ba_ragged_routes(r)
+        with pytest.raises(bb.BartlettError):
+            bb.ba_ragged_bind(r, YA[:10], *outs())     # a pool that misses the trials' blocks
+    # the reference: a handle created on the second set of buffers
+    oref = outs()
+    with bb.ba_ragged_create(plan, desc, KMAX, YB, *oref) as r2:
+        bb.ba_ragged_launch(r2)
+        torch.cuda.synchronize()
+    plan.close()
+    ibits = {4: torch.int32, 8: torch.int64}
+    for a, b in zip(ob_, oref):
+        assert torch.equal(a.view(ibits[a.element_size()]), b.view(ibits[b.element_size()]))
+    # the first set holds the first launch's results: the oracle on pool A
+    o = dict(P=ra[0].cpu().numpy(), idx=ra[1].cpu().numpy(), val=ra[2].cpu().numpy(), ref=ra[3].cpu().numpy(),
+             routes=routes)
+    check(rs, o)
