@@ -145,20 +145,19 @@ __global__ __launch_bounds__(256, 2) void k_proj_qb(const float2* __restrict__ R
       for (int kc = 0; kc < NKC; ++kc) {
         const bf16x8 bh = __builtin_bit_cast(bf16x8, lds_frag(bx, (2 * kc) * 64 + lane));
         const bf16x8 bl = __builtin_bit_cast(bf16x8, lds_frag(bx, (2 * kc + 1) * 64 + lane));
+        // pass-major over the (trial, slot) accumulators: consecutive MFMAs
+        // write different accumulators
 #pragma unroll
-        for (int t = 0; t < NTW; ++t)
+        for (int pass = 0; pass < (PREC == BA_PREC_BF16X3 ? 3 : 1); ++pass)
 #pragma unroll
-          for (int j = 0; j < NSLOT; ++j) {
-            if (kc < slot_kc0(j)) continue;
-            const int f = slot_off(j) + kc - slot_kc0(j);
-            const bf16x8 vah = __builtin_bit_cast(bf16x8, ah[t][f]);
-            acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vah, bh, acc[t][j], 0, 0, 0);
-            if (PREC == BA_PREC_BF16X3) {
-              acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vah, bl, acc[t][j], 0, 0, 0);
-              acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, al[t][f]), bh,
-                                                                  acc[t][j], 0, 0, 0);
+          for (int t = 0; t < NTW; ++t)
+#pragma unroll
+            for (int j = 0; j < NSLOT; ++j) {
+              if (kc < slot_kc0(j)) continue;
+              const int f = slot_off(j) + kc - slot_kc0(j);
+              const bf16x8 va = __builtin_bit_cast(bf16x8, pass == 2 ? al[t][f] : ah[t][f]);
+              acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va, pass == 1 ? bl : bh, acc[t][j], 0, 0, 0);
             }
-          }
       }
       float part[NTW];
 #pragma unroll

@@ -160,6 +160,55 @@ __device__ __forceinline__ void fold_rows_bf16(float (&part)[kCB], const floatx4
   }
 }
 
+// One k-chunk of the split-precision kernel for the last N row-block slots
+// of a wave (those not past their diagonal chunk). For each column block the
+// passes go over all N slots in turn (hi x hi for every slot, then hi x lo,
+// then lo x hi), so consecutive MFMAs write different accumulators; the
+// fragments of column block c + 1 are read from LDS while block c is
+// multiplied.
+template <int N, int RBW, int PREC>
+__device__ __forceinline__ void chunk_bf16(floatx4 (&acc)[RBW][kCB], const uint4 (&ah)[RBW], const uint4 (&al)[RBW],
+                                           const uint4* __restrict__ sb, int lane) {
+  // column blocks in pairs: every pass goes over both blocks of the pair and
+  // all N slots, so even a single active slot has two independent chains
+  uint4 bh0 = lds_frag(sb, lane), bl0 = lds_frag(sb, 64 + lane);
+  uint4 bh1 = lds_frag(sb, 128 + lane), bl1 = lds_frag(sb, 192 + lane);
+#pragma unroll
+  for (int cp = 0; cp < kCB / 2; ++cp) {
+    const int c0 = 2 * cp, c1 = c0 + 1;
+    uint4 nh0 = bh0, nl0 = bl0, nh1 = bh1, nl1 = bl1;
+    if (cp + 1 < kCB / 2) {
+      nh0 = lds_frag(sb, (c0 + 2) * 128 + lane);
+      nl0 = lds_frag(sb, (c0 + 2) * 128 + 64 + lane);
+      nh1 = lds_frag(sb, (c1 + 2) * 128 + lane);
+      nl1 = lds_frag(sb, (c1 + 2) * 128 + 64 + lane);
+    }
+    const bf16x8 vh0 = __builtin_bit_cast(bf16x8, bh0), vl0 = __builtin_bit_cast(bf16x8, bl0);
+    const bf16x8 vh1 = __builtin_bit_cast(bf16x8, bh1), vl1 = __builtin_bit_cast(bf16x8, bl1);
+#pragma unroll
+    for (int r = RBW - N; r < RBW; ++r) {
+      acc[r][c0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ah[r]), vh0, acc[r][c0], 0, 0, 0);
+      acc[r][c1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ah[r]), vh1, acc[r][c1], 0, 0, 0);
+    }
+    if (PREC == BA_PREC_BF16X3) {
+#pragma unroll
+      for (int r = RBW - N; r < RBW; ++r) {
+        acc[r][c0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ah[r]), vl0, acc[r][c0], 0, 0, 0);
+        acc[r][c1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ah[r]), vl1, acc[r][c1], 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = RBW - N; r < RBW; ++r) {
+        acc[r][c0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, al[r]), vh0, acc[r][c0], 0, 0, 0);
+        acc[r][c1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, al[r]), vh1, acc[r][c1], 0, 0, 0);
+      }
+    }
+    bh0 = nh0;
+    bl0 = nl0;
+    bh1 = nh1;
+    bl1 = nl1;
+  }
+}
+
 template <int MP, int PREC>
 __global__ __launch_bounds__(64 * waves_for<PREC>(), 1) void k_proj_s(const void* __restrict__ Qin,
                                                 const float4* __restrict__ Xf,   // FP32 table (fragment order)
@@ -286,36 +335,22 @@ __global__ __launch_bounds__(64 * waves_for<PREC>(), 1) void k_proj_s(const void
           anl[r] = Qw[(int64_t(kc + 1) * NRB + wave + kWaves * r) * 128 + 64 + lane];
         }
       }
-      // slots r < first are past their diagonal chunk: their MFMAs are
-      // skipped by a uniform branch (one code path keeps the register budget
-      // of the dense kernel); the fragments of column block c + 1 are read
-      // while block c is multiplied
+      // slots r < first are past their diagonal chunk: the active ones are a
+      // suffix of the wave's slots, one code path per count (scalar switch)
       const int first = first_active(kc);
       const uint4* sb = sBd + buf * CHUNK16;
-      uint4 bh = lds_frag(sb, lane);
-      uint4 bl = lds_frag(sb, 64 + lane);
-#pragma unroll
-      for (int c = 0; c < kCB; ++c) {
-        uint4 nh = bh, nl = bl;
-        if (c + 1 < kCB) {
-          nh = lds_frag(sb, (c + 1) * 128 + lane);
-          nl = lds_frag(sb, (c + 1) * 128 + 64 + lane);
-        }
-        const bf16x8 vbh = __builtin_bit_cast(bf16x8, bh);
-        const bf16x8 vbl = __builtin_bit_cast(bf16x8, bl);
-#pragma unroll
-        for (int r = 0; r < RBW; ++r) {
-          if (r < first) continue;
-          const bf16x8 vah = __builtin_bit_cast(bf16x8, ah[r]);
-          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vah, vbh, acc[r][c], 0, 0, 0);
-          if (PREC == BA_PREC_BF16X3) {
-            const bf16x8 val = __builtin_bit_cast(bf16x8, al[r]);
-            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vah, vbl, acc[r][c], 0, 0, 0);
-            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(val, vbh, acc[r][c], 0, 0, 0);
-          }
-        }
-        bh = nh;
-        bl = nl;
+      switch (RBW - min(RBW, first)) {
+        case 0: break;
+        case 1: chunk_bf16<1, RBW, PREC>(acc, ah, al, sb, lane); break;
+        case 2:
+          if constexpr (RBW >= 2) chunk_bf16<2, RBW, PREC>(acc, ah, al, sb, lane);
+          break;
+        case 3:
+          if constexpr (RBW >= 3) chunk_bf16<3, RBW, PREC>(acc, ah, al, sb, lane);
+          break;
+        default:
+          if constexpr (RBW >= 4) chunk_bf16<4, RBW, PREC>(acc, ah, al, sb, lane);
+          break;
       }
 #pragma unroll
       for (int r = 0; r < RBW; ++r)
