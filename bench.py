@@ -437,7 +437,7 @@ def bench_ragged(args, workers):
     r = bb.ba_ragged_create(plan, bb.ragged_descriptors(rs), kmax, Y, P, idx, val, ref)
     if not args.no_autotune:
         t = time.perf_counter()
-        bb.ba_ragged_autotune(r, "/tmp/bartlett_ragged_tune.txt", repeats=2, max_probe=256)
+        bb.ba_ragged_autotune(r, None, repeats=2, max_probe=256)   # tuned afresh on every run
         log("autotuned in %.1f s: waves along rows per class %s" % (time.perf_counter() - t, bb.ba_ragged_config(r)))
     routes = bb.ba_ragged_routes(r)
     for _ in range(args.warmup):

@@ -73,23 +73,27 @@ __device__ __forceinline__ void covariance_lds(const float2* __restrict__ Yb, in
   const int nbm = (M + BM - 1) / BM, nbn = (M + BN - 1) / BN;
   int n_bp = 0;
   for (int bn = 0; bn < nbn; ++bn) n_bp += min(nbm - 1, (BN * bn + BN - 1) / BM) + 1;
-  // thread groups split the snapshots when the matrix is small; their partial
-  // sums must fit between R and the snapshot staging area
+  // thread groups split the snapshots when the matrix is small (at most 32
+  // groups, and no more than there are snapshots); every group's partial sums
+  // go to LDS between R and the snapshot staging area, and the combine is
+  // spread over all threads, one output value each, summed in group order
+  // (deterministic)
   const int part_bytes = n_bp * BM * BN * 8;
   const int room = (kOffY - M * M * 8) / part_bytes;
-  const int n_tg = max(1, min(kThreads / n_bp, 1 + room));
+  const int n_tg = max(1, min(min(kThreads / n_bp, room), min(32, T)));
   const int bp = tid % n_bp, tg = tid / n_bp;
   const bool active = tg < n_tg && tid < n_bp * n_tg;
-  int bm = 0, bn = 0;
-  {
-    int r = bp;
-    for (bn = 0; bn < nbn; ++bn) {
-      const int c = min(nbm - 1, (BN * bn + BN - 1) / BM) + 1;
+  auto block_of = [&](int pair, int& bm_out, int& bn_out) {
+    int r = pair, c = 0;
+    for (bn_out = 0; bn_out < nbn; ++bn_out) {
+      c = min(nbm - 1, (BN * bn_out + BN - 1) / BM) + 1;
       if (r < c) break;
       r -= c;
     }
-    bm = r;
-  }
+    bm_out = r;
+  };
+  int bm = 0, bn = 0;
+  block_of(bp, bm, bn);
   float ar[BM][BN], ai[BM][BN];
 #pragma unroll
   for (int i = 0; i < BM; ++i)
@@ -130,42 +134,32 @@ __device__ __forceinline__ void covariance_lds(const float2* __restrict__ Yb, in
     }
     __syncthreads();
   }
-  // combine the thread groups in a fixed order
-  if (active && tg > 0) {
-    float2* dst = sPart + (int64_t(tg - 1) * n_bp + bp) * (BM * BN);
+  if (active) {
+    float2* dst = sPart + (int64_t(tg) * n_bp + bp) * (BM * BN);
 #pragma unroll
     for (int i = 0; i < BM; ++i)
 #pragma unroll
       for (int j = 0; j < BN; ++j) dst[i * BN + j] = make_float2(ar[i][j], ai[i][j]);
   }
   __syncthreads();
-  if (active && tg == 0) {
-    for (int g2 = 1; g2 < n_tg; ++g2) {
-      const float2* src = sPart + (int64_t(g2 - 1) * n_bp + bp) * (BM * BN);
-#pragma unroll
-      for (int i = 0; i < BM; ++i)
-#pragma unroll
-        for (int j = 0; j < BN; ++j) {
-          ar[i][j] += src[i * BN + j].x;
-          ai[i][j] += src[i * BN + j].y;
-        }
+  const float invT = 1.0f / float(T);
+  for (int pe = tid; pe < n_bp * BM * BN; pe += kThreads) {
+    const int pr = pe / (BM * BN), e = pe % (BM * BN);
+    float2 acc = make_float2(0.f, 0.f);
+    for (int g2 = 0; g2 < n_tg; ++g2) {
+      const float2 v = sPart[(int64_t(g2) * n_bp + pr) * (BM * BN) + e];
+      acc.x += v.x;
+      acc.y += v.y;
     }
-  }
-  __syncthreads();
-  if (active && tg == 0) {
-    const float invT = 1.0f / float(T);
-#pragma unroll
-    for (int i = 0; i < BM; ++i)
-#pragma unroll
-      for (int j = 0; j < BN; ++j) {
-        const int m = BM * bm + i, n = BN * bn + j;
-        if (m < M && n < M && m <= n) {
-          const float re = ar[i][j] * invT;
-          const float im = (m == n) ? 0.f : ai[i][j] * invT;
-          sR[m * M + n] = make_float2(re, im);
-          sR[n * M + m] = make_float2(re, -im);
-        }
-      }
+    int pbm = 0, pbn = 0;
+    block_of(pr, pbm, pbn);
+    const int m = BM * pbm + e / BN, n = BN * pbn + e % BN;
+    if (m < M && n < M && m <= n) {
+      const float re = acc.x * invT;
+      const float im = (m == n) ? 0.f : acc.y * invT;
+      sR[m * M + n] = make_float2(re, im);
+      sR[n * M + m] = make_float2(re, -im);
+    }
   }
   __syncthreads();
 }
@@ -210,14 +204,29 @@ __device__ __attribute__((noinline)) void stage_covariance_gram(const float2* __
     accB[c] = floatx4{0.f, 0.f, 0.f, 0.f};
   }
   const int fi = lane & 15, fk = lane >> 4;
-  for (int t0 = 0; t0 < T; t0 += TC) {
-    for (int v = threadIdx.x; v < TC * (W / 2); v += kThreads) {
+  // the next stage's snapshots are loaded into registers while the current
+  // stage is multiplied
+  constexpr int kPer = (TC * (W / 2) + kThreads - 1) / kThreads;
+  float2 yv[kPer];
+  auto load_stage = [&](int t0) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int v = threadIdx.x + q * kThreads;
       const int tt = v / (W / 2), m = v - tt * (W / 2);
       const int t = t0 + tt;
-      const float2 y = (t < T && m < M) ? Yb[int64_t(t) * M + m] : make_float2(0.f, 0.f);
-      *reinterpret_cast<float2*>(&sZ[tt * LD + 2 * m]) = y;
+      yv[q] = (v < TC * (W / 2) && t < T && m < M) ? Yb[int64_t(t) * M + m] : make_float2(0.f, 0.f);
+    }
+  };
+  load_stage(0);
+  for (int t0 = 0; t0 < T; t0 += TC) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int v = threadIdx.x + q * kThreads;
+      const int tt = v / (W / 2), m = v - tt * (W / 2);
+      if (v < TC * (W / 2)) *reinterpret_cast<float2*>(&sZ[tt * LD + 2 * m]) = yv[q];
     }
     __syncthreads();
+    if (t0 + TC < T) load_stage(t0 + TC);
     if (act) {
       for (int s = 0; s < TC / 4; ++s) {
         const float* row = sZ + (4 * s + fk) * LD + fi;
