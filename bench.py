@@ -54,7 +54,7 @@ def measured_traffic(key):
 
 
 # projection kernels that evaluate x^T Q x in its symmetric form (upper triangle of Q)
-SYMMETRIC_KERNELS = {"k_proj_q", "k_proj_qb", "k_proj_s"}
+SYMMETRIC_KERNELS = {"k_proj_q", "k_proj_qc", "k_proj_qb", "k_proj_s"}
 
 
 def proj_flops_per_point(M, kernel):
@@ -70,13 +70,17 @@ def proj_flops_per_point(M, kernel):
     return 8.0 * M * M + 8.0 * M
 
 
-def proj_kernel_name(precision, n_elem):
-    """The kernel that evaluates the projection for a precision and array size."""
+def proj_kernel_name(precision, n_elem, candidates=False):
+    """The kernel that evaluates the projection for a precision and array size
+    (k_proj_qc: the FP32 register-resident kernel that also emits the peak
+    candidates)."""
     if precision == "f32_valu":
         return "k_spec_cov_valu"
     if n_elem > 64:
         return "k_proj_s"
-    return "k_proj_q" if precision == "f32" else "k_proj_qb"
+    if precision == "f32":
+        return "k_proj_qc" if candidates else "k_proj_q"
+    return "k_proj_qb"
 
 
 def rmse_by_snr(ts, refined_deg, idx):
@@ -703,6 +707,9 @@ def main():
                          "361x181 az/el grid; ragged: 50 000 uneven trials (M 8..128, T 16..2048) "
                          "in one persistent launch under a HIP graph")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--staged-peaks", action="store_true",
+                    help="write the spectrum and pick peaks with ba_peaks over it, instead of the "
+                         "candidates the FP32 projection emits on 1-D grids")
     ap.add_argument("--train-trials", type=int, default=1000000)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, copy a buffer of this many MiB once (a plain copy kernel "
@@ -797,15 +804,33 @@ def bench_grid(args, workers):
     val = torch.empty((B, K), dtype=torch.float32, device=dev)
     ref = torch.empty((B, K, plan.ndim), dtype=torch.float64, device=dev)
     ws = bb.spectrum_workspace_for(plan, B, dev)
+    # FP32 on a 1-D grid: the projection emits the peak candidates and a
+    # per-trial merge finishes the pick, so the spectrum is neither re-read
+    # nor written (the step's outputs are the peaks)
+    use_cand = False
+    if not args.staged_peaks:
+        try:
+            bb.ba_candidates_size(plan, B, K)
+            use_cand = True
+        except bb.BartlettError:
+            pass
+    cand = bb.candidates_for(plan, B, K, dev) if use_cand else None
+    log("peak pick: %s" % ("candidates from the projection + merge" if use_cand else "ba_peaks over P"))
 
     def step(ev=None):
         bb.ba_covariance(plan, B, T, Y, R)
         if ev is not None:
             ev[0].record()
-        bb.ba_spectrum(plan, B, R, P, ws)
+        if use_cand:
+            bb.ba_spectrum_candidates(plan, B, R, K, None, cand)
+        else:
+            bb.ba_spectrum(plan, B, R, P, ws)
         if ev is not None:
             ev[1].record()
-        bb.ba_peaks(plan, B, P, K, idx, val, ref)
+        if use_cand:
+            bb.ba_peaks_merge(plan, B, K, cand, idx, val, ref)
+        else:
+            bb.ba_peaks(plan, B, P, K, idx, val, ref)
 
     for _ in range(args.warmup):
         step()
@@ -823,7 +848,8 @@ def bench_grid(args, workers):
     proj_ms = float(np.mean(proj_times))
     log("timed %d steps: %.3f ms/step, projection %.3f ms" % (args.steps, dt / args.steps * 1e3, proj_ms))
 
-    flops_proj = float(B) * G * proj_flops_per_point(M, proj_kernel_name(args.precision, M))
+    kname = proj_kernel_name(args.precision, M, use_cand)
+    flops_proj = float(B) * G * proj_flops_per_point(M, kname)
     bound, peak = PEAK[args.precision]
     achieved = flops_proj / (proj_ms * 1e-3) / 1e12
 
@@ -836,6 +862,15 @@ def bench_grid(args, workers):
     from oracle import bartlett as ob
     A = ob.steering(ts.pos_wl, ob.directions(ts.grid_kind, ts.grid))
     nspot = 8 if M <= 64 else 2
+    if use_cand:
+        # the timed step wrote no spectrum: evaluate it for the spot trials from
+        # the resident covariances, and check the merged peaks against ba_peaks on it
+        bb.ba_spectrum(plan, nspot, R, P, ws)
+        i_chk = torch.empty((nspot, K), dtype=torch.int32, device=dev)
+        v_chk = torch.empty((nspot, K), dtype=torch.float32, device=dev)
+        bb.ba_peaks(plan, nspot, P, K, i_chk, v_chk, None)
+        if not (torch.equal(i_chk, idx[:nspot]) and torch.equal(v_chk, val[:nspot])):
+            raise RuntimeError("merged candidates differ from ba_peaks on the spot trials")
     P_h = P[:nspot].cpu().numpy().astype(np.float64)
     errs = []
     for b in range(nspot):
@@ -910,13 +945,12 @@ def bench_grid(args, workers):
                    "precision": args.precision},
         "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
-                     "traffic": measured_traffic("%s|%s|%s|b%d" % (
-                         proj_kernel_name(args.precision, M), args.precision, ts.name, B)),
-                     "kernel": proj_kernel_name(args.precision, M), "kernel_ms": proj_ms,
+                     "traffic": measured_traffic("%s|%s|%s|b%d" % (kname, args.precision, ts.name, B)),
+                     "kernel": kname, "kernel_ms": proj_ms,
                      "kernel_ms_median": float(np.median(proj_times)),
                      "flops_per_launch": flops_proj,
                      "form": ("symmetric: one triangle of the 2M x 2M real Q"
-                              if proj_kernel_name(args.precision, M) in SYMMETRIC_KERNELS else "full Q"),
+                              if kname in SYMMETRIC_KERNELS else "full Q"),
                      # the dense count 8M^2G + 8MG of the full complex product, for reference
                      "achieved_dense_count": float(B) * G * (8.0 * M * M + 8.0 * M) / (proj_ms * 1e-3) / 1e12},
         "cpu_baseline": cpu,
@@ -925,6 +959,8 @@ def bench_grid(args, workers):
         "failed_trials": fails,
         "accuracy": metrics.accuracy_summary(trial_errors(ts, est_deg, idx_h)),
         "spot_parity_normwise_max": float(np.max(errs)),
+        "peak_pick": ("candidates from the projection epilogue + per-trial merge (spectrum not written)"
+                      if use_cand else "ba_peaks over the written spectrum"),
     }
     if vs_f32 is not None:
         line["vs_f32_same_trials"] = vs_f32

@@ -103,7 +103,9 @@ ba_status ba_plan_info(ba_plan p, int32_t* n_elem, int64_t* n_grid, int32_t* ndi
 /*
  * Workspace bytes that ba_run needs for n_trials trials; with_spectrum_out = 0
  * means ba_run is called with P == NULL, so the spectrum is staged in the
- * workspace.
+ * workspace, except on plans that ba_spectrum_candidates serves: there the
+ * workspace holds the covariances and the peak candidates (sized for k = 16)
+ * and the spectrum is written only to a P the caller passes.
  */
 ba_status ba_workspace_size(ba_plan p, int32_t n_trials, int32_t n_snap,
                             int32_t with_spectrum_out, size_t* bytes);
@@ -165,6 +167,35 @@ ba_status ba_peaks(ba_plan p, int32_t n_trials, const float* P, int32_t k, int32
                    float* val, double* refined, void* stream);
 
 /*
+ * Spectrum and peak candidates in one pass (Sec. IV-D.2: the cost over the
+ * candidate set and its maximum, as ba_spectrum followed by ba_peaks): the
+ * projection's epilogue applies the peak rule of ba_peaks to each column range
+ * a workgroup covers and keeps that range's k best interior maxima with their
+ * neighbour values, plus the values at the range's two ends; ba_peaks_merge
+ * then finishes the pick per trial. The spectrum is not re-read, and not
+ * written at all when P is NULL.
+ * FP32 plans of up to 64 elements on 1-D grids only (BA_ERR_UNSUPPORTED
+ * otherwise, from all three calls).
+ *   R      dev c64 [B][M][M] (ba_covariance).
+ *   k      1 <= k <= 16; the same k must reach ba_peaks_merge.
+ *   P      dev float [B][G] or NULL; when given, bit-identical to ba_spectrum.
+ *   cand   dev, >= ba_candidates_size(p, B, k) bytes, 16-byte aligned; opaque
+ *          records owned by the caller, every byte of the sized part written.
+ */
+ba_status ba_candidates_size(ba_plan p, int32_t n_trials, int32_t k, size_t* bytes);
+ba_status ba_spectrum_candidates(ba_plan p, int32_t n_trials, const void* R, int32_t k, float* P,
+                                 void* cand, size_t cand_bytes, void* stream);
+
+/*
+ * Per-trial merge of the records ba_spectrum_candidates wrote for the same
+ * plan, n_trials and k (enqueue it after that call on the same stream).
+ *   idx/val/refined as ba_peaks, with identical values (same rule, same order,
+ *   the refinement from the same three FP32 values).
+ */
+ba_status ba_peaks_merge(ba_plan p, int32_t n_trials, int32_t k, const void* cand, int32_t* idx,
+                         float* val, double* refined, void* stream);
+
+/*
  * Proposal moments of Sec. IV-D.2: weights w_g = P_g / sum P over the distinct
  * grid points, mean mu = coordinates of the global maximum (lowest index among
  * equal maxima), covariance C = sum_g w_g (x_g - mu)(x_g - mu)^T. Coordinates x
@@ -194,9 +225,12 @@ ba_status ba_proposal_sample(ba_plan p, int32_t n_trials, const double* mu_cov, 
                              const double* z, double* particles, double* weights, void* stream);
 
 /*
- * The whole path for B trials: covariance -> spectrum -> peaks (+refinement).
+ * The whole path for B trials: covariance -> spectrum -> peaks (+refinement);
+ * on plans that ba_spectrum_candidates serves, covariance -> spectrum with
+ * candidates -> merge (same results).
  *   Y          dev c64 [B][T][M].
- *   P          dev float [B][G] or NULL (then staged in the workspace).
+ *   P          dev float [B][G] or NULL (then staged in the workspace, or not
+ *              written at all on the candidate path).
  *   idx/val/refined as ba_peaks (refined may be NULL).
  *   workspace  dev, at least ba_workspace_size(p, B, T, P != NULL) bytes,
  *              256-byte aligned.

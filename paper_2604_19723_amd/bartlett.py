@@ -76,6 +76,9 @@ _SIGS = {
     "ba_spectrum": (_i32, [_vp, _i32, _vp, _vp, _vp, _sz, _vp]),
     "ba_spectrum_snapshots": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp]),
     "ba_peaks": (_i32, [_vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp]),
+    "ba_candidates_size": (_i32, [_vp, _i32, _i32, C.POINTER(_sz)]),
+    "ba_spectrum_candidates": (_i32, [_vp, _i32, _vp, _i32, _vp, _vp, _sz, _vp]),
+    "ba_peaks_merge": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp]),
     "ba_proposal_moments": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "ba_run": (_i32, [_vp, _i32, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "ba_run_noalloc": (_i32, [_vp, _i32, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp]),
@@ -303,6 +306,41 @@ def ba_peaks(plan: Plan, n_trials, P, k, idx, val, refined=None, stream=None):
         plan.handle, n_trials, _dev(P, "f32", n_trials * G, "P"), k,
         _dev(idx, "i32", n_trials * k, "idx"), _dev(val, "f32", n_trials * k, "val"),
         _dev(refined, "f64", n_trials * k * nd, "refined", optional=True), _stream(stream)))
+
+
+def ba_candidates_size(plan: Plan, n_trials, k) -> int:
+    """Bytes of the candidate records of ba_spectrum_candidates (raises
+    BartlettError with BA_ERR_UNSUPPORTED for plans it does not serve)."""
+    b = _sz()
+    _check("ba_candidates_size", lib().ba_candidates_size(plan.handle, n_trials, k, C.byref(b)))
+    return b.value
+
+
+def ba_spectrum_candidates(plan: Plan, n_trials, R, k, P, cand, stream=None):
+    """Spectrum (written only when P is not None) and per-range peak candidates."""
+    M, G = plan.M, plan.G
+    need = ba_candidates_size(plan, n_trials, k)
+    ptr, nbytes = _workspace(cand, need)
+    _check("ba_spectrum_candidates", lib().ba_spectrum_candidates(
+        plan.handle, n_trials, _dev(R, "c64", n_trials * M * M, "R"), k,
+        _dev(P, "f32", n_trials * G, "P", optional=True), ptr, nbytes, _stream(stream)))
+
+
+def ba_peaks_merge(plan: Plan, n_trials, k, cand, idx, val, refined=None, stream=None):
+    """Peaks of each trial from the records of ba_spectrum_candidates (same n_trials and k)."""
+    nd = plan.ndim
+    ptr, _ = _workspace(cand, ba_candidates_size(plan, n_trials, k))
+    _check("ba_peaks_merge", lib().ba_peaks_merge(
+        plan.handle, n_trials, k, ptr, _dev(idx, "i32", n_trials * k, "idx"),
+        _dev(val, "f32", n_trials * k, "val"),
+        _dev(refined, "f64", n_trials * k * nd, "refined", optional=True), _stream(stream)))
+
+
+def candidates_for(plan: Plan, n_trials, k, device="cuda"):
+    """A device buffer for the candidate records of n_trials trials and k peaks."""
+    import torch
+    n = ba_candidates_size(plan, n_trials, k)
+    return torch.empty(max(n, 256), dtype=torch.uint8, device=device)
 
 
 def ba_proposal_moments(plan: Plan, n_trials, P, mu_cov, stream=None):

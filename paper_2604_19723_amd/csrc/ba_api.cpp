@@ -305,8 +305,12 @@ ba_status ba_workspace_size(ba_plan p, int32_t n_trials, int32_t n_snap, int32_t
   if (n_trials < 0 || n_snap < 1) return arg_error(fn, "n_trials >= 0 and n_snap >= 1 required");
   const Plan& q = *P_(p);
   size_t b = align256(size_t(n_trials) * q.M * q.M * sizeof(float2));
-  b += align256(spectrum_ws_bytes(q, n_trials));
-  if (!with_spectrum_out) b += align256(size_t(n_trials) * q.G * sizeof(float));
+  if (candidates_supported(q)) {
+    b += align256(candidate_bytes(q, n_trials, kMaxPeaks));
+  } else {
+    b += align256(spectrum_ws_bytes(q, n_trials));
+    if (!with_spectrum_out) b += align256(size_t(n_trials) * q.G * sizeof(float));
+  }
   *bytes = b;
   return BA_OK;
 }
@@ -427,6 +431,58 @@ ba_status ba_proposal_sample(ba_plan p, int32_t n_trials, const double* mu_cov, 
   return e == hipSuccess ? BA_OK : dev_error(fn, e);
 }
 
+// An error reported by the entry point `from` on behalf of `fn`: the message
+// names fn.
+static ba_status renamed_error(const char* fn, const char* from, ba_status st) {
+  std::string m = g_last_error;
+  const size_t n = std::strlen(from);
+  if (m.compare(0, n, from) == 0) m = fn + m.substr(n);
+  set_error(m);
+  return st;
+}
+
+ba_status ba_candidates_size(ba_plan p, int32_t n_trials, int32_t k, size_t* bytes) {
+  static const char* fn = "ba_candidates_size";
+  CHECK_PLAN(fn);
+  if (!bytes) return arg_error(fn, "bytes is NULL");
+  if (n_trials < 0) return arg_error(fn, "n_trials >= 0 required");
+  if (k < 1 || k > kMaxPeaks) return arg_error(fn, "k must be in [1, 16]");
+  if (!candidates_supported(q)) {
+    set_error(std::string(fn) + ": FP32 plans of up to 64 elements on 1-D grids only");
+    return BA_ERR_UNSUPPORTED;
+  }
+  *bytes = candidate_bytes(q, n_trials, k);
+  return BA_OK;
+}
+
+ba_status ba_spectrum_candidates(ba_plan p, int32_t n_trials, const void* R, int32_t k, float* P, void* cand,
+                                 size_t cand_bytes, void* stream) {
+  static const char* fn = "ba_spectrum_candidates";
+  size_t need = 0;
+  const ba_status st = ba_candidates_size(p, n_trials, k, &need);
+  if (st != BA_OK) return renamed_error(fn, "ba_candidates_size", st);
+  if (n_trials == 0) return BA_OK;
+  if (!R || !cand) return arg_error(fn, "null buffer");
+  if (cand_bytes < need) return arg_error(fn, "cand smaller than ba_candidates_size");
+  if (reinterpret_cast<uintptr_t>(cand) & 15) return arg_error(fn, "cand must be 16-byte aligned");
+  hipError_t e = launch_spectrum_candidates(*P_(p), n_trials, static_cast<const float2*>(R), P, k,
+                                            static_cast<float4*>(cand), static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? BA_OK : dev_error(fn, e);
+}
+
+ba_status ba_peaks_merge(ba_plan p, int32_t n_trials, int32_t k, const void* cand, int32_t* idx, float* val,
+                         double* refined, void* stream) {
+  static const char* fn = "ba_peaks_merge";
+  size_t need = 0;
+  const ba_status st = ba_candidates_size(p, n_trials, k, &need);
+  if (st != BA_OK) return renamed_error(fn, "ba_candidates_size", st);
+  if (n_trials == 0) return BA_OK;
+  if (!cand || !idx || !val) return arg_error(fn, "null buffer");
+  hipError_t e = launch_peaks_merge(*P_(p), n_trials, k, static_cast<const float4*>(cand), idx, val, refined,
+                                    static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? BA_OK : dev_error(fn, e);
+}
+
 ba_status ba_run(ba_plan p, int32_t n_trials, int32_t n_snap, const void* Y, int32_t k, float* P,
                  int32_t* idx, float* val, double* refined, void* workspace, size_t workspace_bytes,
                  void* stream) {
@@ -445,6 +501,13 @@ ba_status ba_run(ba_plan p, int32_t n_trials, int32_t n_snap, const void* Y, int
   char* ws = static_cast<char*>(workspace);
   float2* R = reinterpret_cast<float2*>(ws);
   char* Qws = ws + align256(size_t(n_trials) * q.M * q.M * sizeof(float2));
+  if (candidates_supported(q)) {
+    float4* rec = reinterpret_cast<float4*>(Qws);
+    hipError_t e = launch_covariance(q, n_trials, n_snap, static_cast<const float2*>(Y), R, s);
+    if (e == hipSuccess) e = launch_spectrum_candidates(q, n_trials, R, P, k, rec, s);
+    if (e == hipSuccess) e = launch_peaks_merge(q, n_trials, k, rec, idx, val, refined, s);
+    return e == hipSuccess ? BA_OK : dev_error(fn, e);
+  }
   float* Pw = P;
   if (!Pw) Pw = reinterpret_cast<float*>(Qws + align256(spectrum_ws_bytes(q, n_trials)));
   hipError_t e = launch_covariance(q, n_trials, n_snap, static_cast<const float2*>(Y), R, s);

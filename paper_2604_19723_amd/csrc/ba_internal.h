@@ -62,6 +62,25 @@ hipError_t launch_peaks(const Plan& p, int B, const float* P, int k, int* idx, f
                         double* refined, hipStream_t s, const int* count = nullptr);
 hipError_t launch_moments(const Plan& p, int B, const float* P, double* mu_cov, hipStream_t s);
 
+// Peak candidates from the projection epilogue (FP32 register-resident path,
+// 1-D grids): each trial's candidate rows are cut into nsplit column ranges of
+// `span` columns (the last one shorter); every range leaves k + 1 float4
+// records (its top-k interior maxima, then the values at its two ends).
+constexpr int kMaxCandRanges = 64;
+struct CandLayout {
+  int nsplit = 1;    // column ranges per trial
+  int per = 1;       // steering chunks per range
+  int64_t span = 0;  // columns per range
+};
+bool candidates_supported(const Plan& p);
+CandLayout candidate_layout(const Plan& p, int B);
+size_t candidate_bytes(const Plan& p, int B, int k);
+// P may be null (spectrum not written)
+hipError_t launch_spectrum_candidates(const Plan& p, int B, const float2* R, float* P, int k, float4* rec,
+                                      hipStream_t s);
+hipError_t launch_peaks_merge(const Plan& p, int B, int k, const float4* rec, int* idx, float* val,
+                              double* refined, hipStream_t s);
+
 // residual covariance R~ = Pi R Pi (Psi given as vectors [B][S][M], or as grid
 // indices gidx[b * ld + s] into the plan's steering table, -1 = no column)
 hipError_t launch_residual(const Plan& p, int B, const float2* R, int S, const float2* Psi, const int* gidx,

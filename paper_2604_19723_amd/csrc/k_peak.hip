@@ -18,6 +18,7 @@
 
 #include "ba_internal.h"
 #include "coherent.h"
+#include "peak_rule.h"
 
 namespace ba {
 namespace {
@@ -26,9 +27,7 @@ namespace {
 // (16 per lane) stays within the 64 KB a workgroup gets without opting in
 constexpr int kPeakRowMax = 7680;
 
-__device__ __forceinline__ bool better(float va, int ia, float vb, int ib) {
-  return va > vb || (va == vb && ia < ib);
-}
+__device__ __forceinline__ bool better(float va, int ia, float vb, int ib) { return peak_better(va, ia, vb, ib); }
 
 __device__ __forceinline__ int wrap_row(int j0, int rows) {
   return j0 < 0 ? j0 + rows : (j0 >= rows ? j0 - rows : j0);
@@ -73,13 +72,7 @@ __device__ __forceinline__ void insert(float (&lv)[KC], int (&li)[KC], float v, 
   }
 }
 
-__device__ double parabolic(double pm, double p0, double pp) {
-#pragma clang fp contract(off)
-  const double den = pm - 2.0 * p0 + pp;
-  if (den == 0.0 || !isfinite(den)) return 0.0;
-  const double d = 0.5 * (pm - pp) / den;
-  return d > 0.5 ? 0.5 : (d < -0.5 ? -0.5 : d);
-}
+__device__ double parabolic(double pm, double p0, double pp) { return peak_parabolic(pm, p0, pp); }
 
 // ONED: a 1-D grid (s1 == 1) whose candidate row fits in LDS is staged there
 // with coalesced loads first, and each point meets its two neighbours in LDS
@@ -325,7 +318,121 @@ __global__ __launch_bounds__(256) void k_moments(const float* __restrict__ P, in
   }
 }
 
+// Merge of the per-range peak candidates of a 1-D grid (one wave per
+// trial). The interior maxima come from the ranges' lists; the two end
+// columns of every range are tested here against the end values of the
+// neighbouring ranges (wrap of the row when wrap0), with the same rule and
+// order as k_peaks, so the result is identical to k_peaks on the same P.
+constexpr int kMergeCap = kMaxCandRanges * (kMaxPeaks + 2);
+
+__global__ __launch_bounds__(64) void k_peaks_merge(const float4* __restrict__ rec, int nsplit, int64_t span,
+                                                    int rows, int wrap0, int k, int* __restrict__ idx,
+                                                    float* __restrict__ val, double* __restrict__ refined) {
+  const int64_t b = blockIdx.x;
+  const int lane = threadIdx.x;
+  const float4* rb = rec + b * nsplit * (k + 1);
+  __shared__ float cv[kMergeCap], cl[kMergeCap], cr[kMergeCap];
+  __shared__ int ci[kMergeCap];
+
+  // P at a column next to a range end: one of the four end values of its range
+  auto end_val = [&](int64_t g) -> float {
+    const int64_t s = g / span, off = g - s * span;
+    const int64_t rest = rows - s * span, n = rest < span ? rest : span;
+    const float4 e = rb[s * (k + 1) + k];
+    return off == 0 ? e.x : off == 1 ? e.y : off == n - 1 ? e.w : e.z;
+  };
+
+  const int nlist = nsplit * k;
+  for (int e = lane; e < nlist; e += 64) {
+    const float4 r = rb[(e / k) * (k + 1) + e % k];
+    cv[e] = r.x;
+    ci[e] = __float_as_int(r.y);
+    cl[e] = r.z;
+    cr[e] = r.w;
+  }
+  // slot nlist + 2 s: first column of range s; nlist + 2 s + 1: its last
+  for (int e = lane; e < 2 * nsplit; e += 64) {
+    const int s = e >> 1;
+    const int64_t g0 = int64_t(s) * span, rest = rows - g0, n = rest < span ? rest : span;
+    const int64_t g = (e & 1) ? g0 + n - 1 : g0;
+    float v = -INFINITY, l = 0.f, r = 0.f;
+    int gi = INT_MAX;
+    if (n > 0 && !((e & 1) && n == 1)) {
+      const float p = end_val(g);
+      bool ok = p == p;
+      if (g > 0 || wrap0) {
+        l = end_val(g > 0 ? g - 1 : rows - 1);
+        ok = ok && p > l;
+      }
+      if (g + 1 < rows || wrap0) {
+        r = end_val(g + 1 < rows ? g + 1 : 0);
+        ok = ok && p >= r;
+      }
+      if (ok) {
+        v = p;
+        gi = int(g);
+      }
+    }
+    cv[nlist + e] = v;
+    ci[nlist + e] = gi;
+    cl[nlist + e] = l;
+    cr[nlist + e] = r;
+  }
+  __syncthreads();
+
+  const int ncand = nlist + 2 * nsplit;
+  for (int t = 0; t < k; ++t) {
+    float bv = -INFINITY;
+    int bi = INT_MAX, be = -1;
+    for (int e = lane; e < ncand; e += 64)
+      if (peak_better(cv[e], ci[e], bv, bi)) {
+        bv = cv[e];
+        bi = ci[e];
+        be = e;
+      }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const float ov = __shfl_xor(bv, off, 64);
+      const int oi = __shfl_xor(bi, off, 64), oe = __shfl_xor(be, off, 64);
+      if (peak_better(ov, oi, bv, bi)) {
+        bv = ov;
+        bi = oi;
+        be = oe;
+      }
+    }
+    if (lane == 0) {
+      const int64_t o = b * k + t;
+      if (bi == INT_MAX) {
+        idx[o] = -1;
+        val[o] = __int_as_float(0x7fc00000);
+        if (refined) refined[o] = __longlong_as_double(0x7ff8000000000000LL);
+      } else {
+        idx[o] = bi;
+        val[o] = bv;
+        if (refined) {
+          double d0 = 0.0;
+          if (wrap0 || (bi > 0 && bi < rows - 1))
+            d0 = peak_parabolic(double(cl[be]), double(bv), double(cr[be]));
+          refined[o] = double(bi) + d0;
+        }
+        ci[be] = INT_MAX;  // taken
+        cv[be] = -INFINITY;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace
+
+hipError_t launch_peaks_merge(const Plan& p, int B, int k, const float4* rec, int* idx, float* val,
+                              double* refined, hipStream_t s) {
+  const CandLayout L = candidate_layout(p, B);
+  if (L.nsplit * (k + 2) > kMergeCap) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_peaks_merge, dim3(unsigned(B)), dim3(64), 0, s, rec, L.nsplit, L.span, p.rows, p.wrap0, k,
+                     idx, val, refined);
+  return hipGetLastError();
+}
 
 hipError_t launch_peaks(const Plan& p, int B, const float* P, int k, int* idx, float* val,
                         double* refined, hipStream_t s, const int* count) {

@@ -28,21 +28,173 @@
 //    shuffles and across waves through LDS in a fixed order, then scaled by
 //    2/M^2.
 // Element counts up to 64 are padded to MP in {8, 16, 32, 64} with zero rows.
+//
+// Candidate variant (1-D grids): wave 0 also runs the peak rule over the
+// column range while the spectrum passes through it, once per window of 64
+// columns (four chunks at M = 64) gathered in its lanes. Each column whose two
+// neighbours lie inside the range is tested once both are known (the last
+// column of a window waits for the next window's first), and the maxima enter
+// a sorted top-k list held across the wave's lanes (entry j in lane j) with
+// both neighbour values for the refinement. The range's first and last
+// columns, whose neighbours belong to other ranges, are left to the merge
+// kernel, which gets the two values at each end of every range. The spectrum
+// itself is written only when the caller asks for it.
 #include <algorithm>
+#include <climits>
 
+#include "peak_rule.h"
 #include "proj_common.h"
 
 namespace ba {
 namespace {
 
-// One trial's spectrum over the chunks [c0, c1) of the steering table.
-template <int MP>
+__device__ __forceinline__ float lane_val(float x, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+
+// Peak candidates of one column range [g0, gend) (columns at or past the
+// candidate rows excluded), kept by wave 0; all members are wave-uniform
+// except the list entry each lane holds.
+struct RangeCands {
+  int g0, gend;  // grid sizes stay below 2^30
+  int k;
+  float lv, ll, lr;  // list entry of this lane: value, left and right neighbour
+  int li;            // its grid index (INT_MAX: empty)
+  float tv;          // the k-th entry, the bar a new candidate has to pass
+  int ti;
+  float prev_last;   // value of the column before the current chunk
+  float pend_left;   // left neighbour of that column
+  bool pend;         // that column waits for its right neighbour
+  float e[4];        // P at g0, g0 + 1, gl - 1, gl (gl = gend - 1), clamped to the range
+
+  __device__ void init(int g0_, int gend_, int k_) {
+    g0 = g0_;
+    gend = gend_;
+    k = k_;
+    lv = ll = lr = -INFINITY;
+    li = INT_MAX;
+    tv = -INFINITY;
+    ti = INT_MAX;
+    prev_last = pend_left = 0.f;
+    pend = false;
+    e[0] = e[1] = e[2] = e[3] = __int_as_float(0x7fc00000);
+  }
+
+  // (v, g) with its neighbours, offered by the whole wave (uniform arguments)
+  __device__ void offer(float v, int g, float l, float r, int lane) {
+    if (!peak_better(v, g, tv, ti)) return;
+    const bool ahead = lane < k && peak_better(lv, li, v, g);
+    const int pos = __popcll(__ballot(ahead));  // the list is sorted: the entries ahead are a prefix
+    const float sv = __shfl_up(lv, 1, 64), sl = __shfl_up(ll, 1, 64), sr = __shfl_up(lr, 1, 64);
+    const int si = __shfl_up(li, 1, 64);
+    if (lane == pos) {
+      lv = v;
+      li = g;
+      ll = l;
+      lr = r;
+    } else if (lane > pos && lane < k) {
+      lv = sv;
+      li = si;
+      ll = sl;
+      lr = sr;
+    }
+    tv = lane_val(lv, k - 1);
+    ti = __builtin_amdgcn_readlane(li, k - 1);
+  }
+};
+
+// Value of lane - 1 (lane + 1) across the whole wave by DPP wave_shr:1
+// (wave_shl:1); lane 0 (63) keeps its own value, which callers replace or
+// never use.
+__device__ __forceinline__ float wave_from_prev_lane(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float wave_from_next_lane(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x), 0x130, 0xf, 0xf, false));
+}
+
+// Column t (wave-uniform) of a window whose values lie NPL per lane.
+template <int NPL>
+__device__ __forceinline__ float window_col(const float (&v)[NPL], int t) {
+  if constexpr (NPL == 1) {
+    return lane_val(v[0], t);
+  } else {
+    return (t & 1) ? lane_val(v[1], t >> 1) : lane_val(v[0], t >> 1);
+  }
+}
+
+// Peak rule over one window of WIN columns starting at wbase, held by wave 0
+// (column wbase + lane * NPL + i in v[i]; only columns of the range are
+// read), then the bookkeeping for the next window.
+template <int WIN, int NPL>
+__device__ __forceinline__ void window_candidates(RangeCands& rc, const float (&v)[NPL], int wbase, bool first,
+                                                  int lane) {
+  if (rc.gend <= rc.g0) return;
+  // the deferred last column of the previous window meets its right neighbour
+  if (rc.pend) {
+    const float r0 = lane_val(v[0], 0);
+    if (rc.prev_last == rc.prev_last && rc.prev_last > rc.pend_left && rc.prev_last >= r0)
+      rc.offer(rc.prev_last, wbase - 1, rc.pend_left, r0, lane);
+  }
+  float lft[NPL], rgt[NPL];
+#pragma unroll
+  for (int i = 0; i < NPL; ++i) {
+    lft[i] = i > 0 ? v[i - 1] : wave_from_prev_lane(v[NPL - 1]);
+    rgt[i] = i < NPL - 1 ? v[i + 1] : wave_from_next_lane(v[0]);
+  }
+  if (lane == 0) lft[0] = rc.prev_last;
+#pragma unroll
+  for (int i = 0; i < NPL; ++i) {
+    const int t = lane * NPL + i;
+    const int g = wbase + t;
+    // both neighbours inside the range, the right one inside this window
+    const bool inner = t < WIN - 1 && g > rc.g0 && g + 1 < rc.gend;
+    const bool ok = inner && v[i] == v[i] && v[i] > lft[i] && v[i] >= rgt[i];
+    uint64_t m = __ballot(ok);
+    while (m) {
+      const int src = __builtin_ctzll(m);
+      m &= m - 1;
+      rc.offer(lane_val(v[i], src), wbase + src * NPL + i, lane_val(lft[i], src), lane_val(rgt[i], src), lane);
+    }
+  }
+  // values at the two ends of the range for the merge
+  const int gl = rc.gend - 1;
+  if (first) {
+    rc.e[0] = window_col<NPL>(v, rc.g0 - wbase);
+    rc.e[1] = gl > rc.g0 ? window_col<NPL>(v, rc.g0 + 1 - wbase) : rc.e[0];
+  }
+  if (gl >= wbase && gl < wbase + WIN) {
+    rc.e[3] = window_col<NPL>(v, gl - wbase);
+    rc.e[2] = gl == rc.g0 ? rc.e[3] : (gl - 1 >= wbase ? window_col<NPL>(v, gl - 1 - wbase) : rc.prev_last);
+  }
+  const int gt = wbase + WIN - 1;
+  rc.pend = gt > rc.g0 && gt + 1 < rc.gend;
+  rc.pend_left = window_col<NPL>(v, WIN - 2);
+  rc.prev_last = window_col<NPL>(v, WIN - 1);
+}
+
+// One trial's spectrum over the chunks [c0, c1) of the steering table; with
+// CAND, also the peak candidates of the range (rc, wave 0), and P written only
+// when Pb is not null.
+template <int MP, bool CAND = false>
 __device__ __forceinline__ void proj_q_trial(const float2* __restrict__ Rb, const float4* __restrict__ Xg,
                                              float* __restrict__ Pb, int M, int64_t G, int c0, int c1,
-                                             float4* sX, float (*red)[QCfg<MP>::WR][QCfg<MP>::NB * 16]) {
+                                             float4* sX, float (*red)[QCfg<MP>::WR][QCfg<MP>::NB * 16],
+                                             RangeCands* rc = nullptr) {
   using C = QCfg<MP>;
+  // Candidate epilogue: wave 0 gathers the spectrum of CPW consecutive chunks
+  // (a window of WIN >= 64 columns, NPL per lane) and runs the peak rule once
+  // per window
+  constexpr int CW = C::NB * 16;                // columns per chunk
+  constexpr int WIN = CW > 64 ? CW : 64;
+  constexpr int CPW = WIN / CW;
+  constexpr int NPL = WIN / 64;
+  static_assert(!CAND || NPL <= 2, "at most two columns per lane");
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wr = wave % C::WR, wc = wave / C::WR;
+  float vwin[NPL];
+#pragma unroll
+  for (int i = 0; i < NPL; ++i) vwin[i] = 0.f;
 
   // each wave copies its quarter of a chunk, 64 lanes x 16 bytes per DMA
   auto fetch = [&](int c, int buf) {
@@ -68,7 +220,7 @@ __device__ __forceinline__ void proj_q_trial(const float2* __restrict__ Rb, cons
     const float* sx = reinterpret_cast<const float*>(sxb);
     for (int jb = wc; jb < C::NB; jb += C::WC) {
       const float part = block_quadratic<MP>(a, sxb + jb * (C::BLK / 4), sx + jb * C::BLK, wr, lane);
-      if (C::WR == 1) {
+      if (C::WR == 1 && !CAND) {
         const int64_t g = int64_t(c) * C::NB * 16 + jb * 16 + lane;
         if (lane < 16 && g < G) Pb[g] = part * scale;
       } else if (lane < 16) {
@@ -77,7 +229,31 @@ __device__ __forceinline__ void proj_q_trial(const float2* __restrict__ Rb, cons
     }
     lds_dma_wait();
     __syncthreads();
-    if (C::WR > 1) {
+    if constexpr (CAND) {
+      // same sums and scaling as below, so P is bit-identical to the plain launch
+      if (wave == 0) {
+        const int q = c % CPW;  // this chunk's slot in the window
+#pragma unroll
+        for (int i = 0; i < NPL; ++i) {
+          const int t = lane * NPL + i - q * CW;  // column within the chunk
+          if (t >= 0 && t < CW) {
+            float sum;
+            if (C::WR == 1) {
+              sum = red[buf][0][t];
+            } else {
+              sum = 0.f;
+#pragma unroll
+              for (int w = 0; w < C::WR; ++w) sum += red[buf][w][t];
+            }
+            vwin[i] = sum * scale;
+            const int64_t g = int64_t(c) * CW + t;
+            if (Pb && g < G) Pb[g] = vwin[i];
+          }
+        }
+        if (q == CPW - 1 || c == c1 - 1)
+          window_candidates<WIN, NPL>(*rc, vwin, (c / CPW) * WIN, c / CPW == c0 / CPW, lane);
+      }
+    } else if (C::WR > 1) {
       for (int t = threadIdx.x; t < C::NB * 16; t += 256) {
         float s = 0.f;
 #pragma unroll
@@ -128,21 +304,56 @@ __global__ __launch_bounds__(256, 2) void k_proj_q_counted(const float2* __restr
   }
 }
 
+// Spectrum of one trial's column range with its peak candidates: record
+// (b, range) holds k list entries {value, index bits, left, right} (index
+// INT_MAX: empty) and then {P[g0], P[g0 + 1], P[gl - 1], P[gl]}.
+template <int MP>
+__global__ __launch_bounds__(256, 6) void k_proj_qc(const float2* __restrict__ R, const float4* __restrict__ Xg,
+                                                    float* __restrict__ P, int M, int64_t G, int nchunk,
+                                                    int chunks_per_wg, int nsplit, int rows, int k,
+                                                    float4* __restrict__ rec) {
+  using C = QCfg<MP>;
+  constexpr int CW = C::NB * 16;
+  extern __shared__ __attribute__((aligned(16))) float4 sX[];
+  __shared__ float red[2][C::WR][C::NB * 16];
+  const int64_t b = blockIdx.x / nsplit;
+  const int sp = int(blockIdx.x % nsplit);
+  const int c0 = sp * chunks_per_wg;
+  const int c1 = min(c0 + chunks_per_wg, nchunk);
+  RangeCands rc;
+  rc.init(c0 * CW, min(c1 * CW, rows), k);
+  if (c0 < c1)  // always: the host sets nsplit = ceil(nchunk / chunks_per_wg)
+    proj_q_trial<MP, true>(R + b * int64_t(M) * M, Xg, P ? P + b * G : nullptr, M, G, c0, c1, sX, red, &rc);
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    float4* o = rec + (b * nsplit + sp) * (k + 1);
+    if (lane < k) o[lane] = make_float4(rc.lv, __int_as_float(rc.li), rc.ll, rc.lr);
+    if (lane == 0) o[k] = make_float4(rc.e[0], rc.e[1], rc.e[2], rc.e[3]);
+  }
+}
+
+// Split the grid columns over several workgroups per trial until there are
+// enough of them for the last round of workgroups on the CUs to be a small
+// tail (10 000 trials: two column halves, 10.58 -> 10.42 ms), keeping at
+// least 32 chunks per workgroup to pay for building U in its registers, and
+// at most max_split ranges.
+void split_columns(int nchunk, int Bs, int max_split, int* nsplit_out, int* per_out) {
+  int nsplit = 1;
+  while (int64_t(Bs) * nsplit < 16384 && 2 * nsplit * 32 <= nchunk && 2 * nsplit <= max_split) nsplit *= 2;
+  const int per = (nchunk + nsplit - 1) / nsplit;
+  *per_out = per;
+  *nsplit_out = (nchunk + per - 1) / per;
+}
+
 template <int MP>
 hipError_t launch_q(const Plan& p, int B, const float2* R, float* P, hipStream_t s, const int* count = nullptr,
                     int expect = 0) {
   using C = QCfg<MP>;
   const int nchunk = int((p.Gb + C::NB - 1) / C::NB);  // the table holds Xblocks >= nchunk * NB
-  // split the grid columns over several workgroups until there are enough of
-  // them for the last round of workgroups on the CUs to be a small tail
-  // (10 000 trials: two column halves, 10.58 -> 10.42 ms), keeping at least
-  // 32 chunks per workgroup to pay for building U in its registers; a
-  // device-counted batch is split for the size the caller expects
+  // a device-counted batch is split for the size the caller expects
   const int Bs = count ? std::max(1, std::min(expect, B)) : B;
-  int nsplit = 1;
-  while (int64_t(Bs) * nsplit < 16384 && 2 * nsplit * 32 <= nchunk) nsplit *= 2;
-  const int per = (nchunk + nsplit - 1) / nsplit;
-  nsplit = (nchunk + per - 1) / per;
+  int nsplit = 1, per = nchunk;
+  split_columns(nchunk, Bs, INT_MAX, &nsplit, &per);
   const int64_t nblk = int64_t(count ? Bs : B) * nsplit;
   if (nblk > 0x7fffffff) return hipErrorInvalidValue;
   const size_t lds = 2 * C::CH4 * sizeof(float4);
@@ -155,7 +366,49 @@ hipError_t launch_q(const Plan& p, int B, const float2* R, float* P, hipStream_t
   return hipGetLastError();
 }
 
+template <int MP>
+hipError_t launch_qc(const Plan& p, int B, const float2* R, float* P, int k, float4* rec, hipStream_t s) {
+  using C = QCfg<MP>;
+  const CandLayout L = candidate_layout(p, B);
+  const int nchunk = int((p.Gb + C::NB - 1) / C::NB);
+  const int64_t nblk = int64_t(B) * L.nsplit;
+  if (nblk > 0x7fffffff || L.span != int64_t(L.per) * C::NB * 16) return hipErrorInvalidValue;
+  const size_t lds = 2 * C::CH4 * sizeof(float4);
+  hipLaunchKernelGGL((k_proj_qc<MP>), dim3(unsigned(nblk)), dim3(256), lds, s, R,
+                     reinterpret_cast<const float4*>(p.d_X), P, p.M, p.G, nchunk, L.per, L.nsplit, p.rows, k,
+                     rec);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+bool candidates_supported(const Plan& p) {
+  return p.precision == BA_PREC_F32 && p.Mp <= 64 && p.shape1 == 1;
+}
+
+CandLayout candidate_layout(const Plan& p, int B) {
+  const int nb = 64 / p.Mp;  // 16-column blocks per chunk (8 KB of steering)
+  const int nchunk = int((p.Gb + nb - 1) / nb);
+  CandLayout L{};
+  split_columns(nchunk, std::max(B, 1), kMaxCandRanges, &L.nsplit, &L.per);
+  L.span = int64_t(L.per) * nb * 16;
+  return L;
+}
+
+size_t candidate_bytes(const Plan& p, int B, int k) {
+  return size_t(B) * candidate_layout(p, B).nsplit * size_t(k + 1) * sizeof(float4);
+}
+
+hipError_t launch_spectrum_candidates(const Plan& p, int B, const float2* R, float* P, int k, float4* rec,
+                                      hipStream_t s) {
+  switch (p.Mp) {
+    case 8: return launch_qc<8>(p, B, R, P, k, rec, s);
+    case 16: return launch_qc<16>(p, B, R, P, k, rec, s);
+    case 32: return launch_qc<32>(p, B, R, P, k, rec, s);
+    case 64: return launch_qc<64>(p, B, R, P, k, rec, s);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_spectrum_mfma(const Plan& p, int B, const float2* R, float* P, hipStream_t s) {
   switch (p.Mp) {
