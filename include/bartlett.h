@@ -289,8 +289,10 @@ typedef struct ba_ragged_s* ba_ragged;
  * Bartlett cost unchanged). Builds per-size-class steering tables, orders the
  * trials longest first, and captures one persistent fused launch
  * (covariance -> spectrum -> peaks per trial, trials taken from an atomic
- * ticket) in a HIP graph. Buffers are bound here (ba_ragged_bind rebinds
- * them); ba_ragged_launch replays.
+ * ticket) in a HIP graph. On 1-D grids, trials of up to 32 elements on the
+ * covariance route run packed by default: one per wave, eight per ticket
+ * (ba_ragged_autotune decides per class). Buffers are bound here
+ * (ba_ragged_bind rebinds them); ba_ragged_launch replays.
  *   plan        FP32 plan, G <= 16384, 1-D or 2-D grid.
  *   desc        host, n_trials entries (copied).
  *   kmax        1..8: output row width; entries past a trial's k are -1 / NaN.
@@ -322,8 +324,11 @@ ba_status ba_ragged_bind(ba_ragged r, const void* Y_pool, int64_t pool_elems, fl
 
 /*
  * Autotune on this batch: per size class, the MFMA tile (waves along rows vs
- * along grid columns); per (size class, log2 T bucket), the route. Candidates
- * are timed with HIP events on up to max_probe trials each (best of `repeats`
+ * along grid columns); for the 8-, 16- and 32-element classes on 1-D grids,
+ * packed (one trial per wave) or one trial per workgroup; per (size class,
+ * log2 T bucket), the route. Candidates are timed with HIP events on up to
+ * max_probe trials each (32 * max_probe for the packing choice, so that
+ * both layouts fill as many workgroups for several rounds; best of `repeats`
  * launches after one warm-up). Results are cached in cache_path (text, may be
  * NULL) keyed by device, grid size and class/bucket; the graph is re-captured.
  * Synchronous; writes outputs of the probed trials as a side effect.
@@ -335,6 +340,10 @@ ba_status ba_ragged_routes(ba_ragged r, int32_t* routes);
 
 /* Waves along rows chosen per size class (host int32 [5], classes 8..128). */
 ba_status ba_ragged_config(ba_ragged r, int32_t* wr_per_class);
+
+/* Whether each size class runs packed, one trial per wave (host int32 [5],
+ * classes 8..128; 1 = packed; only the first three classes on 1-D grids can be). */
+ba_status ba_ragged_packed(ba_ragged r, int32_t* packed_per_class);
 
 /* Destroy (NULL accepted); synchronises the device first. */
 ba_status ba_ragged_destroy(ba_ragged r);

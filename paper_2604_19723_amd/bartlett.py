@@ -88,6 +88,7 @@ _SIGS = {
     "ba_ragged_autotune": (_i32, [_vp, C.c_char_p, _i32, _i32]),
     "ba_ragged_routes": (_i32, [_vp, _vp]),
     "ba_ragged_config": (_i32, [_vp, _vp]),
+    "ba_ragged_packed": (_i32, [_vp, _vp]),
     "ba_ragged_destroy": (_i32, [_vp]),
     "ba_pack_covariance": (_i32, [_i32, _i32, _vp, _vp, _vp]),
     "ba_mlp_create": (_i32, [C.POINTER(_vp), _i32, _i32, _i32, _i32, _i32, _i32, C.c_uint64]),
@@ -506,6 +507,13 @@ def ba_ragged_routes(r: Ragged):
 def ba_ragged_config(r: Ragged):
     out = np.empty(5, np.int32)
     _check("ba_ragged_config", lib().ba_ragged_config(r.handle, out.ctypes.data_as(_vp)))
+    return out
+
+
+def ba_ragged_packed(r: Ragged):
+    """Per size class (8..128 elements), 1 where trials run packed, one per wave."""
+    out = np.empty(5, np.int32)
+    _check("ba_ragged_packed", lib().ba_ragged_packed(r.handle, out.ctypes.data_as(_vp)))
     return out
 
 

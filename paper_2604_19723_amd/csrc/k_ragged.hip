@@ -20,8 +20,19 @@
 //     exact, a per-point phase common to all elements cancels in |a^H y|^2),
 //     the epilogue forming 2 x^T (U x) or sum |S x|^2 into an LDS spectrum row;
 //  3. peak pick and FP64 refinement from that LDS row.
+//
+// Packed small trials: a trial of at most 32 elements on a 1-D grid (when the
+// host packs its class) runs inside one wave, and a workgroup takes eight of
+// them per ticket. Each wave has 16 KB of LDS of its own and never waits for
+// the other waves: the covariance as the real Gram matrix of the snapshots on
+// the matrix cores, U into A-operand registers, the projection against the
+// class table streamed into its LDS by DMA (waits on its own counters only),
+// and the peaks gathered from the spectrum as it is produced (64-column
+// windows across the lanes, a top-k list, the end columns with the row's
+// wrap), so no spectrum row is kept.
 #include <climits>
 
+#include "cand_window.h"
 #include "proj_common.h"
 #include "ragged.h"
 
@@ -573,6 +584,204 @@ __device__ __attribute__((noinline)) void trial_peaks(const RArgs& A, const RIte
   __syncthreads();  // LDS reused by the next trial
 }
 
+// ---------------------------------------------------------------- packed small trials
+
+constexpr int kWaveLds = 16 * 1024;  // LDS of one wave in packed mode
+
+// Orders this wave's LDS accesses: writes before the point are seen by reads
+// after it from any lane of the wave (the LDS runs one wave's accesses in
+// order), and the compiler moves no LDS access across it.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// R = (1/T) sum_t y_t y_t^H of one trial (M <= MP <= 32) into wR [M][M], by one
+// wave: the real Gram matrix of the snapshots' float views (re, im
+// interleaved, zero-padded to 2 MP) on v_mfma_f32_16x16x4f32, snapshot stages
+// in the wave's LDS (rows of 48 or 80 floats: the four rows a fragment reads
+// fall on different bank quarters), then Re R[m][n] = G[2m][2n] +
+// G[2m+1][2n+1], Im R[m][n] = G[2m+1][2n] - G[2m][2n+1] (exactly Hermitian).
+template <int MP>
+__device__ __forceinline__ void wave_covariance(const float2* __restrict__ Yb, int M, int T, float* wz,
+                                                float2* wR, int lane) {
+  constexpr int W = 2 * MP;
+  constexpr int MT = W / 16;  // Gram tiles per side
+  constexpr int NT = MT * (MT + 1) / 2;
+  constexpr int LD = W <= 32 ? 48 : 80;
+  constexpr int TC = ((kWaveLds / 4) / LD) & ~3;  // snapshots per stage
+  static_assert(W <= LD && TC >= 4, "stage layout");
+  floatx4 acc[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int fi = lane & 15, fk = lane >> 4;
+  for (int t0 = 0; t0 < T; t0 += TC) {
+    const int nt = min(TC, T - t0);
+    for (int v = lane; v < TC * MP; v += 64) {
+      const int tt = v / MP, m = v - tt * MP;
+      float2 y = make_float2(0.f, 0.f);
+      if (tt < nt && m < M) y = Yb[int64_t(t0 + tt) * M + m];
+      *reinterpret_cast<float2*>(&wz[tt * LD + 2 * m]) = y;
+    }
+    wave_lds_sync();
+    for (int s = 0; s < (nt + 3) / 4; ++s) {  // staged rows past nt are zero
+      const float* row = wz + (4 * s + fk) * LD + fi;
+      float f[MT];
+#pragma unroll
+      for (int c = 0; c < MT; ++c) f[c] = row[16 * c];
+      int q = 0;
+#pragma unroll
+      for (int a = 0; a < MT; ++a)
+#pragma unroll
+        for (int b = a; b < MT; ++b, ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(f[a], f[b], acc[q], 0, 0, 0);
+    }
+    wave_lds_sync();
+  }
+  const float invT = 1.0f / float(T);
+  const bool even = (lane & 1) == 0;
+  int q = 0;
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int b = a; b < MT; ++b, ++q) {
+      const floatx4 g = acc[q];
+      floatx4 x;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) x[e] = __shfl_xor(g[e], 1, 64);  // the neighbouring (odd) Gram column
+      if (!even) continue;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int m = 8 * a + 2 * fk + h, n = 8 * b + (fi >> 1);
+        if (m >= M || n >= M || m > n) continue;
+        const float re = (g[2 * h] + x[2 * h + 1]) * invT;
+        const float im = m == n ? 0.f : (g[2 * h + 1] - x[2 * h]) * invT;
+        wR[m * M + n] = make_float2(re, im);
+        if (m != n) wR[n * M + m] = make_float2(re, -im);
+      }
+    }
+  wave_lds_sync();
+}
+
+// One packed trial (covariance route, 1-D grid) by the calling wave, in its
+// LDS region wsm.
+template <int MP>
+__device__ __forceinline__ void wave_trial(const RArgs& A, const RItem& it, const float4* __restrict__ Xg,
+                                           unsigned char* wsm, int lane) {
+  using C = RC<MP>;
+  constexpr int NBW = 8192 / (C::BLK * 4);  // column blocks per 8 KB chunk
+  constexpr int CH4 = 512;                   // float4 per chunk
+  const int M = it.M, T = it.T;
+  const float2* Yb = A.Y + it.y_off;
+
+  // 1. covariance, then U (Q right of the diagonal, half the diagonal) into
+  // the A operand of both row blocks
+  float2* wR = reinterpret_cast<float2*>(wsm);
+  wave_covariance<MP>(Yb, M, T, reinterpret_cast<float*>(wsm), wR, lane);
+  float a[C::NRB][C::KS];
+#pragma unroll
+  for (int rb = 0; rb < C::NRB; ++rb)
+#pragma unroll
+    for (int s = 0; s < C::KS; ++s) {
+      const int i = 16 * rb + (lane & 15);
+      const int k = 4 * s + (lane >> 4);
+      const bool iim = i >= MP, kim = k >= MP;
+      const int ir = iim ? i - MP : i, kr = kim ? k - MP : k;
+      float q = 0.f;
+      if (k >= i && ir < M && kr < M) {
+        const float2 r = wR[ir * M + kr];
+        q = (iim == kim) ? r.x : (iim ? r.y : -r.y);
+        if (k == i) q *= 0.5f;
+      }
+      a[rb][s] = q;
+    }
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): R is read before the DMA overwrites it
+  wave_lds_sync();
+
+  // 2. projection chunk by chunk (8 KB of the class table, the next one in
+  // flight by LDS DMA), 3. peaks gathered on the way
+  const int G = int(A.G), rows = A.rows;
+  const int nblk = (G + 15) / 16;
+  const int nch = (nblk + NBW - 1) / NBW;
+  const float scale = 2.0f / float(M * M);
+  float* Pout = A.P ? A.P + int64_t(it.trial) * A.G : nullptr;
+  float4* sx = reinterpret_cast<float4*>(wsm);  // [2][CH4]
+  auto fetch = [&](int c, int buf) {
+#pragma unroll
+    for (int f = 0; f < CH4 / 64; ++f) lds_dma16(Xg + int64_t(c) * CH4 + f * 64 + lane, sx + buf * CH4 + f * 64);
+  };
+  RangeCands rc;
+  rc.init(0, rows, it.K);
+  float vwin[1] = {0.f};
+  fetch(0, 0);
+  for (int c = 0; c < nch; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nch) {
+      fetch(c + 1, buf ^ 1);  // that buffer's reads finished at the end of chunk c - 1
+      __builtin_amdgcn_s_waitcnt(0x0F70 | (CH4 / 64));  // vmcnt(8): all but the chunk just issued
+    } else {
+      lds_dma_wait();
+    }
+    wave_lds_sync();
+    const float4* xb4 = sx + buf * CH4;
+    for (int jb = 0; jb < NBW; ++jb) {
+      const int blk = c * NBW + jb;
+      if (blk >= nblk) break;
+      const float4* bx = xb4 + jb * (C::BLK / 4);
+      const float* xf = reinterpret_cast<const float*>(bx);
+      float part = 0.f;
+#pragma unroll
+      for (int rb = 0; rb < C::NRB; ++rb) {
+        floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s4 = rb; s4 < C::KS / 4; ++s4) {  // U is zero left of the diagonal block
+          const float4 bv = lds_frag(bx, s4 * 64 + lane);
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 0], bv.x, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 1], bv.y, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 2], bv.z, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 3], bv.w, acc, 0, 0, 0);
+        }
+        // x_i (U x)_i over the row block's rows, from the same LDS block
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = rb * 16 + 4 * (lane >> 4) + r;
+          const int sidx = i >> 2;
+          part += lds_frag(xf, ((sidx >> 2) * 64 + r * 16 + (lane & 15)) * 4 + (sidx & 3)) * acc[r];
+        }
+      }
+      part += __shfl_xor(part, 16, 64);
+      part += __shfl_xor(part, 32, 64);
+      const float p = part * scale;  // every lane: column blk * 16 + lane % 16
+      const int g = blk * 16 + lane;
+      if (Pout && lane < 16 && g < G) Pout[g] = p;
+      const int qslot = blk & 3;  // this block's quarter of its 64-column window
+      if ((lane >> 4) == qslot) vwin[0] = p;
+      if (qslot == 3 || blk == nblk - 1) window_candidates<64, 1>(rc, vwin, (blk >> 2) * 64, blk < 4, lane);
+    }
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): this buffer's reads are done before it is refilled
+    wave_lds_sync();
+  }
+  finish_whole_row(rc, rows, A.wrap0, lane);
+
+  if (lane < A.kmax) {
+    const int64_t o = int64_t(it.trial) * A.kmax + lane;
+    if (rc.li == INT_MAX) {
+      A.idx[o] = -1;
+      A.val[o] = __int_as_float(0x7fc00000);
+      if (A.refined) A.refined[o * A.ndim] = __longlong_as_double(0x7ff8000000000000LL);
+    } else {
+      A.idx[o] = rc.li;
+      A.val[o] = rc.lv;
+      if (A.refined) {
+        double d0 = 0.0;
+        if (A.wrap0 || (rc.li > 0 && rc.li < rows - 1))
+          d0 = peak_parabolic(double(rc.ll), double(rc.lv), double(rc.lr));
+        A.refined[o * A.ndim] = double(rc.li) + d0;
+      }
+    }
+  }
+}
+
 // The arguments live in device memory (a pointer, not a by-value struct):
 // the per-trial routine takes them by reference, which would otherwise force
 // a private copy of the whole struct.
@@ -585,7 +794,23 @@ __global__ __launch_bounds__(kThreads, 1) void k_ragged(const RArgs* __restrict_
     __syncthreads();
     const int t = s_ticket;
     __syncthreads();
-    if (t >= A.n_items) break;  // uniform: every wave leaves
+    if (t >= A.n_units) break;  // uniform: every wave leaves
+    if (t >= A.n_wg_items) {
+      // eight packed trials, one per wave
+      const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+      const int i = A.n_wg_items + (t - A.n_wg_items) * (kThreads / 64) + wave;
+      if (i < A.n_items) {
+        const RItem it = A.items[i];
+        unsigned char* wsm = smem + wave * kWaveLds;
+        switch (__builtin_amdgcn_readfirstlane(it.cls)) {
+          case 0: wave_trial<8>(A, it, A.X[0], wsm, lane); break;
+          case 1: wave_trial<16>(A, it, A.X[1], wsm, lane); break;
+          default: wave_trial<32>(A, it, A.X[2], wsm, lane); break;
+        }
+      }
+      __syncthreads();  // the next ticket may use the LDS as a whole
+      continue;
+    }
     const RItem it = A.items[t];
     // class parameters picked with constant indices (no local copy of the arguments)
     switch (it.cls) {

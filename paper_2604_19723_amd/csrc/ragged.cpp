@@ -35,6 +35,8 @@ struct Ragged {
   float4* X[kRaggedClasses] = {};
   int nchunk[kRaggedClasses] = {};
   int wr[kRaggedClasses] = {1, 1, 2, 4, 8};
+  bool pack[kRaggedPackClasses] = {true, true, true};  // small classes one trial per wave (tuned)
+  int n_wg_items = 0;                            // of the uploaded full batch
   std::map<std::pair<int, int>, int> route_table;  // (class, log2 T bucket) -> route
   RItem* d_items = nullptr;
   RArgs* d_args = nullptr;        // arguments of the captured launch (device copy)
@@ -75,8 +77,22 @@ double cost_of(const Ragged& r, size_t i, int route) {
   return 8.0 * Mp * Mp * G + 2.0 * 4.0 * double(d.n_elem) * d.n_elem * d.n_snap;
 }
 
-std::vector<RItem> make_items(const Ragged& r, const std::vector<size_t>& which,
-                              const int* force_route) {
+// Items in processing order: whole-workgroup items longest first, then the
+// packed ones (longest first among themselves, eight per ticket).
+struct ItemList {
+  std::vector<RItem> items;
+  int n_wg = 0;
+};
+
+// A trial runs packed when its class is packed, it takes the covariance route
+// and the grid is 1-D (the packed path keeps no spectrum row).
+bool packed(const Ragged& r, const RItem& it, bool force_wg) {
+  return !force_wg && it.cls < kRaggedPackClasses && r.pack[it.cls] && it.route == kRouteCov &&
+         r.plan->shape1 == 1;
+}
+
+ItemList make_items(const Ragged& r, const std::vector<size_t>& which, const int* force_route,
+                    bool force_wg = false) {
   std::vector<RItem> items;
   items.reserve(which.size());
   std::vector<double> cost;
@@ -97,15 +113,23 @@ std::vector<RItem> make_items(const Ragged& r, const std::vector<size_t>& which,
   std::vector<size_t> ord(items.size());
   for (size_t i = 0; i < ord.size(); ++i) ord[i] = i;
   std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
-  std::vector<RItem> out(items.size());
-  for (size_t i = 0; i < ord.size(); ++i) out[i] = items[ord[i]];
+  // whole-workgroup items first; the order within each group is kept
+  std::stable_partition(ord.begin(), ord.end(), [&](size_t a) { return !packed(r, items[a], force_wg); });
+  ItemList out;
+  out.items.resize(items.size());
+  for (size_t i = 0; i < ord.size(); ++i) {
+    out.items[i] = items[ord[i]];
+    if (!packed(r, out.items[i], force_wg)) out.n_wg = int(i) + 1;
+  }
   return out;
 }
 
-RArgs make_args(const Ragged& r, const RItem* d_items, int n) {
+RArgs make_args(const Ragged& r, const RItem* d_items, int n, int n_wg_items) {
   RArgs a{};
   a.items = d_items;
   a.n_items = n;
+  a.n_wg_items = n_wg_items;
+  a.n_units = n_wg_items + (n - n_wg_items + kRaggedPackWaves - 1) / kRaggedPackWaves;
   a.Y = r.Y;
   for (int c = 0; c < kRaggedClasses; ++c) {
     a.X[c] = r.X[c];
@@ -126,9 +150,9 @@ RArgs make_args(const Ragged& r, const RItem* d_items, int n) {
   return a;
 }
 
-hipError_t upload_items(Ragged& r, const std::vector<RItem>& items) {
-  hipError_t e = hipMemcpy(r.d_items, items.data(), items.size() * sizeof(RItem), hipMemcpyHostToDevice);
-  return e;
+hipError_t upload_items(Ragged& r, const ItemList& list) {
+  r.n_wg_items = list.n_wg;
+  return hipMemcpy(r.d_items, list.items.data(), list.items.size() * sizeof(RItem), hipMemcpyHostToDevice);
 }
 
 hipError_t capture(Ragged& r) {
@@ -140,7 +164,7 @@ hipError_t capture(Ragged& r) {
     (void)hipGraphDestroy(r.graph);
     r.graph = nullptr;
   }
-  const RArgs a = make_args(r, r.d_items, int(r.desc.size()));
+  const RArgs a = make_args(r, r.d_items, int(r.desc.size()), r.n_wg_items);
   hipError_t e = hipMemcpy(r.d_args, &a, sizeof(RArgs), hipMemcpyHostToDevice);
   if (e != hipSuccess) return e;
   e = hipStreamBeginCapture(r.cap, hipStreamCaptureModeThreadLocal);
@@ -155,7 +179,8 @@ hipError_t capture(Ragged& r) {
 }
 
 // one direct (uncaptured) launch over a subset, timed with events
-hipError_t time_subset(Ragged& r, const std::vector<RItem>& items, int repeats, float* ms) {
+hipError_t time_subset(Ragged& r, const ItemList& list, int repeats, float* ms) {
+  const std::vector<RItem>& items = list.items;
   RItem* d = nullptr;
   hipError_t e = hipMalloc(&d, std::max<size_t>(1, items.size()) * sizeof(RItem));
   if (e != hipSuccess) return e;
@@ -163,9 +188,9 @@ hipError_t time_subset(Ragged& r, const std::vector<RItem>& items, int repeats, 
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
-  const RArgs a = make_args(r, d, int(items.size()));
+  const RArgs a = make_args(r, d, int(items.size()), list.n_wg);
   if (e == hipSuccess) e = hipMemcpy(r.d_args_probe, &a, sizeof(RArgs), hipMemcpyHostToDevice);
-  const int nwg = std::min<int>(r.n_wg, int(items.size()));
+  const int nwg = std::max(1, std::min<int>(r.n_wg, a.n_units));
   float best = 1e30f;
   for (int rep = 0; e == hipSuccess && rep < repeats + 1; ++rep) {
     e = launch_ragged_reset(r.d_counter, r.cap);
@@ -375,7 +400,7 @@ ba_status ba_ragged_autotune(ba_ragged r, const char* cache_path, int32_t repeat
       continue;
     }
     const int cov = kRouteCov;
-    const std::vector<RItem> items = make_items(*r, which, &cov);
+    const ItemList items = make_items(*r, which, &cov, /*force_wg=*/true);
     float best = 1e30f;
     int best_wr = r->wr[c];
     for (int o = 0; e == hipSuccess && o < no; ++o) {
@@ -390,7 +415,31 @@ ba_status ba_ragged_autotune(ba_ragged r, const char* cache_path, int32_t repeat
     r->wr[c] = best_wr;
     cache[key] = best_wr;
   }
-  // 2. routes per (size class, snapshot-count bucket) where both routes exist
+  // 2. small classes: one trial per wave (packed) or per workgroup; the probe
+  // holds up to 4 * kRaggedPackWaves * max_probe trials, so that both layouts
+  // fill as many workgroups and a packed workgroup gets several tickets (in a
+  // single round it would wait for the longest of its eight trials)
+  for (int c = 0; e == hipSuccess && c < kRaggedPackClasses; ++c) {
+    if (r->plan->shape1 != 1) break;  // the packed path needs a 1-D grid
+    std::vector<size_t> which;
+    for (size_t i = 0; i < n && int(which.size()) < 4 * kRaggedPackWaves * max_probe; ++i)
+      if (r->cls[i] == c) which.push_back(i);
+    if (which.empty()) continue;
+    const std::string key = dev + "|pack|" + std::to_string(c);
+    if (cache.count(key)) {
+      r->pack[c] = cache[key] != 0;
+      continue;
+    }
+    const int cov = kRouteCov;
+    float t[2] = {0.f, 0.f};
+    for (int pk = 0; e == hipSuccess && pk < 2; ++pk) {
+      r->pack[c] = pk != 0;
+      e = time_subset(*r, make_items(*r, which, &cov), repeats, &t[pk]);
+    }
+    r->pack[c] = t[1] < t[0];
+    cache[key] = r->pack[c] ? 1 : 0;
+  }
+  // 3. routes per (size class, snapshot-count bucket) where both routes exist
   for (int c = 0; e == hipSuccess && c < kRaggedClasses; ++c) {
     std::map<int, std::vector<size_t>> buckets;
     for (size_t i = 0; i < n; ++i)
@@ -428,6 +477,13 @@ ba_status ba_ragged_autotune(ba_ragged r, const char* cache_path, int32_t repeat
 ba_status ba_ragged_config(ba_ragged r, int32_t* wr_per_class) {
   if (!r || !wr_per_class) return rg_arg("ba_ragged_config", "null argument");
   for (int c = 0; c < kRaggedClasses; ++c) wr_per_class[c] = r->wr[c];
+  return BA_OK;
+}
+
+ba_status ba_ragged_packed(ba_ragged r, int32_t* packed_per_class) {
+  if (!r || !packed_per_class) return rg_arg("ba_ragged_packed", "null argument");
+  for (int c = 0; c < kRaggedClasses; ++c)
+    packed_per_class[c] = (c < kRaggedPackClasses && r->pack[c] && r->plan->shape1 == 1) ? 1 : 0;
   return BA_OK;
 }
 

@@ -11,6 +11,8 @@ constexpr int kRaggedClasses = 5;      // padded element counts 8, 16, 32, 64, 1
 constexpr int kRaggedMaxPeaks = 8;
 constexpr int kRaggedMaxGrid = 16384;  // the spectrum row of one trial lives in LDS
 constexpr int kRaggedLds = 152 * 1024;   // dynamic LDS of the persistent kernel
+constexpr int kRaggedPackWaves = 8;      // packed trials per workgroup ticket (one per wave)
+constexpr int kRaggedPackClasses = 3;    // classes that can run packed (up to 32 elements)
 
 enum { kRouteCov = 0, kRouteSnap = 1 };
 
@@ -24,8 +26,10 @@ struct RItem {
 };
 
 struct RArgs {
-  const RItem* items;
+  const RItem* items;      // whole-workgroup items first, then the packed ones
   int32_t n_items;
+  int32_t n_wg_items;      // items taken one per ticket by a whole workgroup
+  int32_t n_units;         // tickets: n_wg_items + ceil(packed / waves per workgroup)
   const float2* Y;
   const float4* X[kRaggedClasses];   // per-class steering tables (fragment order)
   int32_t nchunk[kRaggedClasses];    // 32 KB chunks per class table that hold grid points

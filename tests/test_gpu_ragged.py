@@ -21,9 +21,10 @@ def ragged_plan(G=3601, M=128):
     return bb.ba_plan_create(M, wl.ula_positions(M), bb.BA_GRID_ULA_DEG, G, wl.ula_grid(G), G, 1, 0)
 
 
-def run(rs, route=bb.BA_ROUTE_AUTO, autotune=None, replays=1):
+def run(rs, route=bb.BA_ROUTE_AUTO, autotune=None, replays=1, plan=None):
     B, G = rs.n_trials, len(rs.grid)
-    plan = ragged_plan(G)
+    own_plan = plan is None
+    plan = ragged_plan(G) if own_plan else plan
     Y = torch.from_numpy(rs.pool_c64()).to(DEV)
     P = torch.full((B, G), -1.0, dtype=torch.float32, device=DEV)
     idx = torch.empty((B, KMAX), dtype=torch.int32, device=DEV)
@@ -43,29 +44,34 @@ def run(rs, route=bb.BA_ROUTE_AUTO, autotune=None, replays=1):
             (x @ x).sum().item()
         routes = bb.ba_ragged_routes(r)
         cfg = bb.ba_ragged_config(r)
-    plan.close()
+        packed = bb.ba_ragged_packed(r)
+    if own_plan:
+        plan.close()
     P, idx, val, ref = [t.cpu().numpy() for t in outs[0]]
-    return dict(P=P, idx=idx, val=val, ref=ref, routes=routes, cfg=cfg, outs=outs)
+    return dict(P=P, idx=idx, val=val, ref=ref, routes=routes, cfg=cfg, packed=packed, outs=outs)
 
 
-def check(rs, o, fp64_peaks=True):
+def check(rs, o, fp64_peaks=True, positions=None, grid_kind=ob.GRID_ULA_DEG, wrap0=0):
+    """Every trial against the oracle on the plan's first M elements
+    (positions: the plan's [M_plan][3] geometry; default the ULA)."""
     pool = rs.pool_c64().astype(np.complex128)
     bad, ncmp = [], 0
     emax = 0.0
     for i in range(rs.n_trials):
         M, T, K = int(rs.n_elem[i]), int(rs.n_snap[i]), int(rs.k[i])
         Yi = pool[rs.y_offset[i]:rs.y_offset[i] + M * T].reshape(T, M)
-        A = ob.steering(wl.ula_positions(M), ob.directions(ob.GRID_ULA_DEG, rs.grid))
+        pos = wl.ula_positions(M) if positions is None else positions[:M]
+        A = ob.steering(pos, ob.directions(grid_kind, rs.grid))
         Pref = ob.spectrum(ob.covariance(Yi), A)
         e = normwise_err(o["P"][i][None], Pref[None])[0]
         emax = max(emax, e)
         assert e <= 1e-5, (i, M, T, K, e, o["routes"][i])
         G = len(rs.grid)
         check_peaks_same_precision(o["P"][i][None], o["idx"][i][None, :K], o["val"][i][None, :K],
-                                   o["ref"][i][None, :K], K, (G, 1), 0)
+                                   o["ref"][i][None, :K], K, (G, 1), wrap0)
         assert np.all(o["idx"][i, K:] == -1) and np.all(np.isnan(o["val"][i, K:]))
         if fp64_peaks:
-            n, _, b = peak_agreement_fp64(Pref[None], o["idx"][i][None, :K], K, (G, 1), 0, 1e-5)
+            n, _, b = peak_agreement_fp64(Pref[None], o["idx"][i][None, :K], K, (G, 1), wrap0, 1e-5)
             ncmp += n
             bad += b
     assert not bad, bad[:3]
@@ -179,3 +185,64 @@ def test_rebinding_buffers_retargets_the_graph():
     o = dict(P=ra[0].cpu().numpy(), idx=ra[1].cpu().numpy(), val=ra[2].cpu().numpy(), ref=ra[3].cpu().numpy(),
              routes=routes)
     check(rs, o)
+
+
+def _with_pack(cache, value):
+    """Rewrite the packing choices in an autotune cache file to `value`."""
+    lines = []
+    for line in open(cache).read().splitlines():
+        key, v = line.rsplit(" ", 1)
+        lines.append("%s %d" % (key, value) if "|pack|" in key else line)
+    open(cache, "w").write("\n".join(lines) + "\n")
+
+
+def test_packed_and_whole_workgroup_small_trials_agree(tmp_path):
+    """The 8-, 16- and 32-element classes run packed (one trial per wave) or
+    one per workgroup, as the autotune cache says: both against the oracle,
+    and spectra within the sum of the two parity gates."""
+    rs = wl.config4(500, first_trial=20000)
+    keep = [i for i in range(rs.n_trials) if rs.n_elem[i] <= 32]
+    rs = _subset(rs, keep)
+    print("small trials:", rs.n_trials, flush=True)
+    cache = str(tmp_path / "tune.txt")
+    o_tuned = run(rs, autotune=cache)
+    assert "|pack|" in open(cache).read()
+    runs = {}
+    for value in (0, 1):
+        _with_pack(cache, value)
+        o = run(rs, autotune=cache)
+        assert list(o["packed"][:3]) == [value] * 3, o["packed"]
+        check(rs, o)
+        runs[value] = o
+    d = np.abs(runs[0]["P"].astype(np.float64) - runs[1]["P"]).max(axis=1) / runs[0]["P"].max(axis=1)
+    assert d.max() <= 2e-5, d.max()  # each within 1e-5 of the oracle
+    del o_tuned
+
+
+@pytest.mark.parametrize("wrap0", [0, 1, 2])
+def test_packed_trials_on_a_wrapping_direction_grid(wrap0):
+    """Packed trials on a 1-D azimuth circle (wrap of the row, and a
+    duplicated last direction with wrap0 = 2): the end columns of the row
+    are maxima or not by the wrapped rule."""
+    G, Mp = 721, 32
+    az = np.linspace(0.0, 2 * np.pi, G, endpoint=(wrap0 == 2))
+    dirs = np.stack([np.cos(az), np.sin(az), np.zeros_like(az)], axis=1)
+    rng = np.random.default_rng(41 + wrap0)
+    pos = np.zeros((Mp, 3))
+    pos[:, 0] = 0.5 * np.arange(Mp)
+    pos[:, 1] = 0.25 * rng.standard_normal(Mp)   # not symmetric about the x axis
+    Ms = [1, 2, 5, 8, 9, 12, 16, 16, 3, 16, 7, 14, 17, 32, 25, 32]
+    Ts = [40, 3, 300, 20, 64, 1000, 17, 2048, 100, 33, 9, 128, 50, 700, 2, 31]
+    Ks = [1, 2, 3, 8, 4, 5, 6, 2, 1, 8, 3, 7, 4, 8, 2, 5]
+    blocks = [(rng.standard_normal((T, M)) + 1j * rng.standard_normal((T, M))).reshape(-1)
+              for M, T in zip(Ms, Ts)]
+    sizes = np.array([b.size for b in blocks], np.int64)
+    off = np.zeros(len(Ms), np.int64)
+    off[1:] = np.cumsum(sizes)[:-1]
+    rs = wl.RaggedSet(pool=np.concatenate(blocks), y_offset=off, n_elem=np.array(Ms, np.int32),
+                      n_snap=np.array(Ts, np.int32), k=np.array(Ks, np.int32), truth=[None] * len(Ms),
+                      snr_db=np.zeros(len(Ms)), grid=dirs)
+    with bb.ba_plan_create(Mp, pos, bb.BA_GRID_DIRS, G, dirs, G, 1, wrap0) as plan:
+        o = run(rs, route=bb.BA_ROUTE_COV, plan=plan)
+    assert list(o["packed"][:3]) == [1, 1, 1]
+    check(rs, o, fp64_peaks=False, positions=pos, grid_kind=ob.GRID_DIRS, wrap0=wrap0)
