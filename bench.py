@@ -444,6 +444,8 @@ def bench_ragged(args, workers):
         bb.ba_ragged_autotune(r, None, repeats=2, max_probe=256)   # tuned afresh on every run
         log("autotuned in %.1f s: waves along rows per class %s" % (time.perf_counter() - t, bb.ba_ragged_config(r)))
     routes = bb.ba_ragged_routes(r)
+    packed = bb.ba_ragged_packed(r)
+    log("classes run one trial per wave: %s" % [8 << c for c in range(5) if packed[c]])
     for _ in range(args.warmup):
         bb.ba_ragged_launch(r)
     torch.cuda.synchronize()
@@ -486,7 +488,8 @@ def bench_ragged(args, workers):
         "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded signal model, uneven ULA trials)",
         "config": {"workload": rs.name, "trials": n, "n_grid": G, "kmax": kmax,
-                   "snapshot_route_trials": int(snap.sum()), "autotuned": not args.no_autotune},
+                   "snapshot_route_trials": int(snap.sum()), "autotuned": not args.no_autotune,
+                   "packed_classes": [8 << c for c in range(5) if packed[c]]},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": 157.3, "unit": "TFLOP/s",
                      "frac": achieved / 157.3, "traffic": None, "kernel": "persistent ragged kernel",
                      "kernel_ms": kms, "flops_per_launch": float(flops)},
