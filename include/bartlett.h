@@ -174,11 +174,13 @@ ba_status ba_peaks(ba_plan p, int32_t n_trials, const float* P, int32_t k, int32
  * neighbour values, plus the values at the range's two ends; ba_peaks_merge
  * then finishes the pick per trial. The spectrum is not re-read, and not
  * written at all when P is NULL.
- * FP32 plans of up to 64 elements on 1-D grids only (BA_ERR_UNSUPPORTED
- * otherwise, from all three calls).
+ * Plans of up to 64 elements on 1-D grids in BA_PREC_F32, BA_PREC_BF16X3 or
+ * BA_PREC_BF16 (the register-resident kernels) only; BA_ERR_UNSUPPORTED
+ * otherwise, from all three calls.
  *   R      dev c64 [B][M][M] (ba_covariance).
  *   k      1 <= k <= 16; the same k must reach ba_peaks_merge.
- *   P      dev float [B][G] or NULL; when given, bit-identical to ba_spectrum.
+ *   P      dev float [B][G] or NULL; when given, bit-identical to ba_spectrum
+ *          of the same plan.
  *   cand   dev, >= ba_candidates_size(p, B, k) bytes, 16-byte aligned; opaque
  *          records owned by the caller, every byte of the sized part written.
  */

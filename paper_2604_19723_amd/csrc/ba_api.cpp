@@ -448,7 +448,7 @@ ba_status ba_candidates_size(ba_plan p, int32_t n_trials, int32_t k, size_t* byt
   if (n_trials < 0) return arg_error(fn, "n_trials >= 0 required");
   if (k < 1 || k > kMaxPeaks) return arg_error(fn, "k must be in [1, 16]");
   if (!candidates_supported(q)) {
-    set_error(std::string(fn) + ": FP32 plans of up to 64 elements on 1-D grids only");
+    set_error(std::string(fn) + ": plans of up to 64 elements on 1-D grids in FP32, BF16x3 or BF16 only");
     return BA_ERR_UNSUPPORTED;
   }
   *bytes = candidate_bytes(q, n_trials, k);

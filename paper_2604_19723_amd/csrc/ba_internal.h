@@ -62,10 +62,11 @@ hipError_t launch_peaks(const Plan& p, int B, const float* P, int k, int* idx, f
                         double* refined, hipStream_t s, const int* count = nullptr);
 hipError_t launch_moments(const Plan& p, int B, const float* P, double* mu_cov, hipStream_t s);
 
-// Peak candidates from the projection epilogue (FP32 register-resident path,
-// 1-D grids): each trial's candidate rows are cut into nsplit column ranges of
-// `span` columns (the last one shorter); every range leaves k + 1 float4
-// records (its top-k interior maxima, then the values at its two ends).
+// Peak candidates from the projection epilogue (the register-resident paths
+// of up to 64 elements, FP32 or the BF16 splits, on 1-D grids): each trial's
+// candidate rows are cut into nsplit column ranges of `span` columns (the
+// last one shorter); every range leaves k + 1 float4 records (its top-k
+// interior maxima, then the values at its two ends).
 constexpr int kMaxCandRanges = 64;
 struct CandLayout {
   int nsplit = 1;    // column ranges per trial
@@ -80,6 +81,10 @@ hipError_t launch_spectrum_candidates(const Plan& p, int B, const float2* R, flo
                                       hipStream_t s);
 hipError_t launch_peaks_merge(const Plan& p, int B, int k, const float4* rec, int* idx, float* val,
                               double* refined, hipStream_t s);
+// the BF16 register-resident kernel's column split (trial pairs) and its candidate variant
+void qb_split(const Plan& p, int B, int max_split, int* nsplit, int* per);
+hipError_t launch_spectrum_qb_candidates(const Plan& p, int B, const float2* R, float* P, int k, float4* rec,
+                                         hipStream_t s);
 
 // residual covariance R~ = Pi R Pi (Psi given as vectors [B][S][M], or as grid
 // indices gidx[b * ld + s] into the plan's steering table, -1 = no column)

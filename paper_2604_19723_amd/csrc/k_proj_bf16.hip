@@ -21,6 +21,15 @@
 // registers of hi/lo fragments leave room for two waves per SIMD; the
 // workgroup builds them in LDS first, so no wave holds conversion
 // temporaries beside them (no spills).
+//
+// Candidate variant (1-D grids): after each chunk's barrier wave t holds trial
+// t's 64 new spectrum values, one per lane, which is one window of the peak
+// rule of k_proj_qc (cand_window.h); the spectrum is written only when the
+// caller asks for it.
+#include <algorithm>
+#include <climits>
+
+#include "cand_window.h"
 #include "proj_common.h"
 
 namespace ba {
@@ -57,19 +66,26 @@ __device__ __forceinline__ unsigned short bf16_bits(float x) {
 __device__ __forceinline__ float lo_half(unsigned w) { return __uint_as_float(w << 16); }
 __device__ __forceinline__ float hi_half(unsigned w) { return __uint_as_float(w & 0xffff0000u); }
 
-template <int PREC>
+// CAND: P may be null; rows = candidate rows of the grid; rec = candidate
+// records [B][nsplit][k + 1] as k_proj_qc writes them
+template <int PREC, bool CAND = false>
 __global__ __launch_bounds__(256, 2) void k_proj_qb(const float2* __restrict__ R, const uint4* __restrict__ Xb,
                                                     float* __restrict__ P, int B, int M, int64_t G, int nchunk,
-                                                    int chunks_per_wg, int nsplit) {
+                                                    int chunks_per_wg, int nsplit, int rows = 0, int k = 0,
+                                                    float4* __restrict__ rec = nullptr) {
   extern __shared__ __attribute__((aligned(16))) uint4 sXb[];  // [2][CHW], LDS DMA
   __shared__ float red[2][NTW][WRB][NBB * 16];
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wr = wave % WRB, wc = wave / WRB;  // row wave, column half
   const int64_t pair = blockIdx.x / nsplit;
-  const int c0 = (blockIdx.x % nsplit) * chunks_per_wg;
+  const int sp = int(blockIdx.x % nsplit);
+  const int c0 = sp * chunks_per_wg;
   const int c1 = min(c0 + chunks_per_wg, nchunk);
-  if (c0 >= c1) return;
+  static_assert(NBB * 16 == 64, "a chunk is one 64-column window");
+  RangeCands rc;  // wave t < NTW: trial t's candidates over this column range
+  if (CAND) rc.init(c0 * 64, min(c1 * 64, rows), k);
+  if (c0 >= c1) return;  // never: the host sets nsplit = ceil(nchunk / chunks_per_wg)
 
   // A operand hi/lo of U for both trials: slot j, k-step kc >= slot_kc0(j):
   // rows i = 16 slot_rb(j, wr) + lane%16, k = 32 kc + 8 (lane/16) + e. The
@@ -192,13 +208,61 @@ __global__ __launch_bounds__(256, 2) void k_proj_qb(const float2* __restrict__ R
       const int t = threadIdx.x % (NBB * 16), tw = threadIdx.x / (NBB * 16);
       const int64_t bo = pair * NTW + tw;
       const int64_t g = int64_t(c) * NBB * 16 + t;
-      if (bo < B && g < G) P[bo * G + g] = (red[buf][tw][0][t] + red[buf][tw][1][t]) * scale;
+      const float v = (red[buf][tw][0][t] + red[buf][tw][1][t]) * scale;
+      if (CAND) {
+        float vw[1] = {v};
+        if (P && bo < B && g < G) P[bo * G + g] = v;
+        window_candidates<64, 1>(rc, vw, c * 64, c == c0, lane);  // wave tw, trial tw
+      } else if (bo < B && g < G) {
+        P[bo * G + g] = v;
+      }
     }
   }
 #undef BA_FETCH
+  if (CAND && wave < NTW) {
+    const int64_t bo = pair * NTW + wave;
+    if (bo < B) {
+      float4* o = rec + (bo * nsplit + sp) * (k + 1);
+      if (lane < k) o[lane] = make_float4(rc.lv, __int_as_float(rc.li), rc.ll, rc.lr);
+      if (lane == 0) o[k] = make_float4(rc.e[0], rc.e[1], rc.e[2], rc.e[3]);
+    }
+  }
 }
 
 }  // namespace
+
+// column ranges per trial pair: split until there are 2048 workgroups, at
+// most max_split ranges
+void qb_split(const Plan& p, int B, int max_split, int* nsplit_out, int* per_out) {
+  const int nchunk = int((p.Gb + NBB - 1) / NBB);
+  const int64_t pairs = (int64_t(std::max(B, 1)) + NTW - 1) / NTW;
+  int nsplit = 1;
+  while (pairs * nsplit < 2048 && nsplit < nchunk && 2 * nsplit <= max_split) nsplit *= 2;
+  const int per = (nchunk + nsplit - 1) / nsplit;
+  *per_out = per;
+  *nsplit_out = (nchunk + per - 1) / per;
+}
+
+hipError_t launch_spectrum_qb_candidates(const Plan& p, int B, const float2* R, float* P, int k, float4* rec,
+                                         hipStream_t s) {
+  if (p.Mp != MPB || !p.d_Xb) return hipErrorInvalidValue;
+  if (B == 0) return hipSuccess;
+  const int nchunk = int((p.Gb + NBB - 1) / NBB);
+  if (int64_t(nchunk) * NBB > p.Xblocks) return hipErrorInvalidValue;
+  const CandLayout L = candidate_layout(p, B);
+  if (L.span != int64_t(L.per) * NBB * 16) return hipErrorInvalidValue;
+  const int64_t nblk = (int64_t(B) + NTW - 1) / NTW * L.nsplit;
+  if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+  const size_t lds = 2 * CHW * sizeof(uint4);
+  const uint4* Xb = reinterpret_cast<const uint4*>(p.d_Xb);
+  if (p.precision == BA_PREC_BF16X3)
+    hipLaunchKernelGGL((k_proj_qb<BA_PREC_BF16X3, true>), dim3(unsigned(nblk)), dim3(256), lds, s, R, Xb, P, B, p.M,
+                       p.G, nchunk, L.per, L.nsplit, p.rows, k, rec);
+  else
+    hipLaunchKernelGGL((k_proj_qb<BA_PREC_BF16, true>), dim3(unsigned(nblk)), dim3(256), lds, s, R, Xb, P, B, p.M,
+                       p.G, nchunk, L.per, L.nsplit, p.rows, k, rec);
+  return hipGetLastError();
+}
 
 hipError_t launch_spectrum_qb(const Plan& p, int B, const float2* R, float* P, hipStream_t s) {
   if (p.Mp != MPB || !p.d_Xb) return hipErrorInvalidValue;
@@ -207,10 +271,8 @@ hipError_t launch_spectrum_qb(const Plan& p, int B, const float2* R, float* P, h
   const int nchunk = int((p.Gb + NBB - 1) / NBB);
   if (int64_t(nchunk) * NBB > p.Xblocks) return hipErrorInvalidValue;
   const int64_t pairs = (int64_t(B) + NTW - 1) / NTW;
-  int nsplit = 1;
-  while (pairs * nsplit < 2048 && nsplit < nchunk) nsplit *= 2;
-  const int per = (nchunk + nsplit - 1) / nsplit;
-  nsplit = (nchunk + per - 1) / per;
+  int nsplit = 1, per = nchunk;
+  qb_split(p, B, INT_MAX, &nsplit, &per);
   const int64_t nblk = pairs * nsplit;
   if (nblk > 0x7fffffff) return hipErrorInvalidValue;
   const size_t lds = 2 * CHW * sizeof(uint4);

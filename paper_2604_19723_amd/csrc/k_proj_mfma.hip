@@ -258,13 +258,20 @@ hipError_t launch_qc(const Plan& p, int B, const float2* R, float* P, int k, flo
 }  // namespace
 
 bool candidates_supported(const Plan& p) {
-  return p.precision == BA_PREC_F32 && p.Mp <= 64 && p.shape1 == 1;
+  if (p.shape1 != 1) return false;
+  if (p.precision == BA_PREC_F32) return p.Mp <= 64;
+  return (p.precision == BA_PREC_BF16X3 || p.precision == BA_PREC_BF16) && p.Mp == 64 && p.d_Xb;
 }
 
 CandLayout candidate_layout(const Plan& p, int B) {
+  CandLayout L{};
+  if (p.precision != BA_PREC_F32) {  // k_proj_qb: 64-column chunks, ranges per trial pair
+    qb_split(p, B, kMaxCandRanges, &L.nsplit, &L.per);
+    L.span = int64_t(L.per) * 64;
+    return L;
+  }
   const int nb = 64 / p.Mp;  // 16-column blocks per chunk (8 KB of steering)
   const int nchunk = int((p.Gb + nb - 1) / nb);
-  CandLayout L{};
   split_columns(nchunk, std::max(B, 1), kMaxCandRanges, &L.nsplit, &L.per);
   L.span = int64_t(L.per) * nb * 16;
   return L;
@@ -276,6 +283,7 @@ size_t candidate_bytes(const Plan& p, int B, int k) {
 
 hipError_t launch_spectrum_candidates(const Plan& p, int B, const float2* R, float* P, int k, float4* rec,
                                       hipStream_t s) {
+  if (p.precision != BA_PREC_F32) return launch_spectrum_qb_candidates(p, B, R, P, k, rec, s);
   switch (p.Mp) {
     case 8: return launch_qc<8>(p, B, R, P, k, rec, s);
     case 16: return launch_qc<16>(p, B, R, P, k, rec, s);

@@ -5,8 +5,9 @@ Gates: P bit-identical to ba_spectrum; idx, val and refined bit-identical to
 ba_peaks on that P; and the oracle's peak rule on the same FP32 values gives
 the same indices and values, with its FP64 refinement within 1e-12. Sizes span
 one to 64 column ranges per trial, ragged chunk tails, every padded element
-count of the register-resident kernel (8, 16, 32, 64), wrap0 = 0, 1 and 2,
-k = 1 to 16, and degenerate spectra (all zero: one plateau; NaN)."""
+count of the FP32 register-resident kernel (8, 16, 32, 64) and the BF16
+split kernel (two trials per workgroup), wrap0 = 0, 1 and 2, k = 1 to 16,
+and degenerate spectra (all zero: one plateau; NaN)."""
 import numpy as np
 import pytest
 
@@ -20,14 +21,14 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda"
 
 
-def plan_dirs_1d(M, G, wrap0):
+def plan_dirs_1d(M, G, wrap0, precision=bb.BA_PREC_F32):
     """Line array along x (half-wavelength spacing), azimuth sweep as a 1-D
     direction grid; wrap0 = 2 repeats the first direction at the end."""
     az = np.linspace(0.0, 2 * np.pi, G, endpoint=(wrap0 == 2))
     dirs = np.stack([np.cos(az), np.sin(az), np.zeros_like(az)], axis=1)
     pos = np.zeros((M, 3))
     pos[:, 0] = 0.5 * np.arange(M)
-    return bb.ba_plan_create(M, pos, bb.BA_GRID_DIRS, G, dirs, G, 1, wrap0)
+    return bb.ba_plan_create(M, pos, bb.BA_GRID_DIRS, G, dirs, G, 1, wrap0, precision)
 
 
 def noise_snapshots(B, T, M, seed):
@@ -133,14 +134,36 @@ def test_candidates_degenerate_spectra(M, wrap0):
     assert idx[1].tolist() == [-1] * K  # NaN compares false
 
 
+@pytest.mark.parametrize("precision", [bb.BA_PREC_BF16X3, bb.BA_PREC_BF16])
+@pytest.mark.parametrize("M", [5, 64])
+@pytest.mark.parametrize("G", [1, 2, 17, 1000, 7201])
+@pytest.mark.parametrize("wrap0", [0, 1, 2])
+def test_split_precision_candidates_match_staged_path(precision, M, G, wrap0):
+    """The BF16 register-resident kernel (two trials per workgroup, 64-column
+    windows): odd batches (a pair with one trial), one range per pair up to
+    the 64-range cap, against its own staged spectrum and ba_peaks."""
+    rows = G - 1 if wrap0 == 2 else G
+    if wrap0 and rows < 3:
+        pytest.skip("a plan rejects a wrapping dimension with a period below 3")
+    with plan_dirs_1d(M, G, wrap0, precision) as plan:
+        for B, K in ((1, 16), (5, 4), (2, 1)):
+            Y = noise_snapshots(B, 2 * M, M, 6007 * M + 37 * G + wrap0 + B + precision)
+            R = torch.empty((B, M, M), dtype=torch.complex64, device=DEV)
+            bb.ba_covariance(plan, B, 2 * M, Y, R)
+            check_against_staged_and_oracle(plan, B, R, K, wrap0)
+
+
 def test_unsupported_plans_are_rejected():
     ts = wl.config3(1)
     with bb.plan_for(ts) as plan:   # 2-D grid
         with pytest.raises(bb.BartlettError) as e:
             bb.ba_candidates_size(plan, 1, 3)
         assert e.value.status == bb.BA_ERR_UNSUPPORTED
-    ts = wl.config2(1)
-    with bb.plan_for(ts, bb.BA_PREC_BF16X3) as plan:
+    with plan_dirs_1d(100, 500, 0, bb.BA_PREC_BF16X3) as plan:   # streamed kernel (more than 64 elements)
+        with pytest.raises(bb.BartlettError) as e:
+            bb.ba_candidates_size(plan, 1, 4)
+        assert e.value.status == bb.BA_ERR_UNSUPPORTED
+    with plan_dirs_1d(8, 500, 0, bb.BA_PREC_F32_VALU) as plan:   # vector-ALU reference
         with pytest.raises(bb.BartlettError) as e:
             bb.ba_candidates_size(plan, 1, 4)
         assert e.value.status == bb.BA_ERR_UNSUPPORTED
