@@ -212,7 +212,13 @@ def bench_sequential(args, workers):
     torch.cuda.synchronize()
     est_p = metrics.fractional_index_to_deg(ts.grid_kind, ts.grid, ts.grid_shape, out["refined"].cpu().numpy())
     rmse_plain, fails_plain = rmse_by_snr(ts, est_p, out["idx"].cpu().numpy())
-    flops = float(B) * K * G * proj_flops_per_point(M, proj_kernel_name(args.precision, M))
+    try:
+        bb.ba_candidates_size(plan, B, 1)
+        cand = True   # each pass emits its peak candidates
+    except bb.BartlettError:
+        cand = False
+    kname = proj_kernel_name(args.precision, M, cand)
+    flops = float(B) * K * G * proj_flops_per_point(M, kname)
     bound, peak = PEAK[args.precision]
     achieved = flops / (seq_ms * 1e-3) / 1e12
     value = B * args.steps / dt
@@ -226,8 +232,7 @@ def bench_sequential(args, workers):
                    "n_grid": G, "precision": args.precision},
         "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None,
-                     "kernel": "%s x %d passes (residual and peak kernels inside the timed span)" % (
-                         proj_kernel_name(args.precision, M), K),
+                     "kernel": "%s x %d passes (residual and peak kernels inside the timed span)" % (kname, K),
                      "kernel_ms": seq_ms, "flops_per_launch": flops},
         "cpu_baseline": None,
         "grid_points_trials_per_s": value * G * K,

@@ -16,11 +16,14 @@ struct SeqLayout {
   size_t rt, p, i1, v1, r1, spec, total;
 };
 
+// Each pass's spectrum is staged in the workspace, except on plans whose
+// projection emits peak candidates: there the workspace holds the candidate
+// records of one pass (k = 1) instead.
 SeqLayout seq_layout(const Plan& p, int B) {
   SeqLayout L;
   size_t o = 0;
   L.rt = o; o += al(size_t(B) * p.M * p.M * 8);
-  L.p = o; o += al(size_t(B) * p.G * 4);
+  L.p = o; o += al(candidates_supported(p) ? candidate_bytes(p, B, 1) : size_t(B) * p.G * 4);
   L.i1 = o; o += al(size_t(B) * 4);
   L.v1 = o; o += al(size_t(B) * 4);
   L.r1 = o; o += al(size_t(B) * p.ndim * 8);
@@ -94,8 +97,14 @@ ba_status ba_sequential_peaks(ba_plan plan, int32_t n_trials, const void* R, int
       e = launch_residual(p, n_trials, R0, pass, nullptr, idx, k, Rt, s);
       src = Rt;
     }
-    if (e == hipSuccess) e = launch_spectrum(p, n_trials, src, P, spec, s);
-    if (e == hipSuccess) e = launch_peaks(p, n_trials, P, 1, i1, v1, r1, s);
+    if (candidates_supported(p)) {
+      float4* rec = reinterpret_cast<float4*>(P);
+      if (e == hipSuccess) e = launch_spectrum_candidates(p, n_trials, src, nullptr, 1, rec, s);
+      if (e == hipSuccess) e = launch_peaks_merge(p, n_trials, 1, rec, i1, v1, r1, s);
+    } else {
+      if (e == hipSuccess) e = launch_spectrum(p, n_trials, src, P, spec, s);
+      if (e == hipSuccess) e = launch_peaks(p, n_trials, P, 1, i1, v1, r1, s);
+    }
     if (e == hipSuccess) e = launch_put_column(n_trials, pass, k, p.ndim, i1, v1, r1, idx, val, refined, s);
   }
   return e == hipSuccess ? BA_OK : s_dev(fn, e);
