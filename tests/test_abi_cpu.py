@@ -137,3 +137,17 @@ def test_message_entry_points_reject_bad_arguments_before_device_work():
     mi = bb.MsgInputs(6, 100)
     mo = bb.MsgOutputs()
     assert L.ba_update_messages(None, C.byref(mi), C.byref(mo), None, 0, None) == bb.BA_ERR_ARG
+
+
+def test_candidate_and_packing_entry_points_reject_bad_arguments_before_device_work():
+    L = bb.lib()
+    sz = C.c_size_t()
+    assert L.ba_candidates_size(None, 1, 4, C.byref(sz)) == bb.BA_ERR_ARG
+    assert L.ba_last_error().decode().startswith("ba_candidates_size: plan is NULL")
+    # the size check they share reports under the caller's name
+    assert L.ba_spectrum_candidates(None, 1, None, 4, None, None, 0, None) == bb.BA_ERR_ARG
+    assert L.ba_last_error().decode().startswith("ba_spectrum_candidates: plan is NULL")
+    assert L.ba_peaks_merge(None, 1, 4, None, None, None, None, None) == bb.BA_ERR_ARG
+    assert L.ba_last_error().decode().startswith("ba_peaks_merge: plan is NULL")
+    out = np.zeros(5, np.int32)
+    assert L.ba_ragged_packed(None, out.ctypes.data_as(C.c_void_p)) == bb.BA_ERR_ARG
