@@ -458,7 +458,39 @@ __device__ __forceinline__ void trial_project(const RArgs& A, const RItem& it, c
     project_chunks<MP, WR, 0, RB>(A, Xg, nchunk, a, cov, scale, rbg, Pout, smem);
 }
 
-// 3. peaks from the LDS row (same rule as the standalone peak kernel)
+// 3. peaks from the LDS row (same rule as the standalone peak kernel). Grid
+// indices fit 32 bits (rows x s1 <= 16384); a 1-D row needs no division.
+// Each thread keeps a sorted list of its best KC maxima; each wave then
+// selects its own best K by K butterfly rounds over its lanes' list heads (no
+// barriers), and wave 0 selects the trial's best K from the eight wave lists.
+// Every list holds at least K entries, so the result is the top K of the row
+// under the same total order.
+__device__ __forceinline__ void offer_local(float p, int g, float (&lv)[kRaggedMaxPeaks],
+                                            int (&li)[kRaggedMaxPeaks]) {
+#pragma unroll
+  for (int j = kRaggedMaxPeaks - 1; j >= 0; --j) {
+    if (j > 0 && better(p, g, lv[j - 1], li[j - 1])) {
+      lv[j] = lv[j - 1];
+      li[j] = li[j - 1];
+    } else if (better(p, g, lv[j], li[j])) {
+      lv[j] = p;
+      li[j] = g;
+    }
+  }
+}
+
+__device__ __forceinline__ void wave_best(float& v, int& i) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const float ov = __shfl_xor(v, off, 64);
+    const int oi = __shfl_xor(i, off, 64);
+    if (better(ov, oi, v, i)) {
+      v = ov;
+      i = oi;
+    }
+  }
+}
+
 __device__ __attribute__((noinline)) void trial_peaks(const RArgs& A, const RItem& it, unsigned char* smem) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const float* sP = reinterpret_cast<const float*>(smem + kOffP);
@@ -471,112 +503,113 @@ __device__ __attribute__((noinline)) void trial_peaks(const RArgs& A, const RIte
     li[j] = INT_MAX;
   }
   const int s1 = A.s1, rows = A.rows, wrap0 = A.wrap0;
-  const int64_t ncand = int64_t(rows) * s1;
-  for (int64_t g = threadIdx.x; g < ncand; g += kThreads) {
-    const float p = sP[g];
-    if (p != p) continue;
-    const int i0 = int(g / s1), i1 = int(g % s1);
-    bool ok = true;
-    for (int di = -1; di <= 1; ++di) {
-      int j0 = i0 + di;
-      if (wrap0)
-        j0 = wrap_row(j0, rows);
-      else if (j0 < 0 || j0 >= rows)
-        continue;
-      for (int dj = -1; dj <= 1; ++dj) {
-        if ((di == 0 && dj == 0) || (s1 == 1 && dj != 0)) continue;
-        const int j1 = i1 + dj;
-        if (j1 < 0 || j1 >= s1) continue;
-        const float q = sP[int64_t(j0) * s1 + j1];
-        const bool earlier = di < 0 || (di == 0 && dj < 0);
-        ok = ok && (earlier ? (p > q) : (p >= q));
-      }
+  if (s1 == 1) {
+    for (int g = threadIdx.x; g < rows; g += kThreads) {
+      const float p = sP[g];
+      if (p != p) continue;
+      bool ok = true;
+      if (wrap0 || g > 0) ok = p > sP[wrap_row(g - 1, rows)];
+      if (wrap0 || g + 1 < rows) ok = ok && p >= sP[wrap_row(g + 1, rows)];
+      if (ok) offer_local(p, g, lv, li);
     }
-    if (ok) {
-#pragma unroll
-      for (int j = KC - 1; j >= 0; --j) {
-        if (j > 0 && better(p, int(g), lv[j - 1], li[j - 1])) {
-          lv[j] = lv[j - 1];
-          li[j] = li[j - 1];
-        } else if (better(p, int(g), lv[j], li[j])) {
-          lv[j] = p;
-          li[j] = int(g);
+  } else {
+    const int ncand = rows * s1;
+    for (int g = threadIdx.x; g < ncand; g += kThreads) {
+      const float p = sP[g];
+      if (p != p) continue;
+      const int i0 = g / s1, i1 = g - i0 * s1;
+      bool ok = true;
+      for (int di = -1; di <= 1; ++di) {
+        int j0 = i0 + di;
+        if (wrap0)
+          j0 = wrap_row(j0, rows);
+        else if (j0 < 0 || j0 >= rows)
+          continue;
+        for (int dj = -1; dj <= 1; ++dj) {
+          if (di == 0 && dj == 0) continue;
+          const int j1 = i1 + dj;
+          if (j1 < 0 || j1 >= s1) continue;
+          const float q = sP[j0 * s1 + j1];
+          const bool earlier = di < 0 || (di == 0 && dj < 0);
+          ok = ok && (earlier ? (p > q) : (p >= q));
         }
       }
+      if (ok) offer_local(p, g, lv, li);
     }
   }
-  float* sv = reinterpret_cast<float*>(smem);                     // [512][KC]
-  int* si = reinterpret_cast<int*>(smem + kThreads * KC * 4);     // [512][KC]
-  float* wv = reinterpret_cast<float*>(smem + kOffRed);           // [8]
-  int* wi = reinterpret_cast<int*>(smem + kOffRed + 64);          // [8]
-  float* selv = reinterpret_cast<float*>(smem + kOffRed + 128);   // [KC]
-  int* seli = reinterpret_cast<int*>(smem + kOffRed + 192);       // [KC]
+  // each wave's best K: round r takes the best list head of the wave
+  float* wv = reinterpret_cast<float*>(smem + kOffRed);              // [8][KC]
+  int* wi = reinterpret_cast<int*>(smem + kOffRed + 8 * KC * 4);     // [8][KC]
+  const int K = it.K;
+  int head = 0;
+  for (int r = 0; r < K; ++r) {
+    float v = -INFINITY;
+    int i = INT_MAX;
 #pragma unroll
-  for (int j = 0; j < KC; ++j) {
-    sv[threadIdx.x * KC + j] = lv[j];
-    si[threadIdx.x * KC + j] = li[j];
+    for (int j = 0; j < KC; ++j)
+      if (j == head) {
+        v = lv[j];
+        i = li[j];
+      }
+    const int hi = i;
+    wave_best(v, i);
+    if (i != INT_MAX && hi == i) ++head;  // grid indices are unique: this lane's head won
+    if (lane == 0) {
+      wv[wave * KC + r] = v;
+      wi[wave * KC + r] = i;
+    }
   }
   __syncthreads();
-  int head = 0;
-  for (int r = 0; r < it.K; ++r) {
-    float v = head < KC ? sv[threadIdx.x * KC + head] : -INFINITY;
-    int i = head < KC ? si[threadIdx.x * KC + head] : INT_MAX;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const float ov = __shfl_xor(v, off, 64);
-      const int oi = __shfl_xor(i, off, 64);
-      if (better(ov, oi, v, i)) {
-        v = ov;
-        i = oi;
+  if (wave == 0) {
+    // lane l holds entry l % K of wave l / K's list (K <= 8: all 64 fit)
+    float cv = -INFINITY;
+    int ci = INT_MAX;
+    if (lane < (kThreads / 64) * K) {
+      cv = wv[(lane / K) * KC + lane % K];
+      ci = wi[(lane / K) * KC + lane % K];
+    }
+    float selv = -INFINITY;
+    int seli = INT_MAX;
+    for (int r = 0; r < K; ++r) {
+      float v = cv;
+      int i = ci;
+      wave_best(v, i);
+      if (i != INT_MAX && ci == i) {
+        cv = -INFINITY;
+        ci = INT_MAX;
+      }
+      if (lane == r) {
+        selv = v;
+        seli = i;
       }
     }
-    if (lane == 0) {
-      wv[wave] = v;
-      wi[wave] = i;
-    }
-    __syncthreads();
-    float bv = wv[0];
-    int bi = wi[0];
-#pragma unroll
-    for (int w = 1; w < kThreads / 64; ++w)
-      if (better(wv[w], wi[w], bv, bi)) {
-        bv = wv[w];
-        bi = wi[w];
-      }
-    if (bi != INT_MAX && head < KC && si[threadIdx.x * KC + head] == bi) ++head;
-    if (threadIdx.x == 0) {
-      selv[r] = bv;
-      seli[r] = bi;
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x < A.kmax) {
-    const int j = threadIdx.x;
-    const int64_t o = int64_t(it.trial) * A.kmax + j;
-    const int g = j < it.K ? seli[j] : INT_MAX;
-    const double nan = __longlong_as_double(0x7ff8000000000000LL);
-    if (g == INT_MAX) {
-      A.idx[o] = -1;
-      A.val[o] = __int_as_float(0x7fc00000);
-      if (A.refined)
-        for (int d = 0; d < A.ndim; ++d) A.refined[o * A.ndim + d] = nan;
-    } else {
-      A.idx[o] = g;
-      A.val[o] = selv[j];
-      if (A.refined) {
-        const int i0 = g / s1, i1 = g % s1;
-        const double p0 = double(sP[g]);
-        double d0 = 0.0;
-        if (wrap0 || (i0 > 0 && i0 < rows - 1)) {
-          const int jm = wrap_row(i0 - 1, rows), jp = wrap_row(i0 + 1, rows);
-          d0 = parabolic(double(sP[int64_t(jm) * s1 + i1]), p0, double(sP[int64_t(jp) * s1 + i1]));
-        }
-        A.refined[o * A.ndim] = double(i0) + d0;
-        if (A.ndim == 2) {
-          double d1 = 0.0;
-          if (i1 > 0 && i1 < s1 - 1)
-            d1 = parabolic(double(sP[int64_t(i0) * s1 + i1 - 1]), p0, double(sP[int64_t(i0) * s1 + i1 + 1]));
-          A.refined[o * A.ndim + 1] = double(i1) + d1;
+    if (lane < A.kmax) {
+      const int j = lane;
+      const int64_t o = int64_t(it.trial) * A.kmax + j;
+      const int g = j < K ? seli : INT_MAX;
+      const double nan = __longlong_as_double(0x7ff8000000000000LL);
+      if (g == INT_MAX) {
+        A.idx[o] = -1;
+        A.val[o] = __int_as_float(0x7fc00000);
+        if (A.refined)
+          for (int d = 0; d < A.ndim; ++d) A.refined[o * A.ndim + d] = nan;
+      } else {
+        A.idx[o] = g;
+        A.val[o] = selv;
+        if (A.refined) {
+          const int i0 = g / s1, i1 = g - i0 * s1;
+          const double p0 = double(sP[g]);
+          double d0 = 0.0;
+          if (wrap0 || (i0 > 0 && i0 < rows - 1)) {
+            const int jm = wrap_row(i0 - 1, rows), jp = wrap_row(i0 + 1, rows);
+            d0 = parabolic(double(sP[jm * s1 + i1]), p0, double(sP[jp * s1 + i1]));
+          }
+          A.refined[o * A.ndim] = double(i0) + d0;
+          if (A.ndim == 2) {
+            double d1 = 0.0;
+            if (i1 > 0 && i1 < s1 - 1) d1 = parabolic(double(sP[i0 * s1 + i1 - 1]), p0, double(sP[i0 * s1 + i1 + 1]));
+            A.refined[o * A.ndim + 1] = double(i1) + d1;
+          }
         }
       }
     }
