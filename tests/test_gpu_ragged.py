@@ -29,7 +29,7 @@ def run(rs, route=bb.BA_ROUTE_AUTO, autotune=None, replays=1, plan=None):
     P = torch.full((B, G), -1.0, dtype=torch.float32, device=DEV)
     idx = torch.empty((B, KMAX), dtype=torch.int32, device=DEV)
     val = torch.empty((B, KMAX), dtype=torch.float32, device=DEV)
-    ref = torch.empty((B, KMAX, 1), dtype=torch.float64, device=DEV)
+    ref = torch.empty((B, KMAX, plan.ndim), dtype=torch.float64, device=DEV)
     desc = bb.ragged_descriptors(rs, route)
     with bb.ba_ragged_create(plan, desc, KMAX, Y, P, idx, val, ref) as r:
         if autotune is not None:
@@ -51,9 +51,10 @@ def run(rs, route=bb.BA_ROUTE_AUTO, autotune=None, replays=1, plan=None):
     return dict(P=P, idx=idx, val=val, ref=ref, routes=routes, cfg=cfg, packed=packed, outs=outs)
 
 
-def check(rs, o, fp64_peaks=True, positions=None, grid_kind=ob.GRID_ULA_DEG, wrap0=0):
+def check(rs, o, fp64_peaks=True, positions=None, grid_kind=ob.GRID_ULA_DEG, wrap0=0, shape=None):
     """Every trial against the oracle on the plan's first M elements
-    (positions: the plan's [M_plan][3] geometry; default the ULA)."""
+    (positions: the plan's [M_plan][3] geometry; default the ULA; shape: the
+    grid's (rows, columns), default one column)."""
     pool = rs.pool_c64().astype(np.complex128)
     bad, ncmp = [], 0
     emax = 0.0
@@ -67,11 +68,12 @@ def check(rs, o, fp64_peaks=True, positions=None, grid_kind=ob.GRID_ULA_DEG, wra
         emax = max(emax, e)
         assert e <= 1e-5, (i, M, T, K, e, o["routes"][i])
         G = len(rs.grid)
+        shp = (G, 1) if shape is None else shape
         check_peaks_same_precision(o["P"][i][None], o["idx"][i][None, :K], o["val"][i][None, :K],
-                                   o["ref"][i][None, :K], K, (G, 1), wrap0)
+                                   o["ref"][i][None, :K], K, shp, wrap0)
         assert np.all(o["idx"][i, K:] == -1) and np.all(np.isnan(o["val"][i, K:]))
         if fp64_peaks:
-            n, _, b = peak_agreement_fp64(Pref[None], o["idx"][i][None, :K], K, (G, 1), wrap0, 1e-5)
+            n, _, b = peak_agreement_fp64(Pref[None], o["idx"][i][None, :K], K, shp, wrap0, 1e-5)
             ncmp += n
             bad += b
     assert not bad, bad[:3]
@@ -246,3 +248,38 @@ def test_packed_trials_on_a_wrapping_direction_grid(wrap0):
         o = run(rs, route=bb.BA_ROUTE_COV, plan=plan)
     assert list(o["packed"][:3]) == [1, 1, 1]
     check(rs, o, fp64_peaks=False, positions=pos, grid_kind=ob.GRID_DIRS, wrap0=wrap0)
+
+
+@pytest.mark.parametrize("wrap0", [0, 1])
+def test_whole_workgroup_trials_on_an_azimuth_elevation_grid(wrap0):
+    """A 2-D az/el grid (rows = azimuths, columns = elevations; wrap0 = 1
+    closes the azimuth circle): the whole-workgroup peak pick over a 2-D
+    spectrum row (eight neighbours, the earlier ones strictly below), every
+    size class, refinement in both dimensions, against the oracle's spectrum
+    and its 2-D peak rule on the same FP32 values."""
+    az = np.arange(0.0, 360.0, 6.0) if wrap0 else np.arange(-60.0, 61.0, 4.0)
+    el = np.arange(0.0, 41.0, 5.0)
+    grid = np.array([(a, e) for a in az for e in el])
+    rows, s1 = len(az), len(el)
+    Mp = 128
+    rng = np.random.default_rng(97 + wrap0)
+    pos = np.zeros((Mp, 3))
+    pos[:, 0] = 0.5 * (np.arange(Mp) % 16)
+    pos[:, 1] = 0.5 * (np.arange(Mp) // 16)
+    pos[:, 2] = 0.1 * rng.standard_normal(Mp)   # not a symmetric planar array
+    Ms = [128, 100, 64, 40, 33, 32, 24, 16, 9, 8, 5, 3, 128, 64]
+    Ts = [300, 50, 1000, 64, 7, 200, 3, 90, 2048, 16, 40, 5, 20, 33]
+    Ks = [4, 8, 1, 3, 2, 6, 5, 7, 2, 8, 3, 1, 6, 5]
+    blocks = [(rng.standard_normal((T, M)) + 1j * rng.standard_normal((T, M))).reshape(-1)
+              for M, T in zip(Ms, Ts)]
+    sizes = np.array([b.size for b in blocks], np.int64)
+    off = np.zeros(len(Ms), np.int64)
+    off[1:] = np.cumsum(sizes)[:-1]
+    rs = wl.RaggedSet(pool=np.concatenate(blocks), y_offset=off, n_elem=np.array(Ms, np.int32),
+                      n_snap=np.array(Ts, np.int32), k=np.array(Ks, np.int32), truth=[None] * len(Ms),
+                      snr_db=np.zeros(len(Ms)), grid=grid)
+    with bb.ba_plan_create(Mp, pos, bb.BA_GRID_AZEL_DEG, len(grid), grid, rows, s1, wrap0) as plan:
+        assert plan.ndim == 2
+        o = run(rs, plan=plan)
+    assert o["ref"].shape[-1] == 2
+    check(rs, o, fp64_peaks=False, positions=pos, grid_kind=ob.GRID_AZEL_DEG, wrap0=wrap0, shape=(rows, s1))
