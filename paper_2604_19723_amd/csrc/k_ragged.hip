@@ -189,81 +189,133 @@ __device__ __attribute__((noinline)) void stage_covariance(const float2* __restr
   covariance_lds<BN>(Yb, M, T, smem);
 }
 
+// Direct global -> LDS copy of 4 bytes per lane (global_load_lds_dword): lane
+// i's word lands at lds_wave + 4 i (lds_wave wave-uniform); completion is
+// tracked by vmcnt like lds_dma16.
+__device__ __forceinline__ void lds_dma4(const void* gsrc_lane, void* lds_wave) {
+  __builtin_amdgcn_global_load_lds(gsrc_lane, reinterpret_cast<__attribute__((address_space(3))) void*>(
+                                                  reinterpret_cast<uintptr_t>(lds_wave)),
+                                   4, 0, 0);
+}
+
 // Covariance of the larger classes on the matrix cores: the real Gram matrix
 // G = sum_t z_t z_t^T of the snapshots' float views (re, im interleaved), with
 //   Re R[m][n] = G[2m][2n] + G[2m+1][2n+1],  Im R[m][n] = G[2m+1][2n] - G[2m][2n+1],
 // written to the LDS matrix R (exactly Hermitian). The 16x16 Gram tiles on or
-// above the diagonal go to the waves as tile-row pairs (w, MT-1-w); snapshot
-// chunks are staged row-major (row stride 2 MP + 16 floats).
+// above the diagonal go to the waves as tile-row pairs (RA, MT-1-RA), RA a
+// compile-time case per wave, so the MFMA sequence has no per-tile branch and
+// a wave holds only its own MT + 1 accumulator tiles. R is written only after
+// the last snapshot, so the snapshot stages use all of the LDS: two buffers
+// of TC rows (68 snapshots at 128 elements, 132 at 64; row stride 2 MP + 16
+// floats, so the four k-rows of a fragment fall on different bank quarters),
+// the next stage streamed in by LDS DMA while the current one is multiplied
+// (one 16-byte DMA per row when the rows are 16-byte aligned, 4-byte words
+// otherwise: a row of 2M floats is copied exactly, nothing past the trial's
+// block is read), one barrier per stage; within a stage the next k-step's
+// fragments are read while the current one is multiplied. Columns past 2M
+// keep stale values: a Gram entry reads only its own two columns, and those
+// entries are never used. Rows past T up to the next multiple of 4 are zeroed.
 template <int MT>
-__device__ __attribute__((noinline)) void stage_covariance_gram(const float2* __restrict__ Yb, int M, int T,
-                                                                unsigned char* smem) {
-  constexpr int W = 16 * MT;                       // Gram columns = 2 MP
-  constexpr int LD = W + 16;
-  constexpr int TC = (kStageBytes / (LD * 4)) & ~3;  // snapshots per stage, a multiple of 4
-  static_assert(TC >= 4, "stage");
+struct GramCfg {
+  static constexpr int W = 16 * MT;                               // Gram columns = 2 MP
+  static constexpr int LD = W + 16;
+  static constexpr int TC = ((kRaggedLds / 2) / (LD * 4)) & ~3;   // snapshots per stage buffer
+  static_assert(2 * TC * LD * 4 <= kRaggedLds && TC >= 4, "two stage buffers fit the LDS");
+};
+
+// Tile rows (RA, MT - 1 - RA), the tile columns c with c % NH == H of them
+// (NH = 2 splits a pair over two waves when there are fewer pairs than
+// waves); RA < 0: a wave without Gram tiles (it streams snapshots and keeps
+// the barriers).
+template <int MT, int RA, int H, int NH>
+__device__ __forceinline__ void gram_rows(const float* __restrict__ Yf, int M, int T, unsigned char* smem,
+                                          int wave, int lane) {
+  using C = GramCfg<MT>;
+  constexpr int W = C::W, LD = C::LD, TC = C::TC;
+  constexpr bool ACT = RA >= 0;
+  constexpr int RB = ACT ? MT - 1 - RA : 0;
+  constexpr bool TWO = ACT && RB != RA;
+  float* sZ = reinterpret_cast<float*>(smem);  // [2][TC][LD] until R is written
   float2* sR = reinterpret_cast<float2*>(smem);
-  float* sZ = reinterpret_cast<float*>(smem + kOffY);
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int ra = wave, rb = MT - 1 - wave;
-  const bool act = wave < (MT + 1) / 2;
-  const bool two = act && rb != ra;
+  const int fi = lane & 15, fk = lane >> 4;
+  const int nst = (T + TC - 1) / TC;
   floatx4 accA[MT], accB[MT];
 #pragma unroll
   for (int c = 0; c < MT; ++c) {
     accA[c] = floatx4{0.f, 0.f, 0.f, 0.f};
     accB[c] = floatx4{0.f, 0.f, 0.f, 0.f};
   }
-  const int fi = lane & 15, fk = lane >> 4;
-  // the next stage's snapshots are loaded into registers while the current
-  // stage is multiplied
-  constexpr int kPer = (TC * (W / 2) + kThreads - 1) / kThreads;
-  float2 yv[kPer];
-  auto load_stage = [&](int t0) {
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int v = threadIdx.x + q * kThreads;
-      const int tt = v / (W / 2), m = v - tt * (W / 2);
-      const int t = t0 + tt;
-      yv[q] = (v < TC * (W / 2) && t < T && m < M) ? Yb[int64_t(t) * M + m] : make_float2(0.f, 0.f);
-    }
-  };
-  load_stage(0);
-  for (int t0 = 0; t0 < T; t0 += TC) {
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int v = threadIdx.x + q * kThreads;
-      const int tt = v / (W / 2), m = v - tt * (W / 2);
-      if (v < TC * (W / 2)) *reinterpret_cast<float2*>(&sZ[tt * LD + 2 * m]) = yv[q];
-    }
-    __syncthreads();
-    if (t0 + TC < T) load_stage(t0 + TC);
-    if (act) {
-      for (int s = 0; s < TC / 4; ++s) {
-        const float* row = sZ + (4 * s + fk) * LD + fi;
-        const float fa = row[16 * ra], fb = row[16 * rb];
-        float f[MT];
-#pragma unroll
-        for (int c = 0; c < MT; ++c) f[c] = row[16 * c];
-#pragma unroll
-        for (int c = 0; c < MT; ++c) {
-          if (c >= ra) accA[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa, f[c], accA[c], 0, 0, 0);
-          if (two && c >= rb) accB[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(fb, f[c], accB[c], 0, 0, 0);
-        }
+
+  // rows t0 .. t0 + nrow - 1 of stage st into buffer buf, spread over the
+  // waves: a whole row per 16-byte DMA when every row starts on 16 bytes (M
+  // even, the block 16-byte aligned), else 64 floats of a row per 4-byte DMA;
+  // the rows up to the next multiple of 4 past T are zeroed with plain stores
+  const bool wide = (M & 1) == 0 && (reinterpret_cast<uintptr_t>(Yf) & 15) == 0;
+  auto fetch = [&](int st, int buf) {
+    const int t0 = st * TC;
+    const int nrow = min(TC, T - t0);
+    float* dst = sZ + buf * (TC * LD);
+    if (wide) {
+      for (int r = wave; r < nrow; r += kThreads / 64)
+        if (lane < M / 2) lds_dma16(Yf + (int64_t(t0 + r) * M) * 2 + 4 * lane, dst + r * LD);
+    } else {
+      for (int it = wave; it < nrow * (W / 64); it += kThreads / 64) {
+        const int r = it / (W / 64), part = it - r * (W / 64);
+        const int f = part * 64 + lane;
+        if (f < 2 * M) lds_dma4(Yf + (int64_t(t0 + r) * M) * 2 + f, dst + r * LD + part * 64);
       }
     }
+    const int nz = ((nrow + 3) & ~3) - nrow;
+    for (int e = threadIdx.x; e < nz * W; e += kThreads) dst[(nrow + e / W) * LD + e % W] = 0.f;
+  };
+
+  fetch(0, 0);
+  lds_dma_wait();
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int buf = st & 1;
+    if (st + 1 < nst) fetch(st + 1, buf ^ 1);  // that buffer was last read before the previous barrier
+    if constexpr (ACT) {
+      const int nks = (min(TC, T - st * TC) + 3) >> 2;
+      const float* __restrict__ zb = sZ + buf * (TC * LD);
+      auto load = [&](float (&dst)[MT], int s) {
+        const float* row = zb + (4 * s + fk) * LD + fi;
+#pragma unroll
+        for (int c = RA; c < MT; ++c)
+          if (c % NH == H || c == RA || c == RB) dst[c] = lds_frag(row, 16 * c);
+      };
+      auto step = [&](const float (&src)[MT]) {
+#pragma unroll
+        for (int c = RA; c < MT; ++c) {
+          if (c % NH != H) continue;
+          accA[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(src[RA], src[c], accA[c], 0, 0, 0);
+          if (TWO && c >= RB) accB[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(src[RB], src[c], accB[c], 0, 0, 0);
+        }
+      };
+      float f[MT], g[MT];
+      load(f, 0);
+      int s = 0;
+      for (; s + 2 <= nks; s += 2) {
+        load(g, s + 1);
+        step(f);
+        if (s + 2 < nks) load(f, s + 2);
+        step(g);
+      }
+      if (s < nks) step(f);
+    }
+    lds_dma_wait();
     __syncthreads();
   }
-  if (act) {
+  // every stage is consumed: R overwrites the stage buffers
+  if constexpr (ACT) {
     const float invT = 1.0f / float(T);
     const bool even = (lane & 1) == 0;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      if (h == 1 && !two) break;
-      const int r = h == 0 ? ra : rb;
+    for (int h = 0; h < (TWO ? 2 : 1); ++h) {
+      const int r = h == 0 ? RA : RB;
 #pragma unroll
       for (int c = 0; c < MT; ++c) {
-        if (c < r) continue;
+        if (c < r || c % NH != H) continue;
         const floatx4 a = h == 0 ? accA[c] : accB[c];
         floatx4 x;
 #pragma unroll
@@ -283,6 +335,38 @@ __device__ __attribute__((noinline)) void stage_covariance_gram(const float2* __
     }
   }
   __syncthreads();
+}
+
+template <int MT>
+__device__ __attribute__((noinline)) void stage_covariance_gram(const float2* __restrict__ Yb, int M_arg, int T_arg,
+                                                                unsigned char* smem) {
+  // the sizes and the wave index are the same in every lane: scalar loop control
+  const int M = __builtin_amdgcn_readfirstlane(M_arg), T = __builtin_amdgcn_readfirstlane(T_arg);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const float* Yf = reinterpret_cast<const float*>(Yb);
+  static_assert(kThreads / 64 == 8 && MT <= 16, "eight waves cover the tile-row pairs");
+  // MT / 2 pairs: one per wave at 16 tile rows; at 8 each pair's columns are
+  // split by parity over waves w and w + 4 (9 tiles -> 4 and 5)
+  constexpr int NH = MT >= 16 ? 1 : 2;
+  constexpr int NP = (MT + 1) / 2;  // tile-row pairs
+#define BA_GRAM_WAVE(w)                                                                            \
+  case w:                                                                                          \
+    if constexpr (w < NP * NH)                                                                     \
+      gram_rows<MT, (w % NP), (w / NP), NH>(Yf, M, T, smem, wave, lane);                           \
+    else                                                                                           \
+      gram_rows<MT, -1, 0, NH>(Yf, M, T, smem, wave, lane);                                        \
+    break;
+  switch (wave) {
+    BA_GRAM_WAVE(0)
+    BA_GRAM_WAVE(1)
+    BA_GRAM_WAVE(2)
+    BA_GRAM_WAVE(3)
+    BA_GRAM_WAVE(4)
+    BA_GRAM_WAVE(5)
+    BA_GRAM_WAVE(6)
+    BA_GRAM_WAVE(7)
+  }
+#undef BA_GRAM_WAVE
 }
 
 // the chunk loop for NACT active row blocks per wave (a prefix of its RB,
@@ -398,7 +482,7 @@ __device__ __forceinline__ void trial_project(const RArgs& A, const RItem& it, c
   // 1. A operand
   float a[RB][C::KS];
   if (cov) {
-    if (MP >= 64)
+    if constexpr (MP >= 64)
       stage_covariance_gram<MP / 8>(Yb, M, T, smem);
     else
       stage_covariance<4>(Yb, M, T, smem);
