@@ -369,6 +369,33 @@ __device__ __attribute__((noinline)) void stage_covariance_gram(const float2* __
 #undef BA_GRAM_WAVE
 }
 
+// MFMAs of one 16-column block for a wave's two row blocks: W0 >= 0 is the
+// covariance route's pair (W0, NRB - 1 - W0), whose blocks skip the k-steps
+// left of their diagonal (compile-time, no branch per step); W0 < 0 takes
+// every k-step for both (snapshot route).
+template <int MP, int W0>
+__device__ __forceinline__ void pair_chunk_mfma(floatx4 (&acc)[2], const float (&a)[2][RC<MP>::KS],
+                                                const float4* __restrict__ bx, int lane) {
+  using C = RC<MP>;
+  constexpr int S0 = W0 >= 0 ? W0 : 0, S1 = W0 >= 0 ? C::NRB - 1 - W0 : 0;
+#pragma unroll
+  for (int s4 = S0 < S1 ? S0 : S1; s4 < C::KS / 4; ++s4) {
+    const float4 bv = bx[s4 * 64 + lane];
+    if (s4 >= S0) {
+      acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0][4 * s4 + 0], bv.x, acc[0], 0, 0, 0);
+      acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0][4 * s4 + 1], bv.y, acc[0], 0, 0, 0);
+      acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0][4 * s4 + 2], bv.z, acc[0], 0, 0, 0);
+      acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0][4 * s4 + 3], bv.w, acc[0], 0, 0, 0);
+    }
+    if (s4 >= S1) {
+      acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1][4 * s4 + 0], bv.x, acc[1], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1][4 * s4 + 1], bv.y, acc[1], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1][4 * s4 + 2], bv.z, acc[1], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1][4 * s4 + 3], bv.w, acc[1], 0, 0, 0);
+    }
+  }
+}
+
 // the chunk loop for NACT active row blocks per wave (a prefix of its RB,
 // row blocks rbg[0] < rbg[1]); on the covariance route the A operand is the
 // upper triangle U of Q, and row block rbg skips the k-steps left of its
@@ -380,7 +407,8 @@ __device__ __forceinline__ void project_chunks(const RArgs& A, const float4* __r
                                                unsigned char* smem) {
   using C = RC<MP>;
   constexpr int WC = (kThreads / 64) / WR;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // the wave index through a scalar register: the pair switch below is uniform
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int wr = wave % WR, wc = wave / WR;
   float4* sX = reinterpret_cast<float4*>(smem);
   float* sP = reinterpret_cast<float*>(smem + kOffP);
@@ -407,18 +435,39 @@ __device__ __forceinline__ void project_chunks(const RArgs& A, const float4* __r
 #pragma unroll
       for (int rb = 0; rb < NACT; ++rb) acc[rb] = floatx4{0.f, 0.f, 0.f, 0.f};
       const float4* bx = xb4 + jb * (C::BLK / 4);
+      if constexpr (NACT == 2 && RB == 2) {
+        if (cov) {
+          // the covariance route's pair (wr, NRB - 1 - wr) as a compile-time
+          // case: the k-steps left of each block's diagonal are dropped
+          // without a branch per step
+          static_assert(WR <= 8, "pair cases");
+          switch (wr) {
+            case 0: pair_chunk_mfma<MP, 0>(acc, a, bx, lane); break;
+            case 1: if constexpr (WR > 1) pair_chunk_mfma<MP, 1>(acc, a, bx, lane); break;
+            case 2: if constexpr (WR > 2) pair_chunk_mfma<MP, 2>(acc, a, bx, lane); break;
+            case 3: if constexpr (WR > 3) pair_chunk_mfma<MP, 3>(acc, a, bx, lane); break;
+            case 4: if constexpr (WR > 4) pair_chunk_mfma<MP, 4>(acc, a, bx, lane); break;
+            case 5: if constexpr (WR > 5) pair_chunk_mfma<MP, 5>(acc, a, bx, lane); break;
+            case 6: if constexpr (WR > 6) pair_chunk_mfma<MP, 6>(acc, a, bx, lane); break;
+            default: if constexpr (WR > 7) pair_chunk_mfma<MP, 7>(acc, a, bx, lane); break;
+          }
+        } else {
+          pair_chunk_mfma<MP, -1>(acc, a, bx, lane);
+        }
+      } else {
 #pragma unroll
-      for (int s4 = 0; s4 < C::KS / 4; ++s4) {
-        if (NACT == 0) break;
-        if (cov && s4 < rbg[0]) continue;
-        const float4 bv = bx[s4 * 64 + lane];
+        for (int s4 = 0; s4 < C::KS / 4; ++s4) {
+          if (NACT == 0) break;
+          if (cov && s4 < rbg[0]) continue;
+          const float4 bv = bx[s4 * 64 + lane];
 #pragma unroll
-        for (int rb = 0; rb < NACT; ++rb) {
-          if (cov && s4 < rbg[rb]) continue;
-          acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 0], bv.x, acc[rb], 0, 0, 0);
-          acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 1], bv.y, acc[rb], 0, 0, 0);
-          acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 2], bv.z, acc[rb], 0, 0, 0);
-          acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 3], bv.w, acc[rb], 0, 0, 0);
+          for (int rb = 0; rb < NACT; ++rb) {
+            if (cov && s4 < rbg[rb]) continue;
+            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 0], bv.x, acc[rb], 0, 0, 0);
+            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 1], bv.y, acc[rb], 0, 0, 0);
+            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 2], bv.z, acc[rb], 0, 0, 0);
+            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][4 * s4 + 3], bv.w, acc[rb], 0, 0, 0);
+          }
         }
       }
       float part = 0.f;
