@@ -204,7 +204,9 @@ __device__ __forceinline__ void lds_dma4(const void* gsrc_lane, void* lds_wave) 
 // written to the LDS matrix R (exactly Hermitian). The 16x16 Gram tiles on or
 // above the diagonal go to the waves as tile-row pairs (RA, MT-1-RA), RA a
 // compile-time case per wave, so the MFMA sequence has no per-tile branch and
-// a wave holds only its own MT + 1 accumulator tiles. R is written only after
+// a wave holds only its own accumulator tiles (MT + 1; at 64 elements, with
+// four pairs for eight waves, each pair's tile columns are split by parity
+// over two waves, 4 and 5 tiles). R is written only after
 // the last snapshot, so the snapshot stages use all of the LDS: two buffers
 // of TC rows (68 snapshots at 128 elements, 132 at 64; row stride 2 MP + 16
 // floats, so the four k-rows of a fragment fall on different bank quarters),
