@@ -891,11 +891,22 @@ def bench_grid(args, workers):
         rmse_v = rmse_se_by_snr(ts, est_deg, idx_h)
         with bb.plan_for(ts, bb.BA_PREC_F32) as plan32:
             ws32 = bb.spectrum_workspace_for(plan32, B, dev)
+            # the same peak pick as the timed path: candidates + merge where served
+            cand32 = None
+            if use_cand:
+                try:
+                    cand32 = bb.candidates_for(plan32, B, K, dev)
+                except bb.BartlettError:
+                    pass
 
             def step32():
                 bb.ba_covariance(plan32, B, T, Y, R)
-                bb.ba_spectrum(plan32, B, R, P, ws32)
-                bb.ba_peaks(plan32, B, P, K, idx, val, ref)
+                if cand32 is not None:
+                    bb.ba_spectrum_candidates(plan32, B, R, K, None, cand32)
+                    bb.ba_peaks_merge(plan32, B, K, cand32, idx, val, ref)
+                else:
+                    bb.ba_spectrum(plan32, B, R, P, ws32)
+                    bb.ba_peaks(plan32, B, P, K, idx, val, ref)
 
             for _ in range(args.warmup):
                 step32()
