@@ -1,78 +1,11 @@
 // Sample covariance R = (1/T) sum_t y_t y_t^H per trial (the R of the Bartlett
-// cost in its covariance form, Sec. IV-D.2 read for T snapshots).
-//
-// One workgroup computes a 32x32 tile of R for one trial from the upper
-// triangle of tile pairs (mt <= nt). Snapshot blocks of 32 x 32 complex values
-// are staged in LDS with coalesced loads (each snapshot is a contiguous
-// M-vector in HBM) and accumulated in FP32. The lower triangle is written as
-// the conjugate of the upper one, so R is exactly Hermitian with a real
-// diagonal.
+// cost in its covariance form, Sec. IV-D.2 read for T snapshots), on the
+// matrix cores in FP32. Only the upper triangle is formed; the lower one is
+// written as its conjugate, so R is exactly Hermitian with a real diagonal.
 #include "ba_internal.h"
 
 namespace ba {
 namespace {
-
-constexpr int kTile = 32;   // output tile edge
-constexpr int kChunk = 32;  // snapshots per LDS stage
-
-__global__ __launch_bounds__(256) void k_cov_tiles(const float2* __restrict__ Y,
-                                                   float2* __restrict__ R, int M, int T,
-                                                   int ntile, int npairs) {
-  const int64_t b = blockIdx.x / npairs;
-  int rem = blockIdx.x % npairs;
-  int mt = 0;
-  while (rem >= ntile - mt) {
-    rem -= ntile - mt;
-    ++mt;
-  }
-  const int nt = mt + rem;
-  const float2* Yb = Y + b * int64_t(T) * M;
-
-  __shared__ float2 sm[kChunk][kTile + 1];
-  __shared__ float2 sn[kChunk][kTile + 1];
-  const int tx = threadIdx.x & 31;
-  const int ty = threadIdx.x >> 5;  // 0..7
-  float accr[4] = {0.f, 0.f, 0.f, 0.f};
-  float acci[4] = {0.f, 0.f, 0.f, 0.f};
-
-  for (int t0 = 0; t0 < T; t0 += kChunk) {
-    for (int i = threadIdx.x; i < kChunk * kTile; i += 256) {
-      const int tt = i / kTile, mm = i % kTile;
-      const int t = t0 + tt;
-      const int gm = mt * kTile + mm, gn = nt * kTile + mm;
-      const bool tok = t < T;
-      sm[tt][mm] = (tok && gm < M) ? Yb[int64_t(t) * M + gm] : make_float2(0.f, 0.f);
-      sn[tt][mm] = (tok && gn < M) ? Yb[int64_t(t) * M + gn] : make_float2(0.f, 0.f);
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int tt = 0; tt < kChunk; ++tt) {
-      const float2 yn = sn[tt][tx];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float2 ym = sm[tt][ty + 8 * i];
-        // ym * conj(yn)
-        accr[i] += ym.x * yn.x + ym.y * yn.y;
-        acci[i] += ym.y * yn.x - ym.x * yn.y;
-      }
-    }
-    __syncthreads();
-  }
-
-  const float invT = 1.0f / float(T);
-  float2* Rb = R + b * int64_t(M) * M;
-  const int n = nt * kTile + tx;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int m = mt * kTile + ty + 8 * i;
-    if (m < M && n < M && m <= n) {
-      const float re = accr[i] * invT;
-      const float im = (m == n) ? 0.f : acci[i] * invT;
-      Rb[int64_t(m) * M + n] = make_float2(re, im);
-      Rb[int64_t(n) * M + m] = make_float2(re, -im);
-    }
-  }
-}
 
 // Arrays of up to 64 elements: the covariance as a real Gram matrix on the
 // matrix cores. With z_t the 2M floats of snapshot t (re, im interleaved),
@@ -222,6 +155,170 @@ __global__ __launch_bounds__(256) void k_cov_mfma(const float2* __restrict__ Y, 
   }
 }
 
+// Arrays of more than 64 elements: R in blocks of 64 x 64 elements, one
+// workgroup per pair of element blocks (mb <= nb) of one trial. The pair's
+// share of the real Gram, G over the float rows of block mb and the float
+// columns of block nb, is a 128 x 128 array of 8 x 8 tiles of 16. On a
+// diagonal pair only the tiles on or above the diagonal are formed, split
+// over the waves by tile-row pairs (w, 7 - w) as above; off the diagonal
+// wave w takes tile rows 2w and 2w + 1 across all eight tile columns. Chunks
+// of 32 snapshots of both blocks are staged row-major in LDS, the next one
+// held in registers while the current one is multiplied.
+constexpr int kBlkE = 64;              // elements per block
+constexpr int kBlkW = 2 * kBlkE;       // floats per block row
+constexpr int kBlkLD = kBlkW + 16;     // LDS row stride (as kGramChunk's)
+constexpr int kBlkChunk = 32;          // snapshots per stage
+constexpr int kBlkWide = kBlkChunk * kBlkE / 2 / 256;  // float4 per thread per block (4)
+
+// Tile rows RA and RB (RB == RA: one row); columns from RA (resp. RB) on when
+// UPPER, else all eight. Ym, Yn: the snapshots' first element of each block
+// (row stride M); cm, cn: elements in each block; Rb: the trial's R.
+template <int RA, int RB, bool UPPER>
+__device__ __forceinline__ void cov_block_wave(const float2* __restrict__ Ym, const float2* __restrict__ Yn,
+                                               float2* __restrict__ Rb, int M, int T, int cm, int cn, int m0,
+                                               int n0, bool wide, float* sM, float* sN, int lane) {
+  constexpr bool TWO = RB != RA;
+  constexpr int CA = UPPER ? RA : 0, CB = UPPER ? RB : 0;
+  constexpr bool SAME = UPPER;  // a diagonal pair stages one block
+  floatx4 accA[8], accB[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    accA[c] = floatx4{0.f, 0.f, 0.f, 0.f};
+    accB[c] = floatx4{0.f, 0.f, 0.f, 0.f};
+  }
+  const int fi = lane & 15, fk = lane >> 4;
+  float4 ym[kBlkWide], yn[kBlkWide];
+  // thread v of a block's chunk: row v / 32, elements 2 (v % 32) and 2 (v % 32) + 1
+  auto load_block = [&](const float2* __restrict__ Yb, int cnt, int t0, float4 (&y)[kBlkWide]) {
+#pragma unroll
+    for (int q = 0; q < kBlkWide; ++q) {
+      const int v = threadIdx.x + q * 256;
+      const int tt = v >> 5, m = 2 * (v & 31);
+      const int t = t0 + tt;
+      if (wide) {
+        y[q] = (t < T && m < cnt) ? *reinterpret_cast<const float4*>(Yb + int64_t(t) * M + m)
+                                  : make_float4(0.f, 0.f, 0.f, 0.f);
+      } else {
+        const float2 a = (t < T && m < cnt) ? Yb[int64_t(t) * M + m] : make_float2(0.f, 0.f);
+        const float2 b = (t < T && m + 1 < cnt) ? Yb[int64_t(t) * M + m + 1] : make_float2(0.f, 0.f);
+        y[q] = make_float4(a.x, a.y, b.x, b.y);
+      }
+    }
+  };
+  auto store_block = [&](float* s, const float4 (&y)[kBlkWide]) {
+#pragma unroll
+    for (int q = 0; q < kBlkWide; ++q) {
+      const int v = threadIdx.x + q * 256;
+      *reinterpret_cast<float4*>(&s[(v >> 5) * kBlkLD + 4 * (v & 31)]) = y[q];
+    }
+  };
+  load_block(Ym, cm, 0, ym);
+  if constexpr (!SAME) load_block(Yn, cn, 0, yn);
+  const float* sB = SAME ? sM : sN;
+  for (int t0 = 0; t0 < T; t0 += kBlkChunk) {
+    store_block(sM, ym);
+    if constexpr (!SAME) store_block(sN, yn);
+    __syncthreads();
+    if (t0 + kBlkChunk < T) {
+      load_block(Ym, cm, t0 + kBlkChunk, ym);
+      if constexpr (!SAME) load_block(Yn, cn, t0 + kBlkChunk, yn);
+    }
+#pragma unroll 2
+    for (int s = 0; s < kBlkChunk / 4; ++s) {
+      const int row = (4 * s + fk) * kBlkLD + fi;
+      const float fa = sM[row + 16 * RA];
+      const float fb = TWO ? sM[row + 16 * RB] : 0.f;
+      float f[8];
+#pragma unroll
+      for (int c = CA < CB ? CA : CB; c < 8; ++c) f[c] = sB[row + 16 * c];
+#pragma unroll
+      for (int c = CA; c < 8; ++c) accA[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa, f[c], accA[c], 0, 0, 0);
+      if constexpr (TWO) {
+#pragma unroll
+        for (int c = CB; c < 8; ++c) accB[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(fb, f[c], accB[c], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  // D[i][j] of a tile sits in lane j + 16 (i / 4), register i % 4; the odd
+  // column 2n+1 is in the neighbouring lane
+  const float invT = 1.0f / float(T);
+  const bool even = (lane & 1) == 0;
+#pragma unroll
+  for (int h = 0; h < (TWO ? 2 : 1); ++h) {
+    const int r = h == 0 ? RA : RB;
+    const int c0 = h == 0 ? CA : CB;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      if (c < c0) continue;
+      const floatx4 a = h == 0 ? accA[c] : accB[c];
+      floatx4 x;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) x[e] = __shfl_xor(a[e], 1, 64);
+      if (!even) continue;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int ml = 8 * r + 2 * (lane >> 4) + q, nl = 8 * c + (fi >> 1);
+        const int m = m0 + ml, n = n0 + nl;
+        if (ml >= cm || nl >= cn || m > n) continue;
+        const float re = (a[2 * q] + x[2 * q + 1]) * invT;
+        const float im = m == n ? 0.f : (a[2 * q + 1] - x[2 * q]) * invT;
+        Rb[int64_t(m) * M + n] = make_float2(re, im);
+        if (m != n) Rb[int64_t(n) * M + m] = make_float2(re, -im);
+      }
+    }
+  }
+}
+
+// nbk = ceil(M / 64) element blocks, npair = nbk (nbk + 1) / 2 pairs per
+// trial, total = B npair logical workgroups. The launch is padded to a
+// multiple of 8; workgroup i runs on XCD i mod 8, so logical workgroup
+// (i mod 8) (n / 8) + i / 8 gives every XCD a contiguous run and a trial's
+// pairs read its snapshots through one L2.
+__global__ __launch_bounds__(256) void k_cov_blocks(const float2* __restrict__ Y, float2* __restrict__ R, int M,
+                                                    int T, int nbk, int npair, int64_t total) {
+  __shared__ __attribute__((aligned(16))) float sM[kBlkChunk * kBlkLD];
+  __shared__ __attribute__((aligned(16))) float sN[kBlkChunk * kBlkLD];
+  const int64_t nphys = int64_t(gridDim.x);
+  const int64_t l = int64_t(blockIdx.x % 8) * (nphys / 8) + blockIdx.x / 8;
+  if (l >= total) return;  // padding: the whole workgroup leaves before any barrier
+  const int64_t b = l / npair;
+  int rem = int(l - b * npair), mb = 0;
+  while (rem >= nbk - mb) {
+    rem -= nbk - mb;
+    ++mb;
+  }
+  const int nb = mb + rem;
+  const int m0 = kBlkE * mb, n0 = kBlkE * nb;
+  const int cm = min(kBlkE, M - m0), cn = min(kBlkE, M - n0);
+  const float2* Yb = Y + b * int64_t(T) * M;
+  float2* Rb = R + b * int64_t(M) * M;
+  const float2* Ym = Yb + m0;
+  const float2* Yn = Yb + n0;
+  // 16-byte loads when every block row starts on 16 bytes
+  const bool wide = (M & 1) == 0 && (reinterpret_cast<uintptr_t>(Yb) & 15) == 0;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+#define BA_COV_BLOCK_CASE(w)                                                                          \
+  case w:                                                                                             \
+    if (mb == nb)                                                                                     \
+      cov_block_wave<w, 7 - w, true>(Ym, Yn, Rb, M, T, cm, cn, m0, n0, wide, sM, sN, lane);           \
+    else                                                                                              \
+      cov_block_wave<2 * w, 2 * w + 1, false>(Ym, Yn, Rb, M, T, cm, cn, m0, n0, wide, sM, sN, lane);  \
+    break;
+  switch (wave) {
+    BA_COV_BLOCK_CASE(0)
+    BA_COV_BLOCK_CASE(1)
+    BA_COV_BLOCK_CASE(2)
+    default:
+      if (mb == nb)
+        cov_block_wave<3, 4, true>(Ym, Yn, Rb, M, T, cm, cn, m0, n0, wide, sM, sN, lane);
+      else
+        cov_block_wave<6, 7, false>(Ym, Yn, Rb, M, T, cm, cn, m0, n0, wide, sM, sN, lane);
+      break;
+  }
+#undef BA_COV_BLOCK_CASE
+}
+
 }  // namespace
 
 hipError_t launch_covariance(const Plan& p, int B, int T, const float2* Y, float2* R,
@@ -240,11 +337,12 @@ hipError_t launch_covariance(const Plan& p, int B, int T, const float2* Y, float
     }
     return hipGetLastError();
   }
-  const int ntile = (p.M + kTile - 1) / kTile;
-  const int npairs = ntile * (ntile + 1) / 2;
-  const int64_t nblk = int64_t(B) * npairs;
-  if (nblk > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_cov_tiles, dim3(unsigned(nblk)), dim3(256), 0, s, Y, R, p.M, T, ntile, npairs);
+  const int nbk = (p.M + kBlkE - 1) / kBlkE;
+  const int npair = nbk * (nbk + 1) / 2;
+  const int64_t total = int64_t(B) * npair;
+  const int64_t nphys = (total + 7) / 8 * 8;
+  if (nphys > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cov_blocks, dim3(unsigned(nphys)), dim3(256), 0, s, Y, R, p.M, T, nbk, npair, total);
   return hipGetLastError();
 }
 
