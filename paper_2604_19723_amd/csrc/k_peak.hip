@@ -9,9 +9,9 @@
 // and every comparison with NaN is false. Ties in value go to the lower index.
 //
 // One workgroup per trial. Each lane scans a strided slice of the grid
-// (coalesced; a 1-D row is staged in LDS first) and keeps a sorted top-KC list
-// in registers; the lists meet in LDS and K rounds of a wave-shuffle argmax
-// pick the winners in order.
+// (coalesced; a 1-D row is staged in LDS first, other grids in bands of rows)
+// and keeps a sorted top-KC list in registers; the lists meet in LDS and K
+// rounds of a wave-shuffle argmax pick the winners in order.
 #include <climits>
 
 #include <algorithm>
@@ -74,11 +74,48 @@ __device__ __forceinline__ void insert(float (&lv)[KC], int (&li)[KC], float v, 
 
 __device__ double parabolic(double pm, double p0, double pp) { return peak_parabolic(pm, p0, pp); }
 
-// ONED: a 1-D grid (s1 == 1) whose candidate row fits in LDS is staged there
-// with coalesced loads first, and each point meets its two neighbours in LDS
-// (same rule as is_local_max: the earlier neighbour strictly, the later one
-// with >=, wrap of the row when wrap0, every comparison with NaN false).
-template <int KC, bool ONED>
+// Where the candidates meet their neighbours:
+//  kPeakGlobal: in global memory (is_local_max), for rows too wide for LDS;
+//  kPeakOneD:   a 1-D grid (s1 == 1) whose candidate row fits in LDS is staged
+//               there with coalesced loads first, and each point meets its two
+//               neighbours in LDS (the earlier neighbour strictly, the later
+//               one with >=, wrap of the row when wrap0, every comparison
+//               with NaN false);
+//  kPeakBand:   any other grid is walked in bands of whole dim-0 rows, each
+//               staged in LDS with the row before and the row after it
+//               (wrapped when wrap0), and tested by the same rule as
+//               is_local_max against the staged rows.
+// Every lane keeps its own sorted top-KC list, so the result does not
+// depend on which lane meets which point.
+constexpr int kPeakGlobal = 0, kPeakOneD = 1, kPeakBand = 2;
+
+// rows of a band of a grid with s1 points per dim-0 row (0: too wide)
+__host__ __device__ __forceinline__ int peak_band_rows(int s1) { return kPeakRowMax / s1 - 2; }
+
+// is_local_max against staged rows: sR + L s1 is the point's own row, the
+// rows before and after it sit at L - 1 and L + 1
+__device__ __forceinline__ bool is_local_max_band(const float* sR, int L, int i0, int i1, float p, int s1,
+                                                  int rows, int wrap0) {
+  if (p != p) return false;
+  bool ok = true;
+#pragma unroll
+  for (int di = -1; di <= 1; ++di) {
+    if (!wrap0 && (i0 + di < 0 || i0 + di >= rows)) continue;
+    const float* q = sR + (L + di) * s1;
+#pragma unroll
+    for (int dj = -1; dj <= 1; ++dj) {
+      if (di == 0 && dj == 0) continue;
+      if (s1 == 1 && dj != 0) continue;
+      const int j1 = i1 + dj;
+      if (j1 < 0 || j1 >= s1) continue;
+      const bool earlier = di < 0 || (di == 0 && dj < 0);
+      ok = ok && (earlier ? (p > q[j1]) : (p >= q[j1]));
+    }
+  }
+  return ok;
+}
+
+template <int KC, int MODE>
 __device__ __forceinline__ void peaks_trial(int64_t b, const float* __restrict__ P, int64_t G, int s1,
                                             int rows, int wrap0, int k, int* __restrict__ idx,
                                             float* __restrict__ val,
@@ -94,7 +131,7 @@ __device__ __forceinline__ void peaks_trial(int64_t b, const float* __restrict__
     li[j] = INT_MAX;
   }
   const int64_t ncand = int64_t(rows) * s1;
-  if (ONED) {
+  if constexpr (MODE == kPeakOneD) {
     extern __shared__ float sRow[];  // [rows]
     // eight loads in flight per lane before their values are stored
     for (int g0 = 0; g0 < rows; g0 += 8 * 256) {
@@ -118,6 +155,39 @@ __device__ __forceinline__ void peaks_trial(int64_t b, const float* __restrict__
       if (wrap0 || gm >= 0) ok = ok && p > sRow[gm < 0 ? gm + rows : gm];
       if (wrap0 || gp < rows) ok = ok && p >= sRow[gp >= rows ? gp - rows : gp];
       if (ok) insert<KC>(lv, li, p, g);
+    }
+  } else if constexpr (MODE == kPeakBand) {
+    extern __shared__ float sRow[];  // [(H + 2) s1], H = peak_band_rows(s1) >= 1
+    const int H = peak_band_rows(s1);
+    for (int r0 = 0; r0 < rows; r0 += H) {
+      const int hb = min(H, rows - r0);
+      // staged row lr is grid row r0 - 1 + lr (wrapped when wrap0; left
+      // unset where it does not exist, and then never read)
+      const int nl = (hb + 2) * s1;
+      for (int e0 = 0; e0 < nl; e0 += 8 * 256) {
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int e = e0 + j * 256 + tid;
+          const int lr = e / s1, i1 = e - lr * s1;
+          int j0 = r0 - 1 + lr;
+          if (wrap0) j0 = wrap_row(j0, rows);
+          v[j] = (e < nl && j0 >= 0 && j0 < rows) ? Pb[int64_t(j0) * s1 + i1] : 0.f;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int e = e0 + j * 256 + tid;
+          if (e < nl) sRow[e] = v[j];
+        }
+      }
+      __syncthreads();
+      for (int e = tid; e < hb * s1; e += 256) {
+        const int lr = e / s1, i1 = e - lr * s1;
+        const int i0 = r0 + lr;
+        const float p = sRow[(lr + 1) * s1 + i1];
+        if (is_local_max_band(sRow, lr + 1, i0, i1, p, s1, rows, wrap0)) insert<KC>(lv, li, p, i0 * s1 + i1);
+      }
+      __syncthreads();  // the next band reuses the staging
     }
   } else {
     for (int64_t g = tid; g < ncand; g += 256) {
@@ -207,23 +277,23 @@ __device__ __forceinline__ void peaks_trial(int64_t b, const float* __restrict__
   }
 }
 
-template <int KC, bool ONED>
+template <int KC, int MODE>
 __global__ __launch_bounds__(256) void k_peaks(const float* __restrict__ P, int64_t G, int s1, int rows,
                                                int wrap0, int k, int* __restrict__ idx, float* __restrict__ val,
                                                double* __restrict__ refined, int ndim) {
-  peaks_trial<KC, ONED>(blockIdx.x, P, G, s1, rows, wrap0, k, idx, val, refined, ndim);
+  peaks_trial<KC, MODE>(blockIdx.x, P, G, s1, rows, wrap0, k, idx, val, refined, ndim);
 }
 
 // The same over a batch whose size is only known on the device (*count
 // trials): workgroups step through the trials with the grid's stride.
-template <int KC, bool ONED>
+template <int KC, int MODE>
 __global__ __launch_bounds__(256) void k_peaks_counted(const float* __restrict__ P, int64_t G, int s1, int rows,
                                                        int wrap0, int k, int* __restrict__ idx,
                                                        float* __restrict__ val, double* __restrict__ refined,
                                                        int ndim, const int* __restrict__ count) {
   const int64_t n = *count;
   for (int64_t b = blockIdx.x; b < n; b += gridDim.x) {
-    peaks_trial<KC, ONED>(b, P, G, s1, rows, wrap0, k, idx, val, refined, ndim);
+    peaks_trial<KC, MODE>(b, P, G, s1, rows, wrap0, k, idx, val, refined, ndim);
     __syncthreads();  // the next trial reuses the shared staging
   }
 }
@@ -438,21 +508,27 @@ hipError_t launch_peaks(const Plan& p, int B, const float* P, int k, int* idx, f
                         double* refined, hipStream_t s, const int* count) {
   // counted: at most 2048 workgroups step through the device-side count
   const dim3 grid{static_cast<uint32_t>(count ? std::min(B, 2048) : B)}, block{256u};
-  // a 1-D candidate row of up to kPeakRowMax points is staged in LDS
+  // a 1-D candidate row of up to kPeakRowMax points is staged in LDS whole;
+  // other grids in bands of dim-0 rows when a band of one row fits
   const bool oned = p.shape1 == 1 && p.rows <= kPeakRowMax;
-  const size_t lds = oned ? size_t(p.rows) * sizeof(float) : 0;
-#define BA_PK1(KCV, OD)                                                                                     \
+  const int H = peak_band_rows(p.shape1);
+  const bool band = !oned && H >= 1;
+  const size_t lds = oned ? size_t(p.rows) * sizeof(float)
+                          : (band ? size_t(H + 2) * p.shape1 * sizeof(float) : 0);
+#define BA_PK1(KCV, MD)                                                                                     \
   if (count)                                                                                                 \
-    hipLaunchKernelGGL((k_peaks_counted<KCV, OD>), grid, block, OD ? lds : 0, s, P, p.G, p.shape1, p.rows,   \
-                       p.wrap0, k, idx, val, refined, p.ndim, count);                                        \
+    hipLaunchKernelGGL((k_peaks_counted<KCV, MD>), grid, block, lds, s, P, p.G, p.shape1, p.rows, p.wrap0,   \
+                       k, idx, val, refined, p.ndim, count);                                                 \
   else                                                                                                       \
-    hipLaunchKernelGGL((k_peaks<KCV, OD>), grid, block, OD ? lds : 0, s, P, p.G, p.shape1, p.rows, p.wrap0, k, \
-                       idx, val, refined, p.ndim)
-#define BA_PK(KCV)       \
-  if (oned) {            \
-    BA_PK1(KCV, true);   \
-  } else {               \
-    BA_PK1(KCV, false);  \
+    hipLaunchKernelGGL((k_peaks<KCV, MD>), grid, block, lds, s, P, p.G, p.shape1, p.rows, p.wrap0, k, idx,   \
+                       val, refined, p.ndim)
+#define BA_PK(KCV)                \
+  if (oned) {                     \
+    BA_PK1(KCV, kPeakOneD);       \
+  } else if (band) {              \
+    BA_PK1(KCV, kPeakBand);       \
+  } else {                        \
+    BA_PK1(KCV, kPeakGlobal);     \
   }
   if (k <= 1)
     BA_PK(1)
