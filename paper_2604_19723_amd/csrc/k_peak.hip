@@ -310,6 +310,12 @@ __device__ __forceinline__ double block_sum(double x, double* red) {
 
 // Proposal moments: w = P / sum P over the distinct points, mu at the first
 // global maximum, C = sum w (x - mu)(x - mu)^T with azimuth wrap.
+// STAGED: the trial's ncand <= kPeakRowMax values are first copied into LDS
+// with 16-byte loads (the row's unaligned head and tail one value at a
+// time, so nothing outside the row is read), and both passes read them
+// there. Each lane takes the points tid, tid + 256, ... in that order either
+// way, so the sums are the same bit for bit.
+template <bool STAGED>
 __global__ __launch_bounds__(256) void k_moments(const float* __restrict__ P, int64_t G,
                                                  int64_t ncand, const double* __restrict__ X,
                                                  int d, int azwrap, double* __restrict__ out) {
@@ -319,12 +325,44 @@ __global__ __launch_bounds__(256) void k_moments(const float* __restrict__ P, in
   __shared__ double red[4];
   __shared__ float wv[4];
   __shared__ int wi[4];
+  extern __shared__ float sP[];  // [ncand] when STAGED
+  if constexpr (STAGED) {
+    const int n = int(ncand);
+    const int off = int((reinterpret_cast<uintptr_t>(Pb) >> 2) & 3);  // floats past a 16-byte boundary
+    const int h = min(n, (4 - off) & 3);
+    const int nv = (n - h) >> 2;
+    const float4* P4 = reinterpret_cast<const float4*>(Pb + h);
+    for (int i0 = 0; i0 < nv; i0 += 8 * 256) {
+      float4 v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int i = i0 + j * 256 + tid;
+        v[j] = i < nv ? P4[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int i = i0 + j * 256 + tid;
+        if (i < nv) {
+          float* q = sP + h + 4 * i;
+          q[0] = v[j].x;
+          q[1] = v[j].y;
+          q[2] = v[j].z;
+          q[3] = v[j].w;
+        }
+      }
+    }
+    const int t0 = h + 4 * nv;
+    if (tid < h) sP[tid] = Pb[tid];
+    if (tid < n - t0) sP[t0 + tid] = Pb[t0 + tid];
+    __syncthreads();
+  }
+  auto value = [&](int64_t g) { return STAGED ? sP[g] : Pb[g]; };
 
   double s = 0.0;
   float bv = -INFINITY;
   int bi = INT_MAX;
   for (int64_t g = tid; g < ncand; g += 256) {
-    const float p = Pb[g];
+    const float p = value(g);
     s += double(p);
     if (better(p, int(g), bv, bi)) {
       bv = p;
@@ -359,18 +397,39 @@ __global__ __launch_bounds__(256) void k_moments(const float* __restrict__ P, in
   for (int a = 0; a < d; ++a) mu[a] = gs != INT_MAX ? X[int64_t(gs) * d + a] : nan;
 
   double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int64_t g = tid; g < ncand; g += 256) {
-    const double p = double(Pb[g]);
-    double D[3] = {0.0, 0.0, 0.0};
-    for (int a = 0; a < d; ++a) D[a] = X[g * d + a] - mu[a];
-    if (azwrap) {
-      double r = fmod(D[0] + 180.0, 360.0);
-      if (r < 0.0) r += 360.0;
-      D[0] = r - 180.0;
+  if (d == 1 && !azwrap) {
+    // 1-D grids: eight coordinates in flight per lane, same order and arithmetic
+    for (int64_t g0 = 0; g0 < ncand; g0 += 8 * 256) {
+      double x[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int64_t g = g0 + j * 256 + tid;
+        x[j] = g < ncand ? X[g] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int64_t g = g0 + j * 256 + tid;
+        if (g < ncand) {
+          const double p = double(value(g));
+          const double D0 = x[j] - mu[0];
+          acc[0] += p * D0 * D0;
+        }
+      }
     }
-    int c = 0;
-    for (int i = 0; i < d; ++i)
-      for (int j = i; j < d; ++j) acc[c++] += p * D[i] * D[j];
+  } else {
+    for (int64_t g = tid; g < ncand; g += 256) {
+      const double p = double(value(g));
+      double D[3] = {0.0, 0.0, 0.0};
+      for (int a = 0; a < d; ++a) D[a] = X[g * d + a] - mu[a];
+      if (azwrap) {
+        double r = fmod(D[0] + 180.0, 360.0);
+        if (r < 0.0) r += 360.0;
+        D[0] = r - 180.0;
+      }
+      int c = 0;
+      for (int i = 0; i < d; ++i)
+        for (int j = i; j < d; ++j) acc[c++] += p * D[i] * D[j];
+    }
   }
   double C[6];
   const int nc = d * (d + 1) / 2;
@@ -693,8 +752,13 @@ hipError_t launch_point_moments(int B, const float* P, int64_t G, const double* 
 
 hipError_t launch_moments(const Plan& p, int B, const float* P, double* mu_cov, hipStream_t s) {
   const int64_t ncand = int64_t(p.rows) * p.shape1;
-  hipLaunchKernelGGL(k_moments, dim3(unsigned(B)), dim3(256), 0, s, P, p.G, ncand, p.d_coords,
-                     p.coord_dim, p.kind == BA_GRID_AZEL_DEG ? 1 : 0, mu_cov);
+  const int azwrap = p.kind == BA_GRID_AZEL_DEG ? 1 : 0;
+  if (ncand <= kPeakRowMax)
+    hipLaunchKernelGGL(k_moments<true>, dim3(unsigned(B)), dim3(256), size_t(ncand) * sizeof(float), s, P, p.G,
+                       ncand, p.d_coords, p.coord_dim, azwrap, mu_cov);
+  else
+    hipLaunchKernelGGL(k_moments<false>, dim3(unsigned(B)), dim3(256), 0, s, P, p.G, ncand, p.d_coords,
+                       p.coord_dim, azwrap, mu_cov);
   return hipGetLastError();
 }
 
