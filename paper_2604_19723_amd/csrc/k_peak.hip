@@ -625,11 +625,21 @@ __global__ __launch_bounds__(256) void k_point_max(const float* __restrict__ P, 
   float bv = -INFINITY;
   int bi = INT_MAX;
   const int64_t g1 = min(G, int64_t(sl + 1) * kPtSlice);
-  for (int64_t g = int64_t(sl) * kPtSlice + tid; g < g1; g += 256) {
-    const float pf = Pb[g];
-    if (better(pf, int(g), bv, bi)) {
-      bv = pf;
-      bi = int(g);
+  // each lane takes its points in index order, eight loads in flight
+  for (int64_t g0 = int64_t(sl) * kPtSlice; g0 < g1; g0 += 8 * 256) {
+    float v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int64_t g = g0 + j * 256 + tid;
+      v[j] = g < g1 ? Pb[g] : 0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int64_t g = g0 + j * 256 + tid;
+      if (g < g1 && better(v[j], int(g), bv, bi)) {
+        bv = v[j];
+        bi = int(g);
+      }
     }
   }
 #pragma unroll
@@ -692,16 +702,31 @@ __global__ __launch_bounds__(256) void k_point_partial(const float* __restrict__
   const double mu0 = X[3 * int64_t(bi)], mu1 = X[3 * int64_t(bi) + 1], mu2 = X[3 * int64_t(bi) + 2];
   double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   const int64_t g1 = min(G, int64_t(sl + 1) * kPtSlice);
-  for (int64_t g = int64_t(sl) * kPtSlice + tid; g < g1; g += 256) {
-    const double p = double(Pb[g]);
-    const double y0 = X[3 * g] - mu0, y1 = X[3 * g + 1] - mu1, y2 = X[3 * g + 2] - mu2;
-    acc[0] += p;
-    acc[1] += p * y0 * y0;
-    acc[2] += p * y0 * y1;
-    acc[3] += p * y0 * y2;
-    acc[4] += p * y1 * y1;
-    acc[5] += p * y1 * y2;
-    acc[6] += p * y2 * y2;
+  // each lane takes its points in index order, four points in flight
+  for (int64_t g0 = int64_t(sl) * kPtSlice; g0 < g1; g0 += 4 * 256) {
+    float v[4];
+    double x[4][3];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t g = g0 + j * 256 + tid;
+      const bool in = g < g1;
+      v[j] = in ? Pb[g] : 0.f;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) x[j][a] = in ? X[3 * g + a] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (g0 + j * 256 + tid >= g1) continue;
+      const double p = double(v[j]);
+      const double y0 = x[j][0] - mu0, y1 = x[j][1] - mu1, y2 = x[j][2] - mu2;
+      acc[0] += p;
+      acc[1] += p * y0 * y0;
+      acc[2] += p * y0 * y1;
+      acc[3] += p * y0 * y2;
+      acc[4] += p * y1 * y1;
+      acc[5] += p * y1 * y2;
+      acc[6] += p * y2 * y2;
+    }
   }
   for (int c = 0; c < kPtParts; ++c) {
     const double v = block_sum(acc[c], red);
