@@ -61,39 +61,44 @@ __device__ __forceinline__ float lval(const float2* __restrict__ Rb, int M, int 
 //   lane l, word h, element e holds L[16 rbg + l%16][32 kc + 4 (4h + e) + l/16].
 // BF16 layout: Lb[b][kc][rbg][hl][lane][8]: lane l, element e holds
 //   (hi or lo of) L[16 rbg + l%16][32 kc + 8 (l/16) + e].
-// Chunks right of a row block's diagonal hold zeros; neither loaded nor multiplied.
+// Chunks right of a row block's diagonal (kc > rbg / 2) would hold zeros; they
+// are neither loaded nor multiplied, so they are not written either.
 template <int PREC>
 __global__ __launch_bounds__(256) void k_qprep(const float2* __restrict__ R, void* __restrict__ Qout,
                                                int M, int MP) {
-  const int K = 2 * MP, nkc = K / 32, nrb = K / 16;
+  // one workgroup per (row block, trial), walking the row block's k-chunks
+  // up to its diagonal chunk
+  const int K = 2 * MP, nrb = K / 16;
   const int64_t b = blockIdx.y;
-  const int kc = blockIdx.x / nrb, rbg = blockIdx.x % nrb;
+  const int rbg = blockIdx.x;
   const float2* Rb = R + b * int64_t(M) * M;
   const int64_t per_trial = int64_t(K) * K;
   const int t = threadIdx.x;  // 256 threads
-  if (PREC == BA_PREC_F32) {
-    // 16 rows x 32 k = 512 values, 2 per thread
-    float* Q = static_cast<float*>(Qout) + b * per_trial + (int64_t(kc) * nrb + rbg) * 512;
-    for (int v = t; v < 512; v += 256) {
-      const int h = v >> 8, l = (v >> 2) & 63, e = v & 3;
-      const int i = 16 * rbg + (l & 15);
-      const int k = 32 * kc + 4 * (4 * h + e) + (l >> 4);
-      Q[v] = lval(Rb, M, MP, i, k);
-    }
-  } else {
-    unsigned short* Q = static_cast<unsigned short*>(Qout) + 2 * (b * per_trial + (int64_t(kc) * nrb + rbg) * 512);
-    for (int v = t; v < 512; v += 256) {
-      const int l = v >> 3, e = v & 7;
-      const int i = 16 * rbg + (l & 15);
-      const int k = 32 * kc + 8 * (l >> 4) + e;
-      const float q = lval(Rb, M, MP, i, k);
-      const unsigned short hi = bf16_rne(q);
-      const unsigned short lo = bf16_rne(q - bf16_to_f(hi));
-      Q[v] = hi;
-      Q[512 + v] = lo;
+  for (int kc = 0; kc <= (rbg >> 1); ++kc) {
+    if (PREC == BA_PREC_F32) {
+      // 16 rows x 32 k = 512 values, 2 per thread
+      float* Q = static_cast<float*>(Qout) + b * per_trial + (int64_t(kc) * nrb + rbg) * 512;
+      for (int v = t; v < 512; v += 256) {
+        const int h = v >> 8, l = (v >> 2) & 63, e = v & 3;
+        const int i = 16 * rbg + (l & 15);
+        const int k = 32 * kc + 4 * (4 * h + e) + (l >> 4);
+        Q[v] = lval(Rb, M, MP, i, k);
+      }
+    } else {
+      unsigned short* Q =
+          static_cast<unsigned short*>(Qout) + 2 * (b * per_trial + (int64_t(kc) * nrb + rbg) * 512);
+      for (int v = t; v < 512; v += 256) {
+        const int l = v >> 3, e = v & 7;
+        const int i = 16 * rbg + (l & 15);
+        const int k = 32 * kc + 8 * (l >> 4) + e;
+        const float q = lval(Rb, M, MP, i, k);
+        const unsigned short hi = bf16_rne(q);
+        const unsigned short lo = bf16_rne(q - bf16_to_f(hi));
+        Q[v] = hi;
+        Q[512 + v] = lo;
+      }
     }
   }
-  (void)nkc;
 }
 
 // One k-chunk of the FP32 kernel for the last N row-block slots of a wave
@@ -408,7 +413,7 @@ size_t qprep_bytes(const Plan& p, int B) {
 hipError_t launch_spectrum_stream(const Plan& p, int B, const float2* R, void* Qws, float* P,
                                   hipStream_t s) {
   const int K = 2 * p.Mp;
-  const dim3 g1(unsigned((K / 32) * (K / 16)), unsigned(B));
+  const dim3 g1(unsigned(K / 16), unsigned(B));
   const bool f32 = p.precision == BA_PREC_F32;
   if (f32)
     hipLaunchKernelGGL(k_qprep<BA_PREC_F32>, g1, dim3(256), 0, s, R, Qws, p.M, p.Mp);
