@@ -89,6 +89,9 @@ __device__ double parabolic(double pm, double p0, double pp) { return peak_parab
 // depend on which lane meets which point.
 constexpr int kPeakGlobal = 0, kPeakOneD = 1, kPeakBand = 2;
 
+// columns one lane tests per step in a band
+constexpr int kPeakRun = 8;
+
 // rows of a band of a grid with s1 points per dim-0 row (0: too wide)
 __host__ __device__ __forceinline__ int peak_band_rows(int s1) { return kPeakRowMax / s1 - 2; }
 
@@ -164,28 +167,76 @@ __device__ __forceinline__ void peaks_trial(int64_t b, const float* __restrict__
       // staged row lr is grid row r0 - 1 + lr (wrapped when wrap0; left
       // unset where it does not exist, and then never read)
       const int nl = (hb + 2) * s1;
+      // (staged row, column) of this lane's element, advanced by 256 per step
+      const int adv_r = 256 / s1, adv_c = 256 - adv_r * s1;
+      int lr = tid / s1, i1 = tid - (tid / s1) * s1;
       for (int e0 = 0; e0 < nl; e0 += 8 * 256) {
         float v[8];
+        int lrj = lr, i1j = i1;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           const int e = e0 + j * 256 + tid;
-          const int lr = e / s1, i1 = e - lr * s1;
-          int j0 = r0 - 1 + lr;
+          int j0 = r0 - 1 + lrj;
           if (wrap0) j0 = wrap_row(j0, rows);
-          v[j] = (e < nl && j0 >= 0 && j0 < rows) ? Pb[int64_t(j0) * s1 + i1] : 0.f;
+          v[j] = (e < nl && j0 >= 0 && j0 < rows) ? Pb[int64_t(j0) * s1 + i1j] : 0.f;
+          lrj += adv_r;
+          i1j += adv_c;
+          if (i1j >= s1) {
+            i1j -= s1;
+            ++lrj;
+          }
         }
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           const int e = e0 + j * 256 + tid;
           if (e < nl) sRow[e] = v[j];
         }
+        lr = lrj;
+        i1 = i1j;
       }
       __syncthreads();
-      for (int e = tid; e < hb * s1; e += 256) {
-        const int lr = e / s1, i1 = e - lr * s1;
-        const int i0 = r0 + lr;
-        const float p = sRow[(lr + 1) * s1 + i1];
-        if (is_local_max_band(sRow, lr + 1, i0, i1, p, s1, rows, wrap0)) insert<KC>(lv, li, p, i0 * s1 + i1);
+      // each lane tests a run of kPeakRun columns of one row against the
+      // three staged rows held in registers
+      const int nrun = (s1 + kPeakRun - 1) / kPeakRun;
+      for (int w = tid; w < hb * nrun; w += 256) {
+        const int rl = w / nrun, c0 = (w - rl * nrun) * kPeakRun;
+        const int i0 = r0 + rl;
+        const bool has_up = wrap0 || i0 > 0, has_dn = wrap0 || i0 + 1 < rows;
+        const float* up = sRow + rl * s1;
+        const float* me = up + s1;
+        const float* dn = me + s1;
+        float u[kPeakRun + 2], m[kPeakRun + 2], d[kPeakRun + 2];
+#pragma unroll
+        for (int j = 0; j < kPeakRun + 2; ++j) {
+          const int c = c0 - 1 + j;
+          const bool in = c >= 0 && c < s1;
+          m[j] = in ? me[c] : 0.f;
+          u[j] = in && has_up ? up[c] : 0.f;
+          d[j] = in && has_dn ? dn[c] : 0.f;
+        }
+#pragma unroll
+        for (int j = 1; j <= kPeakRun; ++j) {
+          const int c = c0 + j - 1;
+          if (c >= s1) break;
+          const float p = m[j];
+          // the earlier neighbours strictly below, the later ones at most
+          // equal, missing ones not compared, NaN never a maximum
+          const bool l_ok = c > 0, r_ok = c + 1 < s1;
+          bool ok = p == p;
+          if (has_up) {
+            ok = ok && p > u[j];
+            if (l_ok) ok = ok && p > u[j - 1];
+            if (r_ok) ok = ok && p > u[j + 1];
+          }
+          if (l_ok) ok = ok && p > m[j - 1];
+          if (r_ok) ok = ok && p >= m[j + 1];
+          if (has_dn) {
+            ok = ok && p >= d[j];
+            if (l_ok) ok = ok && p >= d[j - 1];
+            if (r_ok) ok = ok && p >= d[j + 1];
+          }
+          if (ok) insert<KC>(lv, li, p, i0 * s1 + c);
+        }
       }
       __syncthreads();  // the next band reuses the staging
     }
