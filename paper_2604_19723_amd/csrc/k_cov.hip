@@ -160,25 +160,31 @@ __global__ __launch_bounds__(256) void k_cov_mfma(const float2* __restrict__ Y, 
 // share of the real Gram, G over the float rows of block mb and the float
 // columns of block nb, is a 128 x 128 array of 8 x 8 tiles of 16. On a
 // diagonal pair only the tiles on or above the diagonal are formed, split
-// over the waves by tile-row pairs (w, 7 - w) as above; off the diagonal
-// wave w takes tile rows 2w and 2w + 1 across all eight tile columns. Chunks
-// of 32 snapshots of both blocks are staged row-major in LDS, the next one
-// held in registers while the current one is multiplied.
+// over waves 0-3 by tile-row pairs (w, 7 - w) as above; off the diagonal
+// each of the eight waves takes one tile row across all eight tile columns.
+// Chunks of 32 snapshots of both blocks are staged row-major in LDS by all
+// eight waves, the next one held in registers while the current one is
+// multiplied.
 constexpr int kBlkE = 64;              // elements per block
 constexpr int kBlkW = 2 * kBlkE;       // floats per block row
 constexpr int kBlkLD = kBlkW + 16;     // LDS row stride (as kGramChunk's)
 constexpr int kBlkChunk = 32;          // snapshots per stage
-constexpr int kBlkWide = kBlkChunk * kBlkE / 2 / 256;  // float4 per thread per block (4)
+constexpr int kBlkWaves = 8;           // waves per workgroup
+constexpr int kBlkThreads = 64 * kBlkWaves;
+constexpr int kBlkWide = kBlkChunk * kBlkE / 2 / kBlkThreads;  // float4 per thread per block
+static_assert(kBlkWide >= 1 && kBlkChunk * kBlkE / 2 % kBlkThreads == 0, "staging split");
 
-// Tile rows RA and RB (RB == RA: one row); columns from RA (resp. RB) on when
-// UPPER, else all eight. Ym, Yn: the snapshots' first element of each block
-// (row stride M); cm, cn: elements in each block; Rb: the trial's R.
+// Tile rows RA and RB (RB == RA: one row; RA < 0: no tiles, the wave only
+// stages snapshots and keeps the barriers); columns from RA (resp. RB) on
+// when UPPER, else all eight. Ym, Yn: the snapshots' first element of each
+// block (row stride M); cm, cn: elements in each block; Rb: the trial's R.
 template <int RA, int RB, bool UPPER>
 __device__ __forceinline__ void cov_block_wave(const float2* __restrict__ Ym, const float2* __restrict__ Yn,
                                                float2* __restrict__ Rb, int M, int T, int cm, int cn, int m0,
                                                int n0, bool wide, float* sM, float* sN, int lane) {
-  constexpr bool TWO = RB != RA;
-  constexpr int CA = UPPER ? RA : 0, CB = UPPER ? RB : 0;
+  constexpr bool ACT = RA >= 0;
+  constexpr bool TWO = ACT && RB != RA;
+  constexpr int CA = !ACT ? 0 : (UPPER ? RA : 0), CB = !ACT ? 0 : (UPPER ? RB : 0);
   constexpr bool SAME = UPPER;  // a diagonal pair stages one block
   floatx4 accA[8], accB[8];
 #pragma unroll
@@ -192,7 +198,7 @@ __device__ __forceinline__ void cov_block_wave(const float2* __restrict__ Ym, co
   auto load_block = [&](const float2* __restrict__ Yb, int cnt, int t0, float4 (&y)[kBlkWide]) {
 #pragma unroll
     for (int q = 0; q < kBlkWide; ++q) {
-      const int v = threadIdx.x + q * 256;
+      const int v = threadIdx.x + q * kBlkThreads;
       const int tt = v >> 5, m = 2 * (v & 31);
       const int t = t0 + tt;
       if (wide) {
@@ -208,7 +214,7 @@ __device__ __forceinline__ void cov_block_wave(const float2* __restrict__ Ym, co
   auto store_block = [&](float* s, const float4 (&y)[kBlkWide]) {
 #pragma unroll
     for (int q = 0; q < kBlkWide; ++q) {
-      const int v = threadIdx.x + q * 256;
+      const int v = threadIdx.x + q * kBlkThreads;
       *reinterpret_cast<float4*>(&s[(v >> 5) * kBlkLD + 4 * (v & 31)]) = y[q];
     }
   };
@@ -223,6 +229,7 @@ __device__ __forceinline__ void cov_block_wave(const float2* __restrict__ Ym, co
       load_block(Ym, cm, t0 + kBlkChunk, ym);
       if constexpr (!SAME) load_block(Yn, cn, t0 + kBlkChunk, yn);
     }
+    if constexpr (ACT) {
 #pragma unroll 2
     for (int s = 0; s < kBlkChunk / 4; ++s) {
       const int row = (4 * s + fk) * kBlkLD + fi;
@@ -238,8 +245,10 @@ __device__ __forceinline__ void cov_block_wave(const float2* __restrict__ Ym, co
         for (int c = CB; c < 8; ++c) accB[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(fb, f[c], accB[c], 0, 0, 0);
       }
     }
+    }
     __syncthreads();
   }
+  if constexpr (!ACT) return;
   // D[i][j] of a tile sits in lane j + 16 (i / 4), register i % 4; the odd
   // column 2n+1 is in the neighbouring lane
   const float invT = 1.0f / float(T);
@@ -275,8 +284,8 @@ __device__ __forceinline__ void cov_block_wave(const float2* __restrict__ Ym, co
 // multiple of 8; workgroup i runs on XCD i mod 8, so logical workgroup
 // (i mod 8) (n / 8) + i / 8 gives every XCD a contiguous run and a trial's
 // pairs read its snapshots through one L2.
-__global__ __launch_bounds__(256) void k_cov_blocks(const float2* __restrict__ Y, float2* __restrict__ R, int M,
-                                                    int T, int nbk, int npair, int64_t total) {
+__global__ __launch_bounds__(kBlkThreads) void k_cov_blocks(const float2* __restrict__ Y, float2* __restrict__ R,
+                                                            int M, int T, int nbk, int npair, int64_t total) {
   __shared__ __attribute__((aligned(16))) float sM[kBlkChunk * kBlkLD];
   __shared__ __attribute__((aligned(16))) float sN[kBlkChunk * kBlkLD];
   const int64_t nphys = int64_t(gridDim.x);
@@ -298,22 +307,28 @@ __global__ __launch_bounds__(256) void k_cov_blocks(const float2* __restrict__ Y
   // 16-byte loads when every block row starts on 16 bytes
   const bool wide = (M & 1) == 0 && (reinterpret_cast<uintptr_t>(Yb) & 15) == 0;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-#define BA_COV_BLOCK_CASE(w)                                                                          \
-  case w:                                                                                             \
-    if (mb == nb)                                                                                     \
-      cov_block_wave<w, 7 - w, true>(Ym, Yn, Rb, M, T, cm, cn, m0, n0, wide, sM, sN, lane);           \
-    else                                                                                              \
-      cov_block_wave<2 * w, 2 * w + 1, false>(Ym, Yn, Rb, M, T, cm, cn, m0, n0, wide, sM, sN, lane);  \
+  // off the diagonal wave w forms tile row w across all eight tile columns;
+  // on it waves 0-3 form the tile-row pairs (w, 7 - w) and waves 4-7 only stage
+#define BA_COV_BLOCK_CASE(w, RA, RB)                                                       \
+  case w:                                                                                  \
+    if (mb == nb)                                                                          \
+      cov_block_wave<RA, RB, true>(Ym, Yn, Rb, M, T, cm, cn, m0, n0, wide, sM, sN, lane);  \
+    else                                                                                   \
+      cov_block_wave<w, w, false>(Ym, Yn, Rb, M, T, cm, cn, m0, n0, wide, sM, sN, lane);   \
     break;
   switch (wave) {
-    BA_COV_BLOCK_CASE(0)
-    BA_COV_BLOCK_CASE(1)
-    BA_COV_BLOCK_CASE(2)
+    BA_COV_BLOCK_CASE(0, 0, 7)
+    BA_COV_BLOCK_CASE(1, 1, 6)
+    BA_COV_BLOCK_CASE(2, 2, 5)
+    BA_COV_BLOCK_CASE(3, 3, 4)
+    BA_COV_BLOCK_CASE(4, -1, -1)
+    BA_COV_BLOCK_CASE(5, -1, -1)
+    BA_COV_BLOCK_CASE(6, -1, -1)
     default:
       if (mb == nb)
-        cov_block_wave<3, 4, true>(Ym, Yn, Rb, M, T, cm, cn, m0, n0, wide, sM, sN, lane);
+        cov_block_wave<-1, -1, true>(Ym, Yn, Rb, M, T, cm, cn, m0, n0, wide, sM, sN, lane);
       else
-        cov_block_wave<6, 7, false>(Ym, Yn, Rb, M, T, cm, cn, m0, n0, wide, sM, sN, lane);
+        cov_block_wave<7, 7, false>(Ym, Yn, Rb, M, T, cm, cn, m0, n0, wide, sM, sN, lane);
       break;
   }
 #undef BA_COV_BLOCK_CASE
@@ -342,7 +357,7 @@ hipError_t launch_covariance(const Plan& p, int B, int T, const float2* Y, float
   const int64_t total = int64_t(B) * npair;
   const int64_t nphys = (total + 7) / 8 * 8;
   if (nphys > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_cov_blocks, dim3(unsigned(nphys)), dim3(256), 0, s, Y, R, p.M, T, nbk, npair, total);
+  hipLaunchKernelGGL(k_cov_blocks, dim3(unsigned(nphys)), dim3(kBlkThreads), 0, s, Y, R, p.M, T, nbk, npair, total);
   return hipGetLastError();
 }
 
